@@ -1,0 +1,667 @@
+/*
+ * ns_oracle.c -- plain, slow, FP64 reference implementation of gradient-guided
+ * nested sampling (GGNS) with the batched Hamiltonian slice sampling (HSS) walk.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this file.  The GPU engine shares no code,
+ * header, table or constant with it; both sides only read the same seeded
+ * inputs (positions, likelihood parameters, run settings and the 64-bit seed)
+ * and each implements the two published random-number generators on its own.
+ *
+ * What it follows (paper: Lemos et al., "Improving Gradient-guided Nested
+ * Sampling for Posterior Inference", arXiv:2312.03911):
+ *   - Appendix A, Algorithm "simple nested sampling" and Eqs. (cum_prior_mass),
+ *     (ns_sum), (delta_x), (importance_weight), (shell_volume): kill the lowest
+ *     point, add X*L/(n+1) to Z, shrink X by n/(n+1).
+ *   - Appendix H, Algorithm "GGNS": kill n_live//2 per iteration, start walkers
+ *     from surviving live points, run the HSS walk, adapt dt from out_frac
+ *     (x0.9 above 0.15, x1.1 below 0.05), add the new points, final sweep.
+ *   - Appendix H, Algorithm "GGNS HSS": drift x += p dt, evaluate L and grad L,
+ *     mark points outside the slice, reflect p -= 2 (p.n) n with n the unit
+ *     gradient, multiply p by (1 + delta_p * eps), count reflections, keep
+ *     in-slice points after min_ref reflections, return a uniform pick and the
+ *     fraction of outside steps.
+ *   - Section 2.3, Eq. (reflection) and the outside-point scheme; Section 3
+ *     (adaptive dt, trajectory preservation, pruning, parallel evolution,
+ *     termination); Appendix C table of defaults.
+ *   - Appendix H, Eqs. (ini0)-(ini11) and (update0)-(update9), single cluster:
+ *     the moments Zbar, Z2bar, ZXbar, Xbar, X2bar, updated one killed point at
+ *     a time with n_p decreasing while the batch is removed.
+ *   - Section 2.1, Eq. (logZ_error): sigma(log Z) ~ sqrt(D_KL / n_live).
+ *
+ * Readings where the paper is silent or garbled (each one is also taken by the
+ * GPU engine):
+ *   R1  k walkers per iteration (default n_live//2); starts drawn uniformly,
+ *       with replacement, from the survivors listed in ascending slot order.
+ *   R2  L* is the largest killed log-likelihood; a point is outside the slice
+ *       when log L <= L* (strict constraint), compared in FP64.
+ *   R3  kill order: ascending (log L, slot index).
+ *   R4  the reflection normal is taken at the current (outside) position.
+ *   R5  a zero or non-finite gradient reflects p -> -p.
+ *   R6  leaving the prior box counts as outside and takes precedence; the
+ *       momentum component of every violated axis is negated.
+ *   R7  eps is drawn per component and applied to every walker at every step,
+ *       after any reflection.
+ *   R8  a point is saved when it is inside the slice and this walker has made
+ *       at least min_ref reflections (per walker, not the batch minimum).
+ *   R9  the saved set is per walker and sampled uniformly by a size-one
+ *       reservoir (Vitter's Algorithm R).
+ *   R10 empty saved set: output the last in-slice point, else the start point.
+ *   R11 a walker stops at max_ref reflections, capped at n_steps_max steps;
+ *       max_ref = 0 selects a fixed number of steps (n_steps_max).
+ *   R12 pruning: prune_streak consecutive outside steps reset the walker to its
+ *       start point with fresh momentum and zero reflections.
+ *   R13 one dt per run, updated once per iteration from that run's out_frac.
+ *   R14 dt_init is in units of the prior width.
+ *   R16 batch kill with n_p = n, n-1, ..., n-k+1 (the Xbar convention).
+ *   R17 final sweep with n_p = n, ..., 1.
+ *   R18 termination: remaining-evidence test Xbar * max L < tol * Zbar, or the
+ *       X*L peak test of the paper (skipped at the first iteration).
+ *   R19 sigma_mom^2 = log Z2bar - 2 log Zbar from the moment recursion, every
+ *       right-hand side using pre-update values and X2bar initialised to 1.
+ *   R22 random streams: Philox4x32-10 (counter based) for prior draws, start
+ *       indices, initial and pruning momenta and for seeding; xoshiro128++ per
+ *       (walker, block of four coordinates) for the per-step noise and one per
+ *       walker for the reservoir; Box-Muller normals from 24-bit uniforms.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Random numbers (reading R22).                                       */
+/* ------------------------------------------------------------------ */
+
+/* Philox4x32 with 10 rounds, as defined by Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3" (SC'11): each round multiplies
+ * words 0 and 2 by two fixed odd constants, swaps the high/low halves across
+ * the lanes and xors in the key; the key is bumped by two Weyl constants
+ * between rounds. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+enum { TAG_INIT = 1, TAG_START = 2, TAG_P0 = 3, TAG_EPS = 4, TAG_RES = 5 };
+
+static void stream_draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                        uint32_t tag, uint32_t sub, uint32_t out[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, (tag << 24) | (sub & 0xFFFFFFu)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox(ctr, key, out);
+}
+
+/* xoshiro128++ of Blackman and Vigna, "Scrambled linear pseudorandom number
+ * generators" (2018): output rotl(s0 + s3, 7) + s0, then the xor-shift state
+ * update with shift 9 and rotation 11. */
+static inline uint32_t rotl32(uint32_t v, int k) { return (v << k) | (v >> (32 - k)); }
+
+uint32_t orc_xoshiro_next(uint32_t s[4])
+{
+    uint32_t result = rotl32(s[0] + s[3], 7) + s[0];
+    uint32_t t = s[1] << 9;
+    s[2] ^= s[0];
+    s[3] ^= s[1];
+    s[1] ^= s[2];
+    s[0] ^= s[3];
+    s[2] ^= t;
+    s[3] = rotl32(s[3], 11);
+    return result;
+}
+
+static void xoshiro_seed(uint32_t s[4], const uint32_t w[4])
+{
+    s[0] = w[0]; s[1] = w[1]; s[2] = w[2]; s[3] = w[3];
+    if ((s[0] | s[1] | s[2] | s[3]) == 0u) s[0] = 1u;   /* the all-zero state is a fixed point */
+}
+
+/* Uniforms from the top 24 bits: open interval for the logarithm, half-open
+ * for the angle. */
+static inline double u24_open(uint32_t a) { return ((double)(a >> 8) + 0.5) * (1.0 / 16777216.0); }
+static inline double u24_half(uint32_t a) { return (double)(a >> 8) * (1.0 / 16777216.0); }
+
+/* Box-Muller: four 32-bit words give four standard normals. */
+void orc_box_muller4(const uint32_t w[4], double z[4])
+{
+    for (int pair = 0; pair < 2; ++pair) {
+        double u1 = u24_open(w[2 * pair]);
+        double u2 = u24_half(w[2 * pair + 1]);
+        double r = sqrt(-2.0 * log(u1));
+        double ang = 2.0 * M_PI * u2;
+        z[2 * pair] = r * cos(ang);
+        z[2 * pair + 1] = r * sin(ang);
+    }
+}
+
+/* d standard normals for one walker from the counter-based stream `tag`. */
+static void normals_philox(uint64_t seed, uint32_t walker, uint32_t iter, uint32_t tag,
+                           uint32_t sub, int d, double *z)
+{
+    for (int b = 0; 4 * b < d; ++b) {
+        uint32_t w[4];
+        double zz[4];
+        stream_draw(seed, (uint32_t)b, walker, iter, tag, sub, w);
+        orc_box_muller4(w, zz);
+        for (int j = 0; j < 4 && 4 * b + j < d; ++j) z[4 * b + j] = zz[j];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Likelihoods (FP64).  All are normalised densities in theta, so log Z  */
+/* under the uniform box prior has a closed form.                        */
+/* ------------------------------------------------------------------ */
+
+enum { LIK_GAUSS_DIAG = 0, LIK_GAUSS_FULL = 1, LIK_SHELLS = 2, LIK_GMM_DIAG = 3 };
+
+static double logaddexp(double a, double b)
+{
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    double m = a > b ? a : b;
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+/* Round to bfloat16 (round to nearest, ties to even) after rounding to FP32:
+ * the operand rounding of a BF16 matrix-core product. */
+static double round_bf16(double v)
+{
+    float f = (float)v;
+    uint32_t bits;
+    memcpy(&bits, &f, 4);
+    uint32_t lsb = (bits >> 16) & 1u;
+    bits += 0x7FFFu + lsb;
+    bits &= 0xFFFF0000u;
+    memcpy(&f, &bits, 4);
+    return (double)f;
+}
+
+/* Parameter blocks (raw, FP64):
+ *   GAUSS_DIAG: mu[d], sigma[d]
+ *   GAUSS_FULL: mu[d], P[d*d] (precision, row-major), log det P
+ *   SHELLS:     K times { c[d], r, w }
+ *   GMM_DIAG:   K times { mu[d], sigma[d] }, equal weights 1/K
+ * Writes log L to *logl and grad log L to g[d] (when g is not NULL). */
+int orc_loglike(int kind, int n_comp, const double *prm, int d, const double *x,
+                double *logl, double *g, int bf16)
+{
+    const double log2pi = log(2.0 * M_PI);
+    if (kind == LIK_GAUSS_DIAG) {
+        const double *mu = prm, *sg = prm + d;
+        double l = 0.0;
+        for (int a = 0; a < d; ++a) {
+            double r = x[a] - mu[a];
+            double iv = 1.0 / (sg[a] * sg[a]);
+            l += -0.5 * (log2pi + 2.0 * log(sg[a])) - 0.5 * r * r * iv;
+            if (g) g[a] = -r * iv;
+        }
+        *logl = l;
+        return 0;
+    }
+    if (kind == LIK_GAUSS_FULL) {
+        const double *mu = prm, *P = prm + d;
+        double logdet = prm[d + (int64_t)d * d];
+        double *r = (double *)malloc(sizeof(double) * d);
+        double *rr = (double *)malloc(sizeof(double) * d);
+        for (int a = 0; a < d; ++a) {
+            r[a] = x[a] - mu[a];
+            rr[a] = bf16 ? round_bf16(r[a]) : r[a];
+        }
+        double q = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double y = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double pij = P[(int64_t)i * d + j];
+                if (bf16) pij = round_bf16(pij);
+                y += pij * rr[j];
+            }
+            q += r[i] * y;
+            if (g) g[i] = -y;
+        }
+        *logl = -0.5 * d * log2pi + 0.5 * logdet - 0.5 * q;
+        free(r);
+        free(rr);
+        return 0;
+    }
+    if (kind == LIK_SHELLS) {
+        int K = n_comp;
+        double lp[64], rho[64];
+        if (K > 64) return -1;
+        double l = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            const double *c = prm + (int64_t)k * (d + 2);
+            double rad = c[d], w = c[d + 1];
+            double s = 0.0;
+            for (int a = 0; a < d; ++a) s += (x[a] - c[a]) * (x[a] - c[a]);
+            rho[k] = sqrt(s);
+            double e = rho[k] - rad;
+            lp[k] = -0.5 * (log2pi + 2.0 * log(w)) - 0.5 * e * e / (w * w);
+            l = logaddexp(l, lp[k]);
+        }
+        *logl = l;
+        if (g) {
+            for (int a = 0; a < d; ++a) g[a] = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const double *c = prm + (int64_t)k * (d + 2);
+                double rad = c[d], w = c[d + 1];
+                if (!(rho[k] > 0.0)) continue;
+                double resp = exp(lp[k] - l);
+                double coef = -resp * (rho[k] - rad) / (w * w) / rho[k];
+                for (int a = 0; a < d; ++a) g[a] += coef * (x[a] - c[a]);
+            }
+        }
+        return 0;
+    }
+    if (kind == LIK_GMM_DIAG) {
+        int K = n_comp;
+        double lp[64];
+        if (K > 64) return -1;
+        double l = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            const double *mu = prm + (int64_t)k * 2 * d, *sg = mu + d;
+            double s = -log((double)K);
+            for (int a = 0; a < d; ++a) {
+                double r = x[a] - mu[a];
+                s += -0.5 * (log2pi + 2.0 * log(sg[a])) - 0.5 * r * r / (sg[a] * sg[a]);
+            }
+            lp[k] = s;
+            l = logaddexp(l, s);
+        }
+        *logl = l;
+        if (g) {
+            for (int a = 0; a < d; ++a) g[a] = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const double *mu = prm + (int64_t)k * 2 * d, *sg = mu + d;
+                double resp = exp(lp[k] - l);
+                for (int a = 0; a < d; ++a) g[a] += -resp * (x[a] - mu[a]) / (sg[a] * sg[a]);
+            }
+        }
+        return 0;
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Run settings and state (plain structs filled by the Python wrapper). */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t d, n_live, n_kill, kind, n_comp, bf16;
+    double lo, hi, dt_init;
+    int32_t n_steps_max, min_ref, max_ref, prune_streak;
+    double delta_p, out_hi, out_lo, dt_down, dt_up;
+    int32_t term_kind, max_iter;
+    double term_tol;
+    uint64_t seed;
+} orc_desc;
+
+enum { ST_ACTIVE = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3 };
+
+typedef struct {
+    double *live_x;       /* [n_live * d], point-major */
+    double *live_logl;    /* [n_live] */
+    double *dead_logl;    /* [dead_cap] */
+    double *dead_logw;    /* [dead_cap]: log of the prior-volume shell w_i */
+    int64_t dead_cap, n_dead;
+    int32_t *killed;      /* [n_kill], ascending (log L, slot) */
+    int32_t *surv;        /* [n_live - n_kill], ascending slot */
+    int32_t *start;       /* [n_kill], start slot of each walker */
+    double *out_x;        /* [n_kill * d] walker outputs */
+    double *out_logl;     /* [n_kill] */
+    double lz, lx, lz2, lzx, lx2; /* log of the moments Zbar, Z2bar, ZXbar, Xbar, X2bar */
+    double lxl_max, dt, lstar;
+    int64_t iter, evals, steps_out, steps_in, prunes, nosave, it_outs, it_steps;
+    int32_t state, pad;
+    double h, sigma_kl, sigma_mom;
+    /* optional per-step trace of the first trace_steps steps of each walker */
+    double *trace_x;      /* [trace_steps * n_kill * d] */
+    double *trace_logl;   /* [trace_steps * n_kill] */
+    int32_t *trace_out;   /* [trace_steps * n_kill] */
+    int32_t trace_steps, pad2;
+} orc_state;
+
+/* Step 1 of the outer loop: n_live uniform prior draws and their likelihoods
+ * (Algorithm GGNS, first three lines); moments as in Eqs. (ini0)-(ini11). */
+int orc_init(const orc_desc *D, const double *prm, orc_state *S)
+{
+    int d = D->d, n = D->n_live;
+    double w = D->hi - D->lo;
+    for (int i = 0; i < n; ++i) {
+        double *x = S->live_x + (int64_t)i * d;
+        for (int b = 0; 4 * b < d; ++b) {
+            uint32_t u[4];
+            stream_draw(D->seed, (uint32_t)b, (uint32_t)i, 0u, TAG_INIT, 0u, u);
+            for (int j = 0; j < 4 && 4 * b + j < d; ++j) x[4 * b + j] = D->lo + w * u24_open(u[j]);
+        }
+        orc_loglike(D->kind, D->n_comp, prm, d, x, &S->live_logl[i], NULL, D->bf16);
+    }
+    S->lz = -INFINITY; S->lz2 = -INFINITY; S->lzx = -INFINITY;
+    S->lx = 0.0; S->lx2 = 0.0;
+    S->lxl_max = -INFINITY;
+    S->dt = D->dt_init * w;
+    S->lstar = -INFINITY;
+    S->iter = 0; S->evals = n; S->n_dead = 0;
+    S->steps_out = S->steps_in = S->prunes = S->nosave = 0;
+    S->it_outs = S->it_steps = 0;
+    S->state = ST_ACTIVE;
+    S->h = S->sigma_kl = S->sigma_mom = 0.0;
+    return 0;
+}
+
+/* Kill one point with n_p live points before the removal: record the dead
+ * point with its shell volume and apply the single-cluster moment updates
+ * (update0), (update2), (update3), (update5) and (update8); every right-hand
+ * side uses the values before this update. */
+static void kill_one(orc_state *S, double l, int64_t n_p)
+{
+    double ln = log((double)n_p), ln1 = log((double)n_p + 1.0), ln2 = log((double)n_p + 2.0);
+    double lz = S->lz, lz2 = S->lz2, lzx = S->lzx, lx = S->lx, lx2 = S->lx2;
+    double logw = lx - ln1;                       /* E[X_{i-1} - X_i] = Xbar/(n_p+1) */
+    if (S->n_dead < S->dead_cap) {
+        S->dead_logl[S->n_dead] = l;
+        S->dead_logw[S->n_dead] = logw;
+    }
+    S->n_dead += 1;
+    S->lz = logaddexp(lz, lx + l - ln1);
+    S->lz2 = logaddexp(lz2, logaddexp(log(2.0) + lzx + l - ln1,
+                                      log(2.0) + lx2 + 2.0 * l - ln1 - ln2));
+    S->lzx = logaddexp(ln + lzx - ln1, ln + lx2 + l - ln1 - ln2);
+    S->lx = lx + ln - ln1;
+    S->lx2 = lx2 + ln - ln2;
+}
+
+static int cmp_lslot(const double *logl, int a, int b)
+{
+    if (logl[a] < logl[b]) return -1;
+    if (logl[a] > logl[b]) return 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Order slots by ascending (log L, slot) with a bottom-up merge sort. */
+static void sort_slots(const double *logl, int n, int32_t *order)
+{
+    for (int i = 0; i < n; ++i) order[i] = i;
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    for (int width = 1; width < n; width *= 2) {
+        for (int lo = 0; lo < n; lo += 2 * width) {
+            int mid = lo + width < n ? lo + width : n;
+            int hi = lo + 2 * width < n ? lo + 2 * width : n;
+            int i = lo, j = mid, k = lo;
+            while (i < mid && j < hi) tmp[k++] = (cmp_lslot(logl, order[i], order[j]) <= 0) ? order[i++] : order[j++];
+            while (i < mid) tmp[k++] = order[i++];
+            while (j < hi) tmp[k++] = order[j++];
+        }
+        memcpy(order, tmp, sizeof(int32_t) * n);
+    }
+    free(tmp);
+}
+
+/* Final sweep (Algorithm GGNS, closing loop; reading R17) and the run
+ * summary: posterior weights p_i = L_i w_i / Z, H = sum p_i log(L_i / Z),
+ * sigma_KL = sqrt(H / n_live), sigma_mom from the moments. */
+static void final_sweep(const orc_desc *D, orc_state *S)
+{
+    int n = D->n_live;
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * n);
+    sort_slots(S->live_logl, n, order);
+    for (int j = 0; j < n; ++j) kill_one(S, S->live_logl[order[j]], (int64_t)n - j);
+    free(order);
+    int64_t nd = S->n_dead < S->dead_cap ? S->n_dead : S->dead_cap;
+    double h = 0.0;
+    for (int64_t i = 0; i < nd; ++i) {
+        double lp = S->dead_logl[i] + S->dead_logw[i] - S->lz;
+        h += exp(lp) * (S->dead_logl[i] - S->lz);
+    }
+    S->h = h;
+    S->sigma_kl = sqrt(h > 0.0 ? h / n : 0.0);
+    double v = S->lz2 - 2.0 * S->lz;
+    S->sigma_mom = sqrt(v > 0.0 ? v : 0.0);
+}
+
+/* Termination test, kill step and evidence update of one iteration
+ * (Algorithm GGNS, loop head and the kill loop; readings R16, R18). */
+int orc_evidence_update(const orc_desc *D, orc_state *S, int force_final)
+{
+    if (S->state != ST_ACTIVE) return 0;
+    int n = D->n_live, k = D->n_kill;
+    double lmax = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        if (isnan(S->live_logl[i])) { S->state = ST_NONFINITE; return 0; }
+        if (S->live_logl[i] > lmax) lmax = S->live_logl[i];
+    }
+    int stop = force_final != 0;
+    if (D->term_kind == 0) {
+        if (S->lx + lmax < log(D->term_tol) + S->lz) stop = 1;
+    } else {
+        double r = S->lx + lmax;
+        if (r > S->lxl_max) S->lxl_max = r;
+        if (S->iter > 0 && r - S->lxl_max < log(D->term_tol)) stop = 1;
+    }
+    if (!stop && S->iter >= D->max_iter) { final_sweep(D, S); S->state = ST_MAXITER; return 0; }
+    if (stop) { final_sweep(D, S); S->state = ST_DONE; return 0; }
+
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * n);
+    sort_slots(S->live_logl, n, order);
+    for (int j = 0; j < k; ++j) {
+        S->killed[j] = order[j];
+        kill_one(S, S->live_logl[order[j]], (int64_t)n - j);
+    }
+    S->lstar = S->live_logl[order[k - 1]];
+    char *dead = (char *)calloc((size_t)n, 1);
+    for (int j = 0; j < k; ++j) dead[order[j]] = 1;
+    int m = 0;
+    for (int i = 0; i < n; ++i)
+        if (!dead[i]) S->surv[m++] = i;
+    free(dead);
+    free(order);
+    return 0;
+}
+
+/* One walker of the batched HSS walk (Algorithm GGNS HSS; Eq. reflection;
+ * readings R4-R12).  Reports its outside steps, steps, prunes and whether it
+ * saved no point. */
+static void walk_one(const orc_desc *D, const double *prm, orc_state *S, int m,
+                     int64_t *outs_o, int64_t *steps_o, int64_t *prunes_o, int64_t *nosave_o)
+{
+    int d = D->d, k = D->n_kill, nsurv = D->n_live - D->n_kill;
+    uint32_t it = (uint32_t)S->iter;
+    uint32_t u[4];
+    stream_draw(D->seed, 0u, (uint32_t)m, it, TAG_START, 0u, u);
+    int s = S->surv[(int)(((uint64_t)u[0] * (uint64_t)nsurv) >> 32)];
+    S->start[m] = s;
+    double *x = (double *)malloc(sizeof(double) * d);
+    double *x0 = (double *)malloc(sizeof(double) * d);
+    double *p = (double *)malloc(sizeof(double) * d);
+    double *g = (double *)malloc(sizeof(double) * d);
+    double *eps = (double *)malloc(sizeof(double) * (d + 4));
+    int nb = (d + 3) / 4;
+    uint32_t *xs = (uint32_t *)malloc(sizeof(uint32_t) * 4 * nb);
+    memcpy(x0, S->live_x + (int64_t)s * d, sizeof(double) * d);
+    memcpy(x, x0, sizeof(double) * d);
+    double l0 = S->live_logl[s];
+    normals_philox(D->seed, (uint32_t)m, it, TAG_P0, 0u, d, p);
+    for (int b = 0; b < nb; ++b) {
+        stream_draw(D->seed, (uint32_t)b, (uint32_t)m, it, TAG_EPS, 0u, u);
+        xoshiro_seed(xs + 4 * b, u);
+    }
+    uint32_t xr[4];
+    stream_draw(D->seed, 0u, (uint32_t)m, it, TAG_RES, 0u, u);
+    xoshiro_seed(xr, u);
+
+    double *out = S->out_x + (int64_t)m * d;
+    memcpy(out, x0, sizeof(double) * d);
+    double out_l = l0;
+    int nref = 0, streak = 0, steps = 0, outs = 0, n_prune = 0;
+    int64_t nsave = 0;
+    double dt = S->dt, lstar = S->lstar;
+    while (steps < D->n_steps_max && (D->max_ref == 0 || nref < D->max_ref)) {
+        double l;
+        for (int a = 0; a < d; ++a) x[a] = x[a] + dt * p[a];
+        orc_loglike(D->kind, D->n_comp, prm, d, x, &l, g, D->bf16);
+        int box = 0;
+        for (int a = 0; a < d; ++a)
+            if (x[a] < D->lo || x[a] > D->hi) box = 1;
+        int outside = box || (l <= lstar);
+        if (S->trace_x && steps < S->trace_steps) {
+            int64_t row = (int64_t)steps * k + m;
+            memcpy(S->trace_x + row * d, x, sizeof(double) * d);
+            S->trace_logl[row] = l;
+            S->trace_out[row] = outside;
+        }
+        steps += 1;
+        if (outside) {
+            if (box) {
+                for (int a = 0; a < d; ++a)
+                    if (x[a] < D->lo || x[a] > D->hi) p[a] = -p[a];
+            } else {
+                double pg = 0.0, gg = 0.0;
+                for (int a = 0; a < d; ++a) { pg += p[a] * g[a]; gg += g[a] * g[a]; }
+                if (isfinite(gg) && gg > 0.0) {
+                    /* p' = p - 2 (p.n) n with n = g / |g| */
+                    double f = 2.0 * pg / gg;
+                    for (int a = 0; a < d; ++a) p[a] = p[a] - f * g[a];
+                } else {
+                    for (int a = 0; a < d; ++a) p[a] = -p[a];
+                }
+            }
+        }
+        for (int b = 0; b < nb; ++b) {
+            uint32_t w[4];
+            for (int j = 0; j < 4; ++j) w[j] = orc_xoshiro_next(xs + 4 * b);
+            orc_box_muller4(w, eps + 4 * b);
+        }
+        for (int a = 0; a < d; ++a) p[a] = p[a] * (1.0 + D->delta_p * eps[a]);
+        uint32_t ures = orc_xoshiro_next(xr);
+        nref += outside;
+        outs += outside;
+        streak = outside ? streak + 1 : 0;
+        if (!outside) {
+            if (nref >= D->min_ref) {
+                nsave += 1;
+                /* keep this point with probability 1/nsave (Algorithm R) */
+                if ((uint64_t)ures * (uint64_t)nsave < ((uint64_t)1 << 32)) {
+                    memcpy(out, x, sizeof(double) * d);
+                    out_l = l;
+                }
+            } else if (nsave == 0) {
+                memcpy(out, x, sizeof(double) * d);   /* last in-slice point */
+                out_l = l;
+            }
+        }
+        if (D->prune_streak > 0 && streak >= D->prune_streak) {
+            memcpy(x, x0, sizeof(double) * d);
+            n_prune += 1;
+            normals_philox(D->seed, (uint32_t)m, it, TAG_P0, (uint32_t)n_prune, d, p);
+            nref = 0;
+            streak = 0;
+        }
+    }
+    S->out_logl[m] = out_l;
+    *outs_o = outs;
+    *steps_o = steps;
+    *prunes_o = n_prune;
+    *nosave_o = (nsave == 0);
+    free(x); free(x0); free(p); free(g); free(eps); free(xs);
+}
+
+int orc_hss_walk(const orc_desc *D, const double *prm, orc_state *S)
+{
+    if (S->state != ST_ACTIVE) return 0;
+    int k = D->n_kill;
+    int64_t outs = 0, steps = 0, prunes = 0, nosave = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : outs, steps, prunes, nosave)
+    for (int m = 0; m < k; ++m) {
+        int64_t o, st, pr, ns;
+        walk_one(D, prm, S, m, &o, &st, &pr, &ns);
+        outs += o; steps += st; prunes += pr; nosave += ns;
+    }
+    S->it_outs = outs;
+    S->it_steps = steps;
+    S->steps_out += outs;
+    S->steps_in += steps - outs;
+    S->prunes += prunes;
+    S->nosave += nosave;
+    S->evals += steps;
+    return 0;
+}
+
+/* Add the new points into the killed slots and adapt dt from out_frac
+ * (Algorithm GGNS, dt update and "add theta_new"). */
+int orc_replace_dead(const orc_desc *D, orc_state *S)
+{
+    if (S->state != ST_ACTIVE) return 0;
+    int d = D->d, k = D->n_kill;
+    for (int m = 0; m < k; ++m) {
+        int slot = S->killed[m];
+        memcpy(S->live_x + (int64_t)slot * d, S->out_x + (int64_t)m * d, sizeof(double) * d);
+        S->live_logl[slot] = S->out_logl[m];
+    }
+    if (S->it_steps > 0) {
+        double out_frac = (double)S->it_outs / (double)S->it_steps;
+        if (out_frac > D->out_hi) S->dt *= D->dt_down;
+        else if (out_frac < D->out_lo) S->dt *= D->dt_up;
+    }
+    S->iter += 1;
+    return 0;
+}
+
+/* Whole run: init, iterate until termination, final sweep. */
+int orc_run(const orc_desc *D, const double *prm, orc_state *S)
+{
+    orc_init(D, prm, S);
+    while (S->state == ST_ACTIVE) {
+        orc_evidence_update(D, S, 0);
+        if (S->state != ST_ACTIVE) break;
+        orc_hss_walk(D, prm, S);
+        orc_replace_dead(D, S);
+    }
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Raw stream access for the generator tests. */
+void orc_stream_words(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag,
+                      uint32_t sub, uint32_t out[4])
+{
+    stream_draw(seed, c0, c1, c2, tag, sub, out);
+}
+
+double orc_round_bf16(double v) { return round_bf16(v); }

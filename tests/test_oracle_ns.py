@@ -1,0 +1,215 @@
+"""Pins for the oracle's nested-sampling bookkeeping: prior-volume shrinkage
+and weights (Appendix A, Eqs. delta_x, importance_weight, shell_volume), the
+batch kill of Algorithm GGNS, the moment recursion of Eqs. (update0)-(update9),
+termination, and end-to-end evidences against closed forms."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+from paper_2312_03911_amd import exact, inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _flat_run(orc, n, k, n_iter, seed=1):
+    cfg = inputs.config_gauss2d(seed=seed, n_live=n, n_kill=k, max_iter=10 ** 6)
+    o = orc.Oracle(cfg).init()
+    for _ in range(n_iter):
+        o.iterate()
+    return o
+
+
+def test_single_kill_is_simple_nested_sampling(orc):
+    """k = 1: each dead point carries X/(n+1) and X shrinks by n/(n+1) (the
+    simple algorithm of Appendix A)."""
+    n = 40
+    o = _flat_run(orc, n, 1, 25)
+    _, lw = o.dead()
+    i = np.arange(len(lw))
+    np.testing.assert_allclose(lw, -math.log(n + 1) + i * math.log(n / (n + 1)), rtol=0, atol=1e-12)
+
+
+def test_batch_kill_weights_telescope(orc):
+    """k = n/2 with n_p = n, n-1, ...: every killed point of a batch carries the
+    same X/(n+1), and X shrinks by (n+1-k)/(n+1) per batch (derived from the
+    Beta(n_p, 1) shrinkage of each single kill)."""
+    n, k = 100, 50
+    o = _flat_run(orc, n, k, 8)
+    _, lw = o.dead()
+    assert len(lw) == 8 * k
+    t = np.arange(len(lw)) // k
+    expect = t * math.log((n + 1 - k) / (n + 1)) - math.log(n + 1)
+    np.testing.assert_allclose(lw, expect, rtol=0, atol=1e-12)
+    assert abs(o.st.lx - 8 * math.log((n + 1 - k) / (n + 1))) < 1e-12
+
+
+def test_kill_order_and_threshold_with_ties(orc):
+    cfg = inputs.config_gauss2d(n_live=8, n_kill=4)
+    o = orc.Oracle(cfg).init()
+    l = np.array([0.5, -1.0, 0.5, 2.0, -1.0, 0.5, 3.0, 0.5])
+    o.set_state(live_logl=l, log_z=-math.inf)
+    o.evidence_update()
+    # ascending (log L, slot): slots 1, 4 (-1.0) then 0, 2 (0.5)
+    assert o.killed.tolist() == [1, 4, 0, 2]
+    assert o.st.lstar == 0.5
+    assert o.surv[:4].tolist() == [3, 5, 6, 7]
+
+
+def test_moment_recursion_matches_monte_carlo(orc):
+    """Zbar and Z2bar of the recursion equal the mean and second moment of the
+    evidence sum over the stochastic shrinkages t ~ Beta(n_p, 1)."""
+    n, k = 10, 5
+    o = _flat_run(orc, n, k, 6)
+    o.evidence_update(final_sweep=True)
+    ll, _ = o.dead()
+    n_p = np.concatenate([np.tile(n - np.arange(k), 6), n - np.arange(n)])
+    assert len(n_p) == len(ll)
+    L = np.exp(ll - ll.max())
+    rng = np.random.default_rng(0)
+    reps = 400000
+    X = np.ones(reps)
+    Z = np.zeros(reps)
+    for j in range(len(ll)):
+        t = rng.beta(n_p[j], 1.0, size=reps)
+        Xn = X * t
+        Z += (X - Xn) * L[j]
+        X = Xn
+    ez, ez2 = Z.mean(), (Z ** 2).mean()
+    se = Z.std() / math.sqrt(reps)
+    assert abs(math.exp(o.st.lz - ll.max()) - ez) < 4 * se
+    se2 = (Z ** 2).std() / math.sqrt(reps)
+    assert abs(math.exp(o.st.lz2 - 2 * ll.max()) - ez2) < 4 * se2
+
+
+def test_final_sweep_equal_weights(orc):
+    n, k = 30, 15
+    o = _flat_run(orc, n, k, 4)
+    lx = o.st.lx
+    o.evidence_update(final_sweep=True)
+    assert o.st.state == 1
+    _, lw = o.dead()
+    np.testing.assert_allclose(lw[-n:], lx - math.log(n + 1), atol=1e-12)
+    # the residual volume dropped by the sweep is X/(n+1)
+    assert abs(o.st.lx - (lx - math.log(n + 1))) < 1e-12
+
+
+def _ball_box_draws(k, d, radius, lo, hi, rng):
+    """Exact uniform draws from {|x| < radius} within the box, by rejection."""
+    logvb = 0.5 * d * math.log(math.pi) - special.gammaln(0.5 * d + 1) + d * math.log(radius)
+    out, got = [], 0
+    while got < k:
+        if logvb > d * math.log(hi - lo):
+            X = rng.uniform(lo, hi, size=(8 * k, d))
+            ok = (X ** 2).sum(1) < radius ** 2
+        else:
+            X = inputs.ball_points(8 * k, d, np.zeros(d), radius, seed=int(rng.integers(1 << 30)))
+            ok = np.all((X > lo) & (X < hi), axis=1)
+        out.append(X[ok]); got += ok.sum()
+    return np.concatenate(out)[:k]
+
+
+@pytest.mark.parametrize("d,n", [(8, 100)])
+def test_evidence_with_exact_slice_draws(orc, d, n):
+    """Replace the walk by exact uniform draws from the slice (a ball for an
+    isotropic Gaussian): the batch-kill evidence is unbiased and its spread
+    matches sigma_mom."""
+    sig, lo, hi = 0.5, -6.0, 6.0
+    cfg = inputs.RunConfig(kind="gauss_diag", d=d, n_live=n, lo=lo, hi=hi, precision="fp64",
+                           params=inputs.gauss_diag_params(np.zeros(d), np.full(d, sig)), seed=3)
+    c0 = -0.5 * d * math.log(2 * math.pi * sig ** 2)
+    zs, sm = [], []
+    for r in range(24):
+        o = orc.Oracle(cfg.replace(seed=300 + r)).init()
+        rng = np.random.default_rng(500 + r)
+        while True:
+            o.evidence_update()
+            if not o.active:
+                break
+            rad = sig * math.sqrt(2 * (c0 - o.st.lstar))
+            X = _ball_box_draws(cfg.n_kill, d, rad, lo, hi, rng)
+            o.out_x[...] = X
+            o.out_logl[...] = orc.loglike(cfg, X)[0]
+            o.st.it_steps = 0
+            o.replace_dead()
+        zs.append(o.st.lz); sm.append(o.st.sigma_mom)
+    truth = exact.log_z(cfg)
+    zs = np.array(zs)
+    assert abs(zs.mean() - truth) < 3 * zs.std() / math.sqrt(len(zs)) + 0.02
+    assert 0.5 < zs.std() / np.mean(sm) < 1.6
+
+
+def test_closed_form_gauss_d2_ten_seeds(orc):
+    """The FP64 d=2 workload over the paper's 10-run protocol: the mean log Z is
+    within 3 sigma_KL / sqrt(10) of the closed form and each run within 4
+    sigma_KL."""
+    cfg = inputs.config_gauss2d()
+    truth = exact.log_z(cfg)
+    assert abs(truth) < 1e-20
+    z, s = [], []
+    for r in range(10):
+        o = orc.Oracle(cfg.replace(seed=2100 + r)).run()
+        z.append(o.st.lz); s.append(o.st.sigma_kl)
+        assert o.st.state == 1
+    z, s = np.array(z), np.array(s)
+    assert abs(z.mean() - truth) < 3 * s.mean() / math.sqrt(10)
+    assert np.all(np.abs(z - truth) < 4 * s)
+    assert 0.5 < z.std() / s.mean() < 2.0
+
+
+def test_remaining_evidence_termination_fires_first_time(orc):
+    cfg = inputs.config_gauss2d(seed=5)
+    o = orc.Oracle(cfg).init()
+    while True:
+        lmax = o.live_logl.max()
+        fire = o.st.lx + lmax < math.log(cfg.term_tol) + o.st.lz
+        o.evidence_update()
+        if fire:
+            assert o.st.state == 1
+            break
+        assert o.active
+        o.hss_walk(); o.replace_dead()
+
+
+def test_xl_peak_termination(orc):
+    cfg = inputs.config_gauss2d(seed=5, term_kind=1, term_tol=0.01)
+    o = orc.Oracle(cfg).run()
+    assert o.st.state == 1
+    lmax = o.live_logl.max()
+    # at the stop, X*Lmax fell below tol times its running maximum
+    assert (o.st.lx + math.log(cfg.n_live + 1)) + lmax - o.st.lxl_max < math.log(0.01)
+
+
+def test_max_iter_and_nonfinite_states(orc):
+    cfg = inputs.config_gauss2d(seed=5, max_iter=3)
+    o = orc.Oracle(cfg).run()
+    assert o.st.state == 2 and o.st.iter == 3
+    assert o.st.n_dead == 3 * cfg.n_kill + cfg.n_live
+    bad = cfg.replace(params=np.array([0.5, math.nan, 0.05, 0.05]), max_iter=10)
+    o = orc.Oracle(bad).run()
+    assert o.st.state == 3
+
+
+def test_workload_defaults_follow_paper(orc):
+    with open(os.path.join(HERE, "golden", "paper_defaults.json")) as f:
+        g = json.load(f)
+    for cfg in (inputs.config_corr_gauss(d=16, n_live=100), inputs.config_gmm(d=8, n_live=100)):
+        assert cfg.min_ref == g["min_ref"] and cfg.max_ref == g["max_ref"]
+        assert cfg.delta_p == g["delta_p"] and cfg.dt_init == g["dt_init"]
+        assert cfg.out_hi == g["out_frac_high"] and cfg.out_lo == g["out_frac_low"]
+        assert cfg.dt_down == g["dt_factor_down"] and cfg.dt_up == g["dt_factor_up"]
+        assert cfg.n_kill == int(cfg.n_live * g["kill_fraction"])
+
+
+def test_correlated_gaussian_generator():
+    cfg = inputs.config_corr_gauss(d=32, n_live=100, param_seed=9)
+    d = cfg.d
+    prec = cfg.params[d:d + d * d].reshape(d, d)
+    assert np.allclose(prec, prec.T)
+    sign, logdet = np.linalg.slogdet(prec)
+    assert sign > 0 and abs(logdet - cfg.params[-1]) < 1e-9
+    ev = np.linalg.eigvalsh(np.linalg.inv(prec))
+    assert ev.min() > 1e-2 * 0.999 and ev.max() < 1.0 * 1.001
