@@ -1,0 +1,205 @@
+"""Benchmark: likelihood+gradient evaluations per second of the batched HSS walk.
+
+One step = one whole nested-sampling pass over the workload's batch of runs:
+init (prior draws), iterations of evidence_update -> hss_walk -> replace_dead
+until every run has stopped, final sweep and run summary.  Inputs are
+synthetic and seeded; the closed-form log Z of every run is reported next to
+the estimate.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from paper_2312_03911_amd import exact, inputs  # noqa: E402
+
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16mma": 2500.0}
+
+
+def workload(name: str):
+    if name == "shells32x10":
+        # Gaussian shells d=32, n_live=1000, FP32, 5d-step walks; the paper's
+        # protocol of 10 runs per setting, batched into one launch
+        return inputs.replicate(inputs.config_shells(d=32, n_live=1000), 10, base_seed=2200)
+    if name == "shells32":
+        return [inputs.config_shells(d=32, n_live=1000)]
+    if name == "gauss2d":
+        return [inputs.config_gauss2d()]
+    if name == "gauss2dx10":
+        return inputs.replicate(inputs.config_gauss2d(), 10, base_seed=2100)
+    if name == "gmm64":
+        return [inputs.config_gmm()]
+    if name == "corr256":
+        return [inputs.config_corr_gauss()]
+    if name == "batch64":
+        return inputs.config_batch()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def flops_per_eval(cfg, out_frac: float) -> float:
+    """Algorithmic FP operations of one walker step (drift, log L and score,
+    reflection on outside steps, momentum noise with its Box-Muller normals;
+    a transcendental counts as one operation, integer RNG work counts zero)."""
+    d, K = cfg.d, cfg.n_comp
+    drift = 2 * d
+    if cfg.kind == "gauss_diag":
+        lik = 4 * d + 2
+    elif cfg.kind == "shells":
+        lik = 5 * K * d + 10 * K
+    elif cfg.kind == "gmm_diag":
+        lik = 7 * K * d + 10 * K
+    else:
+        lik = 2 * d * d + 3 * d + 2
+    reflect = 6 * d * out_frac
+    noise = 2 * d + 6 * d          # p *= 1 + dp*eps, plus ~6 ops per Box-Muller normal
+    return drift + lik + reflect + noise
+
+
+def cpu_baseline(cfgs, budget_s: float = 12.0):
+    """The oracle on the host cores, on a bounded sample: iterations of the
+    first run until the time budget is used."""
+    import oracle.oracle as O
+    O.build(force=False)
+    cfg = cfgs[0]
+    o = O.Oracle(cfg).init()
+    t0 = time.perf_counter()
+    e0 = o.st.evals
+    it = 0
+    while o.active and time.perf_counter() - t0 < budget_s:
+        o.iterate()
+        it += 1
+    dt = time.perf_counter() - t0
+    ev = o.st.evals - e0
+    return {"value": ev / dt, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{it} iterations of run 0 ({cfg.name}), {ev} walker steps in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="shells32x10")
+    ap.add_argument("--poll", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        raise SystemExit(2)
+
+    import torch
+
+    from paper_2312_03911_amd.engine import Engine
+
+    cfgs = workload(args.workload)
+    truth = [exact.log_z(c) for c in cfgs]
+    eng = Engine(cfgs, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    walk_ms = []
+    walk_evals = []
+
+    def full_run(record: bool):
+        # re-initialise every run on the same arena, then iterate to the end
+        from paper_2312_03911_amd import _lib
+        import ctypes as C
+        eng.close()
+        eng.ctx = C.c_void_p()
+        _lib.check(eng.L.ggns_init(C.byref(eng.ctx), eng.descs, len(cfgs), eng.params.data_ptr(),
+                                   eng.params.numel(), eng.arena.data_ptr(), eng.arena_bytes,
+                                   eng._stream()), "ggns_init")
+        while True:
+            evs = []
+            for _ in range(args.poll):
+                eng.evidence_update()
+                if record:
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    eng.hss_walk()
+                    b.record(stream)
+                    evs.append((a, b))
+                else:
+                    eng.hss_walk()
+                eng.replace_dead()
+            st = eng.stats()
+            if record:
+                for a, b in evs:
+                    walk_ms.append(a.elapsed_time(b))
+            if all(s["state"] != 0 for s in st):
+                return st
+
+    for _ in range(args.warmup):
+        full_run(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        stats = full_run(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    evals = sum(s["evals"] for s in stats)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = evals * args.steps / elapsed
+    # roofline of the walk kernel: algorithmic operations / measured duration
+    steps_total = sum(s["steps_out"] + s["steps_in"] for s in stats)
+    out_frac = sum(s["steps_out"] for s in stats) / max(steps_total, 1)
+    flops_walk = sum(flops_per_eval(c, s["steps_out"] / max(s["steps_out"] + s["steps_in"], 1))
+                     * (s["steps_out"] + s["steps_in"]) for c, s in zip(cfgs, stats))
+    # only launches that did work (the trailing polled iterations of finished runs are no-ops)
+    n_launch_work = max(1, max(s["iter"] for s in stats)) * args.steps
+    wm = sorted(walk_ms, reverse=True)[:n_launch_work]
+    walk_time_s = sum(wm) / 1e3 / args.steps
+    prec = cfgs[0].precision
+    achieved = flops_walk / walk_time_s / 1e12
+    peak = PEAK_TFLOPS["fp64" if prec == "fp64" else "fp32"]
+    dz = [s["log_z"] - t for s, t in zip(stats, truth)]
+    zs = [d / max(s["sigma_kl"], 1e-12) for d, s in zip(dz, stats)]
+    res = {
+        "metric": "likelihood+grad evals/sec in HSS walks (logZ error stated); roofline fraction",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "runs": len(cfgs),
+                   "d": sorted({c.d for c in cfgs}), "n_live": sorted({c.n_live for c in cfgs}),
+                   "kinds": sorted({c.kind for c in cfgs}), "precision": sorted({c.precision for c in cfgs}),
+                   "evals_per_step": evals, "iterations": [s["iter"] for s in stats][:16]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "walk_valu_kernel", "walk_ms_per_step": 1e3 * walk_time_s,
+                     "walk_evals_per_s": steps_total / walk_time_s, "out_frac": out_frac},
+        "accuracy": {"logz_minus_closed_form_mean": float(np.mean(dz)),
+                     "logz_minus_closed_form_sd": float(np.std(dz)),
+                     "z_scores_max_abs": float(np.max(np.abs(zs))),
+                     "sigma_kl_mean": float(np.mean([s["sigma_kl"] for s in stats])),
+                     "sigma_mom_mean": float(np.mean([s["sigma_mom"] for s in stats]))},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(cfgs)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * ggns.h -- C ABI of the MI355X engine for the data-parallel hot path of
+ * gradient-guided nested sampling (GGNS; Lemos et al., arXiv:2312.03911).
+ *
+ * The engine advances many independent nested-sampling runs at once.  Per run
+ * and per iteration the caller enqueues, on one stream and in this order:
+ *
+ *   ggns_evidence_update  termination test, kill of the n_kill lowest live
+ *                         points, evidence and prior-volume bookkeeping
+ *                         (Appendix A Eqs. ns_sum / delta_x / importance_weight
+ *                         / shell_volume; Algorithm GGNS kill loop; Eqs.
+ *                         update0-update9), and the final sweep when the run
+ *                         stops (Algorithm GGNS closing loop);
+ *   ggns_hss_walk         the batched Hamiltonian slice sampling walk that
+ *                         moves every walker at once (Algorithm GGNS HSS;
+ *                         Eq. reflection; Section 3: adaptive dt, trajectory
+ *                         preservation, pruning, parallel evolution);
+ *   ggns_replace_dead     the walk outputs replace the killed points and dt
+ *                         is adapted from the fraction of outside steps
+ *                         (Algorithm GGNS, dt update and "add theta_new").
+ *
+ * Memory.  The library never allocates device memory.  The caller allocates
+ * one device "arena" of ggns_arena_bytes(...) bytes and hands it to
+ * ggns_init; every per-run array (live set, dead records, walker outputs,
+ * accumulators, the parameter blocks converted to the run's precision) lives
+ * inside it at the byte offsets reported by ggns_run_layout.  The arena and
+ * the raw parameter buffer stay owned by the caller and must outlive the
+ * context.  All calls taking `stream` (a hipStream_t; NULL = the default
+ * stream) enqueue asynchronous work and return at once, except
+ * ggns_read_stats, which synchronises the stream.
+ *
+ * Errors.  Return codes below zero (GGNS_E*) mean that nothing was enqueued
+ * (argument or state errors) or that a launch failed (GGNS_EHIP).  Numerical
+ * trouble inside the kernels is reported per run through
+ * ggns_run_stats.state (GGNS_RUN_*); kernels skip runs that are not ACTIVE, so
+ * enqueuing further iterations after a run ended is harmless.
+ *
+ * Layout conventions.  Positions are point-major, [n_live][d] per run, in the
+ * run's precision (double for GGNS_FP64, float otherwise).  Log-likelihoods,
+ * log-weights and every evidence quantity are double.
+ */
+#ifndef GGNS_H
+#define GGNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+enum {
+    GGNS_OK = 0,
+    GGNS_EINVAL = -1,        /* bad argument (sizes, kinds, null pointers, arena too small) */
+    GGNS_EHIP = -2,          /* a HIP call or kernel launch failed */
+    GGNS_EUNSUPPORTED = -3,  /* a size or combination this build does not implement */
+    GGNS_ESTATE = -4         /* call out of order (e.g. no context) */
+};
+
+/* Per-run states (ggns_run_stats.state). */
+enum {
+    GGNS_RUN_ACTIVE = 0,
+    GGNS_RUN_DONE = 1,       /* terminated by its criterion; final sweep done */
+    GGNS_RUN_MAXITER = 2,    /* stopped at max_iter; final sweep done */
+    GGNS_RUN_NONFINITE = 3   /* a live log-likelihood was NaN; the run stopped */
+};
+
+/* Likelihood families.  Raw FP64 parameter blocks, at param_offset:
+ *   GAUSS_DIAG: mu[d], sigma[d]                        N(mu, diag sigma^2)
+ *   GAUSS_FULL: mu[d], P[d*d] (row-major), log det P   N(mu, P^-1)
+ *   SHELLS:     n_comp x { c[d], r, w }   sum_k (2 pi w^2)^-1/2 exp(-(|x-c_k|-r)^2 / 2w^2)
+ *   GMM_DIAG:   n_comp x { mu[d], sigma[d] }           equal-weight diagonal mixture */
+enum { GGNS_LIK_GAUSS_DIAG = 0, GGNS_LIK_GAUSS_FULL = 1, GGNS_LIK_SHELLS = 2, GGNS_LIK_GMM_DIAG = 3 };
+
+/* Arithmetic of the walk.  The threshold compare, the evidence, the weights and
+ * the log prior volume are FP64 in every mode. */
+enum {
+    GGNS_FP64 = 0,           /* positions, momenta, likelihood in double */
+    GGNS_FP32 = 1,           /* positions, momenta, likelihood in float */
+    GGNS_FP32_BF16MMA = 2    /* GAUSS_FULL only: P r on BF16 matrix cores, FP32 accumulate */
+};
+
+/* Termination (paper: Appendix A loop test and the X*L peak criterion of
+ * Section 3 / Appendix I). */
+enum { GGNS_TERM_REMAINING_Z = 0, GGNS_TERM_XL_PEAK = 1 };
+
+/* One run.  Defaults from the paper: min_ref 1, max_ref 3, delta_p 0.05
+ * (Appendix C table), dt_init 0.1 (Appendix G), out_frac band 0.05 / 0.15 with
+ * factors 1.1 / 0.9 (Algorithm GGNS). */
+typedef struct {
+    int32_t d;               /* dimension, 1..256 */
+    int32_t n_live;          /* live points, 2..4096 */
+    int32_t n_kill;          /* killed and re-walked per iteration, 1..n_live-1 (paper: n_live/2) */
+    int32_t lik_kind;        /* GGNS_LIK_* */
+    int32_t precision;       /* GGNS_FP64 / GGNS_FP32 / GGNS_FP32_BF16MMA */
+    int32_t n_comp;          /* components for SHELLS / GMM_DIAG (1..8), else 1 */
+    int64_t param_offset;    /* index (in doubles) of this run's raw block in params_dev */
+    double prior_lo, prior_hi;  /* uniform prior on [lo, hi]^d */
+    double dt_init;          /* initial step in units of (hi - lo) */
+    int32_t n_steps_max;     /* fixed walk length when max_ref == 0, else a cap */
+    int32_t min_ref;         /* keep in-slice points once a walker has this many reflections */
+    int32_t max_ref;         /* a walker stops at this many reflections; 0 = fixed steps */
+    int32_t prune_streak;    /* consecutive outside steps that reset a walker; 0 = never */
+    double delta_p;          /* momentum noise p *= 1 + delta_p * eps */
+    double out_hi, out_lo;   /* out_frac band */
+    double dt_down, dt_up;   /* dt factors above / below the band */
+    int32_t term_kind;       /* GGNS_TERM_* */
+    int32_t max_iter;        /* iteration cap; the dead-record capacity is n_kill*max_iter+n_live */
+    double term_tol;         /* remaining evidence fraction, or the X*L fraction */
+    uint64_t seed;           /* key of every random stream of the run */
+    int32_t tile_c;          /* coordinates per lane in the walk (1,2,4,8); 0 = library choice */
+    int32_t reserved;
+} ggns_run_desc;
+
+/* Byte offsets (from the arena base) of one run's arrays. */
+typedef struct {
+    int64_t live_x;          /* [n_live][d] run precision */
+    int64_t live_logl;       /* [n_live] double */
+    int64_t killed;          /* [n_kill] int32, slots in ascending (log L, slot) order */
+    int64_t survivors;       /* [n_live - n_kill] int32, ascending slot */
+    int64_t start;           /* [n_kill] int32, start slot of each walker */
+    int64_t walk_x;          /* [n_kill][d] run precision, walker outputs */
+    int64_t walk_logl;       /* [n_kill] double */
+    int64_t dead_logl;       /* [dead_cap] double, in kill order */
+    int64_t dead_logw;       /* [dead_cap] double, log prior-volume shell of each dead point */
+    int64_t dead_cap;        /* capacity (elements) */
+    int32_t elem_bytes;      /* 8 (FP64) or 4 */
+    int32_t reserved;
+} ggns_layout;
+
+/* Per-run results and counters. */
+typedef struct {
+    double log_z;            /* log Zbar (batched kills, Xbar convention) */
+    double log_x;            /* log Xbar */
+    double log_z2;           /* log of the second moment of Z (Eqs. update3, update5, update8) */
+    double dt;               /* current step (prior units) */
+    double lstar;            /* current threshold log L* */
+    double log_xl_max;       /* running max of log(X * L_max) (X*L peak criterion) */
+    double h;                /* information H = sum p_i log(L_i / Z), after the final sweep */
+    double sigma_kl;         /* sqrt(H / n_live) (Eq. logZ_error) */
+    double sigma_mom;        /* sqrt(log Z2bar - 2 log Zbar) */
+    int64_t iter;            /* iterations done */
+    int64_t evals;           /* likelihood+gradient evaluations (n_live + walker steps) */
+    int64_t n_dead;          /* dead records written */
+    int64_t steps_out, steps_in;  /* walker steps outside / inside the slice */
+    int64_t prunes;          /* pruning resets */
+    int64_t nosave;          /* walks that saved no point (fell back to the last in-slice point) */
+    int64_t it_outs, it_steps;    /* counters of the last walk (out_frac) */
+    int32_t state;           /* GGNS_RUN_* */
+    int32_t reserved;
+} ggns_run_stats;
+
+/* Values a caller may load into a run (tests, checkpoint/resume). */
+typedef struct {
+    double log_z, log_x, dt;
+    int64_t iter;
+} ggns_run_vars;
+
+typedef struct ggns_ctx ggns_ctx;
+
+/* Bytes of device arena needed for these runs (< 0 on invalid descriptors). */
+int64_t ggns_arena_bytes(const ggns_run_desc *runs, int32_t n_runs);
+
+/* Build a context over a zero-based arena and enqueue the start of every run:
+ * convert parameters, draw n_live points uniformly in the prior box, evaluate
+ * their log-likelihoods, set log Zbar = -inf, log Xbar = 0, dt = dt_init (in
+ * prior units) (Algorithm GGNS, initialisation).  `runs` is copied; params_dev
+ * (n_params doubles, device) must stay valid while the context is used. */
+int ggns_init(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs,
+              const double *params_dev, int64_t n_params, void *arena_dev,
+              int64_t arena_bytes, void *stream);
+
+/* As ggns_init, but over an arena that already holds the state of these runs
+ * (checkpoint/resume): converts parameters only. */
+int ggns_attach(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs,
+                const double *params_dev, int64_t n_params, void *arena_dev,
+                int64_t arena_bytes, void *stream);
+
+/* Termination test, kill and evidence update for every ACTIVE run; a run that
+ * meets its criterion (or max_iter, or final_sweep != 0) gets the final sweep
+ * and its summary (H, sigma_KL, sigma_mom) and leaves the ACTIVE state. */
+int ggns_evidence_update(ggns_ctx *ctx, int32_t final_sweep, void *stream);
+
+/* The batched HSS walk for every ACTIVE run: n_kill walkers, started from
+ * survivors drawn uniformly, write their outputs to walk_x / walk_logl. */
+int ggns_hss_walk(ggns_ctx *ctx, void *stream);
+
+/* Scatter walker outputs into the killed slots, adapt dt, advance the
+ * iteration counter. */
+int ggns_replace_dead(ggns_ctx *ctx, void *stream);
+
+/* log L (and grad log L if grad_dev is not NULL) of run `run` at n points
+ * x_dev [n][d] (run precision); logl_dev [n] double, grad_dev [n][d] run
+ * precision.  The likelihood the walk uses, callable on its own. */
+int ggns_loglike_grad(ggns_ctx *ctx, int32_t run, const void *x_dev, int64_t n,
+                      double *logl_dev, void *grad_dev, void *stream);
+
+/* Adjoint (vector-Jacobian product) of log L: gx[i] = gout[i] * grad log L(x[i]). */
+int ggns_loglike_vjp(ggns_ctx *ctx, int32_t run, const void *x_dev, int64_t n,
+                     const double *gout_dev, void *gx_dev, void *stream);
+
+int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out);
+
+/* Copy every run's stats to host memory `out` (n_runs entries); synchronises `stream`. */
+int ggns_read_stats(ggns_ctx *ctx, ggns_run_stats *out, void *stream);
+
+/* Load log Zbar, log Xbar, dt and the iteration counter of one run. */
+int ggns_write_vars(ggns_ctx *ctx, int32_t run, const ggns_run_vars *vars, void *stream);
+
+/* Record the first trace_steps steps of each walker of `run` during later walks:
+ * trace_x [trace_steps][n_kill][d] run precision, trace_logl [..][n_kill] double,
+ * trace_out [..][n_kill] int32 (1 = outside).  NULL trace_x switches it off. */
+int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl,
+                   int32_t *trace_out, int32_t trace_steps);
+
+/* Coordinates per lane actually used for each run's walk (after defaults). */
+int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
+                    int32_t *lanes_per_walker);
+
+void ggns_free(ggns_ctx *ctx);
+
+const char *ggns_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GGNS_H */

@@ -1,0 +1,424 @@
+// Host side of the C ABI (include/ggns.h): validation, arena layout, walk
+// tiling, and the launches behind each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "ggns_common.h"
+
+using namespace ggns;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+bool valid_desc(const ggns_run_desc &r) {
+    if (r.d < 1 || r.d > kMaxD) return false;
+    if (r.n_live < 2 || r.n_live > kMaxLive) return false;
+    if (r.n_kill < 1 || r.n_kill >= r.n_live) return false;
+    if (r.lik_kind < 0 || r.lik_kind > 3) return false;
+    if (r.precision < 0 || r.precision > 2) return false;
+    if ((r.lik_kind == GGNS_LIK_SHELLS || r.lik_kind == GGNS_LIK_GMM_DIAG) &&
+        (r.n_comp < 1 || r.n_comp > kMaxComp))
+        return false;
+    if (!(r.prior_hi > r.prior_lo)) return false;
+    if (!(r.dt_init > 0.0)) return false;
+    if (r.n_steps_max < 1 || r.min_ref < 0 || r.max_ref < 0 || r.prune_streak < 0) return false;
+    if (!(r.term_tol > 0.0) || r.max_iter < 0) return false;
+    if (r.param_offset < 0) return false;
+    if (r.tile_c != 0 && r.tile_c != 1 && r.tile_c != 2 && r.tile_c != 4 && r.tile_c != 8)
+        return false;
+    return true;
+}
+
+int64_t raw_params(const ggns_run_desc &r) {
+    const int64_t d = r.d, K = r.n_comp;
+    switch (r.lik_kind) {
+        case GGNS_LIK_GAUSS_DIAG: return 2 * d;
+        case GGNS_LIK_GAUSS_FULL: return d + d * d + 1;
+        case GGNS_LIK_SHELLS: return K * (d + 2);
+        default: return K * 2 * d;
+    }
+}
+
+// Coordinates per lane: four (one Philox / xoshiro block of normals per lane)
+// unless d is tiny, eight when four would need more than a wavefront.
+int default_c(int d) {
+    if (d <= 2) return d;
+    if (d <= 4 * 64) return 4;
+    return 8;
+}
+
+struct Plan {
+    std::vector<RunDev> runs;
+    int64_t off_runs = 0, off_tiles = 0, n_tile_slots = 0, total = 0;
+};
+
+// Lay out the arena: run table, tiles, then each run's arrays.
+int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
+    if (n_runs < 1 || descs == nullptr) return GGNS_EINVAL;
+    P.runs.resize(n_runs);
+    int64_t off = 0;
+    P.off_runs = off;
+    off = align_up(off + (int64_t)sizeof(RunDev) * n_runs);
+    // tiles: walk and init tiles of every run (upper bound: one per walker / point)
+    int64_t ntiles = 0;
+    for (int r = 0; r < n_runs; ++r) ntiles += 2 * (int64_t)descs[r].n_live + 2;
+    P.off_tiles = off;
+    P.n_tile_slots = ntiles;
+    off = align_up(off + (int64_t)sizeof(Tile) * ntiles);
+    for (int r = 0; r < n_runs; ++r) {
+        const ggns_run_desc &D = descs[r];
+        if (!valid_desc(D)) return GGNS_EINVAL;
+        if (D.precision == GGNS_FP32_BF16MMA && D.lik_kind != GGNS_LIK_GAUSS_FULL) return GGNS_EINVAL;
+        RunDev &R = P.runs[r];
+        std::memset(&R, 0, sizeof(R));
+        R.d = D.d; R.n_live = D.n_live; R.n_kill = D.n_kill; R.kind = D.lik_kind;
+        R.prec = D.precision; R.n_comp = (D.lik_kind == GGNS_LIK_SHELLS || D.lik_kind == GGNS_LIK_GMM_DIAG) ? D.n_comp : 1;
+        R.n_steps_max = D.n_steps_max; R.min_ref = D.min_ref; R.max_ref = D.max_ref;
+        R.prune_streak = D.prune_streak; R.term_kind = D.term_kind; R.max_iter = D.max_iter;
+        R.lo = D.prior_lo; R.hi = D.prior_hi; R.dt_init = D.dt_init; R.delta_p = D.delta_p;
+        R.out_hi = D.out_hi; R.out_lo = D.out_lo; R.dt_down = D.dt_down; R.dt_up = D.dt_up;
+        R.term_tol = D.term_tol; R.seed = D.seed; R.param_offset = D.param_offset;
+        int C = D.tile_c ? D.tile_c : default_c(D.d);
+        int G = next_pow2((D.d + C - 1) / C);
+        while (G > 64) { C *= 2; G = next_pow2((D.d + C - 1) / C); }
+        if (C > 8 || (D.precision == GGNS_FP64 && C > 4)) return GGNS_EUNSUPPORTED;
+        R.C = C; R.G = G;
+        const int64_t es = (D.precision == GGNS_FP64) ? 8 : 4;
+        R.nprm = converted_params(D.lik_kind, D.d, R.n_comp);
+        const int64_t prm_bytes = (int64_t)R.nprm * es;
+        R.nprm_bytes_lds = (prm_bytes <= 48 * 1024) ? (int32_t)prm_bytes : 0;
+        R.dead_cap = (int64_t)D.n_kill * D.max_iter + D.n_live;
+        R.off_acc = off; off = align_up(off + (int64_t)sizeof(Acc));
+        R.off_prm = off; off = align_up(off + prm_bytes);
+        if (D.precision == GGNS_FP32_BF16MMA) {
+            const int64_t dp = (D.d + 31) / 32 * 32;
+            R.off_prm_bf16 = off; off = align_up(off + dp * dp * 2);
+        } else {
+            R.off_prm_bf16 = -1;
+        }
+        R.off_live_x = off; off = align_up(off + (int64_t)D.n_live * D.d * es);
+        R.off_live_logl = off; off = align_up(off + (int64_t)D.n_live * 8);
+        R.off_killed = off; off = align_up(off + (int64_t)D.n_kill * 4);
+        R.off_surv = off; off = align_up(off + (int64_t)(D.n_live - D.n_kill) * 4);
+        R.off_start = off; off = align_up(off + (int64_t)D.n_kill * 4);
+        R.off_walk_x = off; off = align_up(off + (int64_t)D.n_kill * D.d * es);
+        R.off_walk_logl = off; off = align_up(off + (int64_t)D.n_kill * 8);
+        R.off_dead_logl = off; off = align_up(off + R.dead_cap * 8);
+        R.off_dead_logw = off; off = align_up(off + R.dead_cap * 8);
+    }
+    P.total = off;
+    return GGNS_OK;
+}
+
+struct Class {
+    int prec, C, kind;
+    bool mfma;
+    int64_t tile_off;   // index of the first tile in the arena tile array
+    int n_tiles;
+    size_t lds;
+};
+
+}  // namespace
+
+struct ggns_ctx {
+    Plan plan;
+    std::vector<ggns_run_desc> descs;
+    void *arena = nullptr;
+    int64_t arena_bytes = 0;
+    const double *params = nullptr;
+    int64_t n_params = 0;
+    std::vector<Tile> tiles_host;
+    std::vector<Class> walk_classes, init_classes;
+    std::vector<Acc> acc_host;
+    int max_kd = 1;
+
+    RunDev *runs_dev() const { return at<RunDev>(arena, plan.off_runs); }
+    Tile *tiles_dev() const { return at<Tile>(arena, plan.off_tiles); }
+};
+
+namespace {
+
+// Walk tiles: one walker per lane group, kWalkThreads / G groups per block.
+// Init tiles: the same shape over the n_live prior draws.
+void build_classes(ggns_ctx *c) {
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;   // (prec, C, kind) -> runs
+    std::vector<int> mfma_runs;
+    for (int r = 0; r < (int)c->plan.runs.size(); ++r) {
+        const RunDev &R = c->plan.runs[r];
+        if (R.prec == GGNS_FP32_BF16MMA)
+            mfma_runs.push_back(r);
+        else
+            groups[std::make_tuple(R.prec, R.C, R.kind)].push_back(r);
+        c->max_kd = std::max<int>(c->max_kd, R.n_kill * R.d);
+    }
+    c->tiles_host.clear();
+    auto add_tiles = [&](int r, int count, int per) {
+        for (int b = 0; b < count; b += per) {
+            Tile t;
+            t.run = r; t.m_begin = b; t.m_end = std::min(count, b + per); t.pad = 0;
+            c->tiles_host.push_back(t);
+        }
+    };
+    for (auto &kv : groups) {
+        Class w{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), false,
+                (int64_t)c->tiles_host.size(), 0, 0};
+        size_t lds = 0;
+        for (int r : kv.second) {
+            const RunDev &R = c->plan.runs[r];
+            add_tiles(r, R.n_kill, kWalkThreads / R.G);
+            size_t need = (size_t)((R.nprm_bytes_lds + 15) & ~15);
+            if (R.kind == GGNS_LIK_GAUSS_FULL)
+                need += (size_t)kWalkThreads * R.C * (R.prec == GGNS_FP64 ? 8 : 4);
+            lds = std::max(lds, need);
+        }
+        w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
+        w.lds = lds;
+        c->walk_classes.push_back(w);
+    }
+    for (auto &kv : groups) {
+        Class w{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), false,
+                (int64_t)c->tiles_host.size(), 0, 0};
+        w.lds = (size_t)kWalkThreads * w.C * (w.prec == GGNS_FP64 ? 8 : 4);
+        for (int r : kv.second) add_tiles(r, c->plan.runs[r].n_live, kWalkThreads / c->plan.runs[r].G);
+        w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
+        c->init_classes.push_back(w);
+    }
+    if (!mfma_runs.empty()) {
+        Class w{GGNS_FP32_BF16MMA, 0, GGNS_LIK_GAUSS_FULL, true, (int64_t)c->tiles_host.size(), 0, 0};
+        for (int r : mfma_runs) add_tiles(r, c->plan.runs[r].n_kill, 16);
+        w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
+        c->walk_classes.push_back(w);
+        // prior draws of MMA runs on the FP32 vector path (one class per C)
+        for (int r : mfma_runs) {
+            Class i{GGNS_FP32, c->plan.runs[r].C, GGNS_LIK_GAUSS_FULL, false,
+                    (int64_t)c->tiles_host.size(), 0, 0};
+            add_tiles(r, c->plan.runs[r].n_live, kWalkThreads / c->plan.runs[r].G);
+            i.n_tiles = (int)(c->tiles_host.size() - i.tile_off);
+            c->init_classes.push_back(i);
+        }
+    }
+}
+
+int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const double *params_dev,
+           int64_t n_params, void *arena, int64_t arena_bytes, void *stream, bool fresh) {
+    if (out == nullptr || arena == nullptr || params_dev == nullptr) return GGNS_EINVAL;
+    *out = nullptr;
+    ggns_ctx *c = new ggns_ctx();
+    int rc = make_plan(runs, n_runs, c->plan);
+    if (rc != GGNS_OK) { delete c; return rc; }
+    if (arena_bytes < c->plan.total || (reinterpret_cast<uintptr_t>(arena) % kAlign) != 0) {
+        delete c;
+        return GGNS_EINVAL;
+    }
+    for (int r = 0; r < n_runs; ++r) {
+        if (runs[r].param_offset + raw_params(runs[r]) > n_params) { delete c; return GGNS_EINVAL; }
+    }
+    c->descs.assign(runs, runs + n_runs);
+    c->arena = arena;
+    c->arena_bytes = arena_bytes;
+    c->params = params_dev;
+    c->n_params = n_params;
+    build_classes(c);
+    for (const Class &w : c->walk_classes)
+        if (w.mfma && launch_walk_mfma(nullptr, nullptr, nullptr, 0, 0, nullptr) == GGNS_EUNSUPPORTED) {
+            delete c;
+            return GGNS_EUNSUPPORTED;
+        }
+    // MMA runs convert P to FP32 too: their prior draws and the stand-alone
+    // likelihood use the FP32 vector path
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    c->acc_host.resize(n_runs);
+    if (hipMemcpyAsync(c->runs_dev(), c->plan.runs.data(), sizeof(RunDev) * n_runs,
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->tiles_dev(), c->tiles_host.data(), sizeof(Tile) * c->tiles_host.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess) {
+        delete c;
+        return GGNS_EHIP;
+    }
+    launch_prepare(arena, c->runs_dev(), n_runs, params_dev, s, fresh ? 1 : 0);
+    if (hipGetLastError() != hipSuccess) { delete c; return GGNS_EHIP; }
+    if (fresh) {
+        for (const Class &w : c->init_classes) {
+            rc = launch_init_class(arena, c->runs_dev(), c->tiles_dev() + w.tile_off, w.n_tiles,
+                                   w.prec == GGNS_FP64 ? GGNS_FP64 : GGNS_FP32, w.C, w.kind, s);
+            if (rc != GGNS_OK) { delete c; return rc; }
+        }
+    }
+    *out = c;
+    return GGNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ggns_arena_bytes(const ggns_run_desc *runs, int32_t n_runs) {
+    Plan P;
+    const int rc = make_plan(runs, n_runs, P);
+    return rc == GGNS_OK ? P.total : (int64_t)rc;
+}
+
+int ggns_init(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const double *params_dev,
+              int64_t n_params, void *arena_dev, int64_t arena_bytes, void *stream) {
+    return create(out, runs, n_runs, params_dev, n_params, arena_dev, arena_bytes, stream, true);
+}
+
+int ggns_attach(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const double *params_dev,
+                int64_t n_params, void *arena_dev, int64_t arena_bytes, void *stream) {
+    return create(out, runs, n_runs, params_dev, n_params, arena_dev, arena_bytes, stream, false);
+}
+
+int ggns_evidence_update(ggns_ctx *ctx, int32_t final_sweep, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    launch_evidence(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), final_sweep ? 1 : 0,
+                    reinterpret_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (const Class &w : ctx->walk_classes) {
+        int rc;
+        if (w.mfma)
+            rc = launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
+                                  w.n_tiles, 0, s);
+        else
+            rc = launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
+                                   w.n_tiles, w.prec, w.C, w.kind, w.lds, s);
+        if (rc != GGNS_OK) return rc;
+    }
+    return GGNS_OK;
+}
+
+int ggns_replace_dead(ggns_ctx *ctx, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    launch_replace(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), ctx->max_kd,
+                   reinterpret_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+int ggns_loglike_grad(ggns_ctx *ctx, int32_t run, const void *x_dev, int64_t n, double *logl_dev,
+                      void *grad_dev, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size() || n < 0 || (n > 0 && x_dev == nullptr))
+        return GGNS_EINVAL;
+    if (n == 0) return GGNS_OK;
+    return launch_loglike(ctx->arena, ctx->runs_dev() + run, ctx->plan.runs[run], x_dev, n,
+                          logl_dev, grad_dev, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+int ggns_loglike_vjp(ggns_ctx *ctx, int32_t run, const void *x_dev, int64_t n,
+                     const double *gout_dev, void *gx_dev, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size() || n < 0 ||
+        (n > 0 && (x_dev == nullptr || gout_dev == nullptr || gx_dev == nullptr)))
+        return GGNS_EINVAL;
+    if (n == 0) return GGNS_OK;
+    return launch_loglike(ctx->arena, ctx->runs_dev() + run, ctx->plan.runs[run], x_dev, n,
+                          nullptr, gx_dev, gout_dev, reinterpret_cast<hipStream_t>(stream));
+}
+
+int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size() || out == nullptr) return GGNS_EINVAL;
+    const RunDev &R = ctx->plan.runs[run];
+    out->live_x = R.off_live_x;
+    out->live_logl = R.off_live_logl;
+    out->killed = R.off_killed;
+    out->survivors = R.off_surv;
+    out->start = R.off_start;
+    out->walk_x = R.off_walk_x;
+    out->walk_logl = R.off_walk_logl;
+    out->dead_logl = R.off_dead_logl;
+    out->dead_logw = R.off_dead_logw;
+    out->dead_cap = R.dead_cap;
+    out->elem_bytes = (R.prec == GGNS_FP64) ? 8 : 4;
+    out->reserved = 0;
+    return GGNS_OK;
+}
+
+int ggns_read_stats(ggns_ctx *ctx, ggns_run_stats *out, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (out == nullptr) return GGNS_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int n = (int)ctx->plan.runs.size();
+    for (int r = 0; r < n; ++r) {
+        if (hipMemcpyAsync(&ctx->acc_host[r], at<Acc>(ctx->arena, ctx->plan.runs[r].off_acc),
+                           sizeof(Acc), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return GGNS_EHIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return GGNS_EHIP;
+    for (int r = 0; r < n; ++r) {
+        const Acc &a = ctx->acc_host[r];
+        ggns_run_stats &o = out[r];
+        o.log_z = a.log_z; o.log_x = a.log_x; o.log_z2 = a.log_z2; o.dt = a.dt; o.lstar = a.lstar;
+        o.log_xl_max = a.log_xl_max; o.h = a.h; o.sigma_kl = a.sigma_kl; o.sigma_mom = a.sigma_mom;
+        o.iter = a.iter; o.evals = a.evals; o.n_dead = a.n_dead; o.steps_out = a.steps_out;
+        o.steps_in = a.steps_in; o.prunes = a.prunes; o.nosave = a.nosave;
+        o.it_outs = (int64_t)a.it_outs; o.it_steps = (int64_t)a.it_steps;
+        o.state = a.state; o.reserved = 0;
+    }
+    return GGNS_OK;
+}
+
+int ggns_write_vars(ggns_ctx *ctx, int32_t run, const ggns_run_vars *v, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size() || v == nullptr) return GGNS_EINVAL;
+    launch_set_vars(ctx->arena, ctx->runs_dev() + run, v->log_z, v->log_x, v->dt, (long long)v->iter,
+                    reinterpret_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl,
+                   int32_t *trace_out, int32_t trace_steps) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size() || trace_steps < 0) return GGNS_EINVAL;
+    if (trace_x != nullptr && (trace_logl == nullptr || trace_out == nullptr)) return GGNS_EINVAL;
+    if (trace_x != nullptr && ctx->plan.runs[run].prec == GGNS_FP32_BF16MMA) return GGNS_EUNSUPPORTED;
+    RunDev &R = ctx->plan.runs[run];
+    R.trace_x = trace_x;
+    R.trace_logl = trace_x ? trace_logl : nullptr;
+    R.trace_out = trace_x ? trace_out : nullptr;
+    R.trace_steps = trace_x ? trace_steps : 0;
+    if (hipMemcpy(ctx->runs_dev() + run, &R, sizeof(RunDev), hipMemcpyHostToDevice) != hipSuccess)
+        return GGNS_EHIP;
+    return GGNS_OK;
+}
+
+int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
+                    int32_t *lanes_per_walker) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size()) return GGNS_EINVAL;
+    if (coords_per_lane) *coords_per_lane = ctx->plan.runs[run].C;
+    if (lanes_per_walker) *lanes_per_walker = ctx->plan.runs[run].G;
+    return GGNS_OK;
+}
+
+void ggns_free(ggns_ctx *ctx) { delete ctx; }
+
+const char *ggns_status_string(int code) {
+    switch (code) {
+        case GGNS_OK: return "ok";
+        case GGNS_EINVAL: return "invalid argument";
+        case GGNS_EHIP: return "HIP error";
+        case GGNS_EUNSUPPORTED: return "unsupported size or combination";
+        case GGNS_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

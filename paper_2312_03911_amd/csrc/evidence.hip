@@ -1,0 +1,350 @@
+// Termination test, kill, evidence and prior-volume bookkeeping, final sweep
+// and run summary; one workgroup of 1024 threads per run.
+//
+// Paper: Appendix A (Z = sum L_i w_i with w_i the prior-volume shell, X shrinks
+// by n/(n+1) per kill), Algorithm GGNS (kill n_kill points per iteration, the
+// X*L peak test, final sweep of the live points) and Eqs. (update0)-(update9)
+// for the moments.  Batch form used here: killing k of n points one by one
+// with n_p = n, n-1, ..., n-k+1 gives every killed point the same expected
+// shell Xbar/(n+1) and leaves Xbar (n+1-k)/(n+1) (the per-kill factors
+// telescope), so one iteration needs a sort, one log-sum-exp and one update.
+// The final sweep uses n_p = n, ..., 1, which gives every remaining point
+// Xbar/(n+1).  All of it is FP64.
+#include "ggns_device.h"
+
+namespace ggns {
+
+namespace {
+
+constexpr int kEvThreads = 1024;
+
+__device__ __forceinline__ unsigned long long order_key(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_value(unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// Running log-sum-exp accumulator: (m, s) represents m + log(s).
+__device__ __forceinline__ void lse_push(double v, double &m, double &s) {
+    if (v == -INFINITY) return;
+    if (v > m) {
+        s = (m == -INFINITY) ? 1.0 : s * exp(m - v) + 1.0;
+        m = v;
+    } else {
+        s += exp(v - m);
+    }
+}
+
+__device__ __forceinline__ double lae(double a, double b) {
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    const double m = a > b ? a : b;
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+// Block reductions over 1024 threads (16 waves).
+__device__ double block_max(double v, double *scratch) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    double r = scratch[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = scratch[i] > r ? scratch[i] : r;
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_sum(double v, double *scratch) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += scratch[i];
+    __syncthreads();
+    return r;
+}
+
+// log-sum-exp over the block of per-thread partial (max, sum exp(v - max)).
+__device__ double block_lse(double lmax_local, double sum_local, double *scratch) {
+    const double gmax = block_max(lmax_local, scratch);
+    if (gmax == -INFINITY) return -INFINITY;
+    const double part = (lmax_local == -INFINITY) ? 0.0 : sum_local * exp(lmax_local - gmax);
+    return gmax + log(block_sum(part, scratch));
+}
+
+// Exclusive scans over the block's 1024 per-thread values (Hillis-Steele in LDS).
+__device__ double block_exscan_sum(double v, double *buf) {
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const double a = (t >= o) ? buf[t - o] : 0.0;
+        __syncthreads();
+        buf[t] += a;
+        __syncthreads();
+    }
+    const double incl = buf[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__device__ double block_exscan_lae(double v, double *buf) {
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const double a = (t >= o) ? buf[t - o] : -INFINITY;
+        __syncthreads();
+        buf[t] = lae(buf[t], a);
+        __syncthreads();
+    }
+    const double r = (t > 0) ? buf[t - 1] : -INFINITY;
+    __syncthreads();
+    return r;
+}
+
+__device__ int block_exscan_int(int v, int *buf) {
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const int a = (t >= o) ? buf[t - o] : 0;
+        __syncthreads();
+        buf[t] += a;
+        __syncthreads();
+    }
+    const int incl = buf[t];
+    __syncthreads();
+    return incl - v;
+}
+
+// Live-point count n_p in force when dead record i was killed: iterations
+// killed k points each with n_p = n, ..., n-k+1; the final sweep n points with
+// n_p = n, ..., 1.
+__device__ __forceinline__ double n_p_of(long long i, long long n_batch, int n, int k) {
+    if (i < n_batch) return (double)(n - (int)(i % k));
+    return (double)(n - (int)(i - n_batch));
+}
+
+// Run summary over the whole dead sequence: information H, and the second
+// moment of Z from the single-cluster recursion (update0, update2, update3,
+// update5, update8) written as scans: with X_i = prod n_p/(n_p+1) and
+// Y_i = prod n_p/(n_p+2) before record i, ZX_i = X_i sum_{j<i} Y_j L_j /
+// ((n_j+2) X_j), and Z2 = sum_i 2 ZX_i L_i/(n_i+1) + 2 Y_i L_i^2 /
+// ((n_i+1)(n_i+2)).
+__device__ void run_summary(const RunDev &R, Acc *acc, const double *dl, const double *dw,
+                            long long N, long long n_batch, double *buf, double *scratch) {
+    const int n = R.n_live, k = R.n_kill;
+    const int T = blockDim.x, t = threadIdx.x;
+    const long long chunk = (N + T - 1) / T;
+    const long long i0 = (long long)t * chunk;
+    const long long i1 = (i0 + chunk < N) ? i0 + chunk : N;
+    const double lz = acc->log_z;
+
+    // H = sum p_i (log L_i - log Z), p_i = L_i w_i / Z
+    double hpart = 0.0;
+    for (long long i = i0; i < i1; ++i) {
+        const double lp = dl[i] + dw[i] - lz;
+        hpart += exp(lp) * (dl[i] - lz);
+    }
+    const double h = block_sum(hpart, scratch);
+
+    // prefix sums of log X and log Y
+    double sx = 0.0, sy = 0.0;
+    for (long long i = i0; i < i1; ++i) {
+        const double np = n_p_of(i, n_batch, n, k);
+        sx += log(np) - log(np + 1.0);
+        sy += log(np) - log(np + 2.0);
+    }
+    double lx = block_exscan_sum(sx, buf);
+    double ly = block_exscan_sum(sy, buf);
+    // local log-sum of c_j = Y_j L_j / ((n_j+2) X_j)
+    double cm = -INFINITY, cs = 0.0;
+    {
+        double x = lx, y = ly;
+        for (long long i = i0; i < i1; ++i) {
+            const double np = n_p_of(i, n_batch, n, k);
+            lse_push(y + dl[i] - log(np + 2.0) - x, cm, cs);
+            x += log(np) - log(np + 1.0);
+            y += log(np) - log(np + 2.0);
+        }
+    }
+    const double lc_local = (cm == -INFINITY) ? -INFINITY : cm + log(cs);
+    double lsum = block_exscan_lae(lc_local, buf);
+    // terms of Z2 and of the recursion's Z
+    double am = -INFINITY, as = 0.0, zm = -INFINITY, zs = 0.0;
+    {
+        double x = lx, y = ly, sc = lsum;
+        const double l2 = 0.69314718055994530942;
+        for (long long i = i0; i < i1; ++i) {
+            const double np = n_p_of(i, n_batch, n, k);
+            const double ln1 = log(np + 1.0), ln2 = log(np + 2.0);
+            lse_push(l2 + x + sc + dl[i] - ln1, am, as);
+            lse_push(l2 + y + 2.0 * dl[i] - ln1 - ln2, am, as);
+            lse_push(x + dl[i] - ln1, zm, zs);
+            sc = lae(sc, y + dl[i] - ln2 - x);
+            x += log(np) - ln1;
+            y += log(np) - ln2;
+        }
+    }
+    const double lz2 = block_lse(am, as, scratch);
+    const double lzr = block_lse(zm, zs, scratch);
+    if (t == 0) {
+        acc->h = h;
+        acc->sigma_kl = sqrt(h > 0.0 ? h / n : 0.0);
+        acc->log_z2 = lz2;
+        const double v = lz2 - 2.0 * lzr;
+        acc->sigma_mom = sqrt(v > 0.0 ? v : 0.0);
+    }
+}
+
+__global__ void __launch_bounds__(kEvThreads)
+evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
+    const RunDev &R = runs[blockIdx.x];
+    Acc *acc = at<Acc>(arena, R.off_acc);
+    if (acc->state != GGNS_RUN_ACTIVE) return;
+
+    __shared__ unsigned long long key[kMaxLive];
+    __shared__ int slot[kMaxLive];
+    __shared__ double scratch[32];
+    __shared__ int flags[2];
+
+    const int n = R.n_live, k = R.n_kill;
+    int NP = 1;
+    while (NP < n) NP <<= 1;
+    const double *ll = at<double>(arena, R.off_live_logl);
+    const int t = threadIdx.x, T = blockDim.x;
+
+    if (t == 0) flags[0] = 0;
+    __syncthreads();
+    double lmax = -INFINITY;
+    for (int i = t; i < NP; i += T) {
+        if (i < n) {
+            const double v = ll[i];
+            if (isnan(v)) flags[0] = 1;
+            lmax = v > lmax ? v : lmax;
+            key[i] = order_key(v);
+            slot[i] = i;
+        } else {
+            key[i] = ~0ull;
+            slot[i] = 0x7FFFFFFF;
+        }
+    }
+    lmax = block_max(lmax, scratch);   // contains the barriers
+    if (flags[0]) {
+        if (t == 0) acc->state = GGNS_RUN_NONFINITE;
+        return;
+    }
+    // termination test (reading: remaining-evidence or X*L peak)
+    if (t == 0) {
+        int stop = final_sweep ? GGNS_RUN_DONE : 0;
+        const double ltol = log(R.term_tol);
+        if (R.term_kind == GGNS_TERM_REMAINING_Z) {
+            if (acc->log_x + lmax < ltol + acc->log_z) stop = GGNS_RUN_DONE;
+        } else {
+            const double r = acc->log_x + lmax;
+            if (r > acc->log_xl_max) acc->log_xl_max = r;
+            if (acc->iter > 0 && r - acc->log_xl_max < ltol) stop = GGNS_RUN_DONE;
+        }
+        if (!stop && acc->iter >= R.max_iter) stop = GGNS_RUN_MAXITER;
+        flags[1] = stop;
+    }
+    // bitonic sort of (log L, slot) ascending
+    for (int size = 2; size <= NP; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = t; i < (NP >> 1); i += T) {
+                const int lo = 2 * stride * (i / stride) + (i % stride);
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const unsigned long long ka = key[lo], kb = key[hi];
+                const int sa = slot[lo], sb = slot[hi];
+                const bool greater = (ka > kb) || (ka == kb && sa > sb);
+                if (greater == asc) {
+                    key[lo] = kb; key[hi] = ka;
+                    slot[lo] = sb; slot[hi] = sa;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int stop = flags[1];
+    double *dead_l = at<double>(arena, R.off_dead_logl);
+    double *dead_w = at<double>(arena, R.off_dead_logw);
+    const long long nd = acc->n_dead;
+    const double lw = acc->log_x - log((double)n + 1.0);
+    const int nkill = stop ? n : k;
+
+    // dead records and the log-sum-exp of the killed log L
+    double m_loc = -INFINITY, s_loc = 0.0;
+    for (int j = t; j < nkill; j += T) {
+        const double v = key_value(key[j]);
+        if (nd + j < R.dead_cap) {
+            dead_l[nd + j] = v;
+            dead_w[nd + j] = lw;
+        }
+        lse_push(v, m_loc, s_loc);
+    }
+    const double lse = block_lse(m_loc, s_loc, scratch);
+    if (t == 0) {
+        acc->log_z = lae(acc->log_z, lse + lw);
+        acc->n_dead = nd + nkill;
+        if (stop) {
+            acc->log_x = lw;
+        } else {
+            acc->log_x += log((double)(n + 1 - k)) - log((double)n + 1.0);
+            acc->lstar = key_value(key[k - 1]);
+            acc->it_outs = 0ull;
+            acc->it_steps = 0ull;
+        }
+    }
+    if (stop) {
+        __syncthreads();
+        __threadfence_block();
+        const long long N = (nd + nkill < R.dead_cap) ? nd + nkill : R.dead_cap;
+        __shared__ double buf[kEvThreads];
+        run_summary(R, acc, dead_l, dead_w, N, nd, buf, scratch);
+        if (t == 0) acc->state = stop;
+        return;
+    }
+    // killed slots in kill order; survivors in ascending slot order
+    int32_t *killed = at<int32_t>(arena, R.off_killed);
+    int32_t *surv = at<int32_t>(arena, R.off_surv);
+    for (int j = t; j < k; j += T) killed[j] = slot[j];
+    __syncthreads();
+    // reuse slot[] as a dead flag per live slot (sorted order is no longer needed
+    // past this point except key[], which stays intact)
+    int *dead_flag = slot;
+    for (int i = t; i < NP; i += T) dead_flag[i] = 0;
+    __syncthreads();
+    for (int j = t; j < k; j += T) dead_flag[killed[j]] = 1;
+    __syncthreads();
+    // each thread owns a contiguous range of slots
+    const int per = (n + T - 1) / T;
+    const int s0 = t * per, s1 = (s0 + per < n) ? s0 + per : n;
+    int cnt = 0;
+    for (int i = s0; i < s1; ++i) cnt += dead_flag[i] ? 0 : 1;
+    __shared__ int ibuf[kEvThreads];
+    int pos = block_exscan_int(cnt, ibuf);
+    for (int i = s0; i < s1; ++i)
+        if (!dead_flag[i]) surv[pos++] = i;
+}
+
+}  // namespace
+
+void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_sweep,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(evidence_kernel, dim3(n_runs), dim3(kEvThreads), 0, s, arena, runs_dev,
+                       final_sweep);
+}
+
+}  // namespace ggns

@@ -1,0 +1,89 @@
+// Internal structures shared by the engine's host code and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ggns.h"
+
+namespace ggns {
+
+// Stream tags of the counter-based generator (word 3 of the counter holds
+// tag << 24 | sub).
+enum : uint32_t { TAG_INIT = 1, TAG_START = 2, TAG_P0 = 3, TAG_EPS = 4, TAG_RES = 5 };
+
+constexpr int kMaxD = 256;
+constexpr int kMaxLive = 4096;
+constexpr int kMaxComp = 8;
+constexpr int kWalkThreads = 256;
+
+// Read-only description of one run on the device: settings plus the byte
+// offsets of its arrays in the arena.
+struct RunDev {
+    int32_t d, n_live, n_kill, kind, prec, n_comp;
+    int32_t n_steps_max, min_ref, max_ref, prune_streak;
+    int32_t term_kind, max_iter;
+    int32_t C, G;              // walk tile: coordinates per lane, lanes per walker
+    int32_t nprm;              // elements of the converted parameter block
+    int32_t nprm_bytes_lds;    // bytes staged to LDS by the walk (0: read from global)
+    double lo, hi, dt_init, delta_p, out_hi, out_lo, dt_down, dt_up, term_tol;
+    uint64_t seed;
+    int64_t param_offset;
+    int64_t off_acc, off_prm, off_prm_bf16, off_live_x, off_live_logl, off_killed, off_surv,
+        off_start, off_walk_x, off_walk_logl, off_dead_logl, off_dead_logw;
+    int64_t dead_cap;
+    // per-run trace (parity tests); null when off
+    void *trace_x;
+    double *trace_logl;
+    int32_t *trace_out;
+    int32_t trace_steps, pad;
+};
+
+// Mutable per-run state on the device.
+struct Acc {
+    double log_z, log_x, log_z2, dt, lstar, log_xl_max, h, sigma_kl, sigma_mom;
+    long long iter, evals, n_dead, steps_out, steps_in, prunes, nosave;
+    unsigned long long it_outs, it_steps;
+    int32_t state, pad;
+};
+
+// A walk work item: walkers [m_begin, m_end) of one run.
+struct Tile {
+    int32_t run, m_begin, m_end, pad;
+};
+
+template <typename T>
+__host__ __device__ inline T *at(void *arena, int64_t off) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(arena) + off);
+}
+
+// Size in elements of the converted parameter block (run precision), without
+// the BF16 copy of P.
+inline int32_t converted_params(int kind, int d, int K) {
+    switch (kind) {
+        case GGNS_LIK_GAUSS_DIAG: return 2 * d + 1;             // mu, 1/sigma^2, const
+        case GGNS_LIK_GAUSS_FULL: return d + 1 + d * d;          // mu, const, P
+        case GGNS_LIK_SHELLS: return K * (d + 3);                // {c, r, 1/w^2, lognorm}
+        case GGNS_LIK_GMM_DIAG: return K * (2 * d + 1);          // {mu, 1/sigma^2, lognorm}
+    }
+    return 0;
+}
+
+// Launchers (defined in the .hip files).
+void launch_prepare(void *arena, const RunDev *runs_dev, int n_runs, const double *params,
+                    hipStream_t s, int init_state);
+int launch_init_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int prec,
+                      int C, int kind, hipStream_t s);
+void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_sweep,
+                     hipStream_t s);
+void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s);
+int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
+                      int prec, int C, int kind, size_t lds_bytes, hipStream_t s);
+int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
+                     int d_pad, hipStream_t s);
+int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, const void *x,
+                   int64_t n, double *logl, void *grad, const double *gout, hipStream_t s);
+void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
+                     long long iter, hipStream_t s);
+
+}  // namespace ggns

@@ -1,0 +1,305 @@
+// Run start (parameter conversion, prior draws, first log-likelihoods),
+// replacement of the killed points with dt adaptation, and the stand-alone
+// log-likelihood / adjoint kernels.
+#include "ggns_device.h"
+
+namespace ggns {
+
+namespace {
+
+constexpr double kLog2Pi = 1.83787706640934548356;
+
+// Converted parameters in the run's precision; constants in FP64 first.
+template <typename T>
+__device__ void convert_params(const RunDev &R, const double *raw, T *out) {
+    const int d = R.d, K = R.n_comp, t = threadIdx.x, nt = blockDim.x;
+    if (R.kind == GGNS_LIK_GAUSS_DIAG) {
+        const double *mu = raw, *sg = raw + d;
+        for (int a = t; a < d; a += nt) {
+            out[a] = (T)mu[a];
+            out[d + a] = (T)(1.0 / (sg[a] * sg[a]));
+        }
+        if (t == 0) {
+            double c = 0.0;
+            for (int a = 0; a < d; ++a) c += -0.5 * kLog2Pi - log(sg[a]);
+            out[2 * d] = (T)c;
+        }
+    } else if (R.kind == GGNS_LIK_GAUSS_FULL) {
+        for (int a = t; a < d; a += nt) out[a] = (T)raw[a];
+        for (int64_t e = t; e < (int64_t)d * d; e += nt) out[d + 1 + e] = (T)raw[d + e];
+        if (t == 0) out[d] = (T)(-0.5 * d * kLog2Pi + 0.5 * raw[d + (int64_t)d * d]);
+    } else if (R.kind == GGNS_LIK_SHELLS) {
+        for (int kk = 0; kk < K; ++kk) {
+            const double *blk = raw + kk * (d + 2);
+            T *o = out + kk * (d + 3);
+            for (int a = t; a < d; a += nt) o[a] = (T)blk[a];
+            if (t == 0) {
+                const double w = blk[d + 1];
+                o[d] = (T)blk[d];
+                o[d + 1] = (T)(1.0 / (w * w));
+                o[d + 2] = (T)(-0.5 * kLog2Pi - log(w));
+            }
+        }
+    } else {
+        for (int kk = 0; kk < K; ++kk) {
+            const double *mu = raw + kk * 2 * d, *sg = mu + d;
+            T *o = out + kk * (2 * d + 1);
+            for (int a = t; a < d; a += nt) {
+                o[a] = (T)mu[a];
+                o[d + a] = (T)(1.0 / (sg[a] * sg[a]));
+            }
+            if (t == 0) {
+                double c = -log((double)K);
+                for (int a = 0; a < d; ++a) c += -0.5 * kLog2Pi - log(sg[a]);
+                o[2 * d] = (T)c;
+            }
+        }
+    }
+}
+
+__global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, const double *params,
+                               int init_state) {
+    const RunDev &R = runs[blockIdx.x];
+    const double *raw = params + R.param_offset;
+    if (R.prec == GGNS_FP64)
+        convert_params<double>(R, raw, at<double>(arena, R.off_prm));
+    else
+        convert_params<float>(R, raw, at<float>(arena, R.off_prm));
+    if (R.prec == GGNS_FP32_BF16MMA && R.off_prm_bf16 >= 0) {
+        // P rounded to BF16 (round to nearest even, via FP32), stored row-major
+        // [d_pad][d_pad] with zero padding; the MMA walk stages it into LDS.
+        const int d = R.d, dp = (d + 31) & ~31;
+        uint16_t *pb = at<uint16_t>(arena, R.off_prm_bf16);
+        const double *P = raw + d;
+        for (int64_t e = threadIdx.x; e < (int64_t)dp * dp; e += blockDim.x) {
+            const int i = (int)(e / dp), j = (int)(e % dp);
+            float f = (i < d && j < d) ? (float)P[(int64_t)i * d + j] : 0.0f;
+            uint32_t b = __float_as_uint(f);
+            b += 0x7FFFu + ((b >> 16) & 1u);
+            pb[e] = (uint16_t)(b >> 16);
+        }
+    }
+    if (init_state && threadIdx.x == 0) {
+        Acc *acc = at<Acc>(arena, R.off_acc);
+        acc->log_z = -INFINITY;
+        acc->log_x = 0.0;
+        acc->log_z2 = -INFINITY;
+        acc->dt = R.dt_init * (R.hi - R.lo);
+        acc->lstar = -INFINITY;
+        acc->log_xl_max = -INFINITY;
+        acc->h = acc->sigma_kl = acc->sigma_mom = 0.0;
+        acc->iter = 0;
+        acc->evals = R.n_live;
+        acc->n_dead = 0;
+        acc->steps_out = acc->steps_in = acc->prunes = acc->nosave = 0;
+        acc->it_outs = acc->it_steps = 0ull;
+        acc->state = GGNS_RUN_ACTIVE;
+    }
+}
+
+// Prior draws: coordinate a of point i is lo + (hi - lo) u with u the 24-bit
+// open uniform of word (a & 3) of the INIT stream block (a >> 2); then the
+// log-likelihood of the point.  Lane-group layout as in the walk.
+template <typename T, int C, int KIND>
+__global__ void __launch_bounds__(kWalkThreads)
+init_points_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles) {
+    const Tile tile = tiles[blockIdx.x];
+    const RunDev &R = runs[tile.run];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int d = R.d, G = R.G;
+    const int lane = threadIdx.x & 63, gl = lane & (G - 1), grp = threadIdx.x / G;
+    const int a0 = gl * C;
+    const int i = tile.m_begin + grp;
+    const bool valid = i < tile.m_end;
+    T *xch = reinterpret_cast<T *>(smem) + grp * (G * C);
+    const T *prm = at<T>(arena, R.off_prm);
+    const double w = R.hi - R.lo;
+    T x[C], g[C];
+    uint32_t u[4];
+    int last_b = -1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int a = a0 + c;
+        x[c] = T(0);
+        if (a < d && valid) {
+            if ((a >> 2) != last_b) {
+                last_b = a >> 2;
+                draw4(R.seed, (uint32_t)last_b, (uint32_t)i, 0u, TAG_INIT, 0u, u);
+            }
+            const uint32_t word = (a & 3) == 0 ? u[0] : ((a & 3) == 1 ? u[1] : ((a & 3) == 2 ? u[2] : u[3]));
+            x[c] = (T)(R.lo + w * u24_open(word));
+        }
+    }
+    const T l = lik_eval<T, C, KIND>(R.n_comp, prm, d, a0, G, x, g, xch);
+    if (valid) {
+        T *xo = at<T>(arena, R.off_live_x) + (int64_t)i * d;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (a0 + c < d) xo[a0 + c] = x[c];
+        if (gl == 0) at<double>(arena, R.off_live_logl)[i] = (double)l;
+    }
+}
+
+// Walker outputs into the killed slots; dt update from out_frac; next iteration.
+template <typename T>
+__device__ void scatter_points(void *arena, const RunDev &R, int64_t e0, int64_t stride) {
+    const int d = R.d, k = R.n_kill;
+    const int32_t *killed = at<int32_t>(arena, R.off_killed);
+    const T *wx = at<T>(arena, R.off_walk_x);
+    T *lx = at<T>(arena, R.off_live_x);
+    for (int64_t e = e0; e < (int64_t)k * d; e += stride) {
+        const int m = (int)(e / d), a = (int)(e % d);
+        lx[(int64_t)killed[m] * d + a] = wx[e];
+    }
+}
+
+__global__ void replace_kernel(void *arena, const RunDev *__restrict__ runs) {
+    const RunDev &R = runs[blockIdx.y];
+    Acc *acc = at<Acc>(arena, R.off_acc);
+    if (acc->state != GGNS_RUN_ACTIVE) return;
+    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (R.prec == GGNS_FP64)
+        scatter_points<double>(arena, R, e0, stride);
+    else
+        scatter_points<float>(arena, R, e0, stride);
+    const int32_t *killed = at<int32_t>(arena, R.off_killed);
+    const double *wl = at<double>(arena, R.off_walk_logl);
+    double *ll = at<double>(arena, R.off_live_logl);
+    for (int64_t m = e0; m < R.n_kill; m += stride) ll[killed[m]] = wl[m];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long st = acc->it_steps;
+        if (st > 0) {
+            const double out_frac = (double)acc->it_outs / (double)st;
+            if (out_frac > R.out_hi)
+                acc->dt *= R.dt_down;
+            else if (out_frac < R.out_lo)
+                acc->dt *= R.dt_up;
+        }
+        acc->iter += 1;
+    }
+}
+
+// Stand-alone log L, score or adjoint at caller-provided points.
+template <typename T, int C, int KIND>
+__global__ void __launch_bounds__(kWalkThreads)
+loglike_kernel(void *arena, const RunDev *__restrict__ run, const T *__restrict__ xs, int64_t n,
+               double *logl, T *grad, const double *gout) {
+    const RunDev &R = *run;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int d = R.d, G = R.G;
+    const int lane = threadIdx.x & 63, gl = lane & (G - 1), grp = threadIdx.x / G;
+    const int a0 = gl * C;
+    const int ngroups = blockDim.x / G;
+    const int64_t i = (int64_t)blockIdx.x * ngroups + grp;
+    const bool valid = i < n;
+    T *xch = reinterpret_cast<T *>(smem) + grp * (G * C);
+    const T *prm = at<T>(arena, R.off_prm);
+    T x[C], g[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = (valid && a0 + c < d) ? xs[i * d + a0 + c] : T(0);
+    const T l = lik_eval<T, C, KIND>(R.n_comp, prm, d, a0, G, x, g, xch);
+    if (!valid) return;
+    if (logl != nullptr && gl == 0) logl[i] = (double)l;
+    if (grad != nullptr) {
+        const T s = (gout != nullptr) ? (T)gout[i] : T(1);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (a0 + c < d) grad[i * d + a0 + c] = s * g[c];
+    }
+}
+
+__global__ void set_vars_kernel(void *arena, const RunDev *__restrict__ run, double log_z,
+                                double log_x, double dt, long long iter) {
+    Acc *acc = at<Acc>(arena, run->off_acc);
+    acc->log_z = log_z;
+    acc->log_x = log_x;
+    acc->dt = dt;
+    acc->iter = iter;
+}
+
+template <typename T, int C>
+hipError_t init_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles, int kind,
+                  size_t lds, hipStream_t s) {
+    GGNS_DISPATCH_KIND(kind, hipLaunchKernelGGL((init_points_kernel<T, C, KIND_>), dim3(n_tiles),
+                                                dim3(kWalkThreads), lds, s, arena, runs, tiles));
+    return hipGetLastError();
+}
+
+template <typename T, int C>
+hipError_t loglike_t(void *arena, const RunDev *run, const void *x, int64_t n, double *logl,
+                     void *grad, const double *gout, int G, int kind, hipStream_t s) {
+    const int ngroups = kWalkThreads / G;
+    const int64_t blocks = (n + ngroups - 1) / ngroups;
+    const size_t lds = (size_t)kWalkThreads * C * sizeof(T);
+    GGNS_DISPATCH_KIND(kind, hipLaunchKernelGGL((loglike_kernel<T, C, KIND_>), dim3((unsigned)blocks),
+                                                dim3(kWalkThreads), lds, s, arena, run,
+                                                reinterpret_cast<const T *>(x), n, logl,
+                                                reinterpret_cast<T *>(grad), gout));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void launch_prepare(void *arena, const RunDev *runs_dev, int n_runs, const double *params,
+                    hipStream_t s, int init_state) {
+    hipLaunchKernelGGL(prepare_kernel, dim3(n_runs), dim3(256), 0, s, arena, runs_dev, params,
+                       init_state);
+}
+
+int launch_init_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int prec,
+                      int C, int kind, hipStream_t s) {
+    hipError_t e = hipErrorInvalidValue;
+    const size_t lds = (size_t)kWalkThreads * C * (prec == GGNS_FP64 ? 8 : 4);
+    if (prec == GGNS_FP64) {
+        switch (C) {
+            case 1: e = init_t<double, 1>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 2: e = init_t<double, 2>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 4: e = init_t<double, 4>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+        }
+    } else {
+        switch (C) {
+            case 1: e = init_t<float, 1>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 2: e = init_t<float, 2>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 4: e = init_t<float, 4>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 8: e = init_t<float, 8>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+        }
+    }
+    return e == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s) {
+    int bx = (max_kd + 1023) / 1024;
+    if (bx < 1) bx = 1;
+    if (bx > 64) bx = 64;
+    hipLaunchKernelGGL(replace_kernel, dim3(bx, n_runs), dim3(256), 0, s, arena, runs_dev);
+}
+
+int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, const void *x,
+                   int64_t n, double *logl, void *grad, const double *gout, hipStream_t s) {
+    hipError_t e = hipErrorInvalidValue;
+    const int C = run_host.C, G = run_host.G;
+    if (run_host.prec == GGNS_FP64) {
+        switch (C) {
+            case 1: e = loglike_t<double, 1>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+            case 2: e = loglike_t<double, 2>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+            case 4: e = loglike_t<double, 4>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+        }
+    } else {
+        switch (C) {
+            case 1: e = loglike_t<float, 1>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+            case 2: e = loglike_t<float, 2>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+            case 4: e = loglike_t<float, 4>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+            case 8: e = loglike_t<float, 8>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+        }
+    }
+    return e == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
+                     long long iter, hipStream_t s) {
+    hipLaunchKernelGGL(set_vars_kernel, dim3(1), dim3(1), 0, s, arena, run_dev, log_z, log_x, dt,
+                       iter);
+}
+
+}  // namespace ggns

@@ -1,0 +1,315 @@
+// The batched Hamiltonian slice sampling walk on the vector ALUs.
+//
+// Paper: Algorithm GGNS HSS (drift x += p dt, log L and its gradient, outside
+// mask, reflection p -= 2 (p.n) n with n the unit score (Eq. reflection),
+// momentum noise p *= 1 + delta_p eps, reflection count, kept in-slice points,
+// out_frac) and Section 3 (trajectory preservation, pruning, parallel
+// evolution of the killed points).  Readings: the walker stops at max_ref
+// reflections (or runs n_steps_max steps when max_ref == 0); the prior box
+// counts as outside and flips the violated momentum components; a zero or
+// non-finite score reflects p -> -p; a walker keeps its in-slice points once it
+// has min_ref reflections and returns a uniform pick through a size-one
+// reservoir, else its last in-slice point, else its start; prune_streak outside
+// steps in a row reset it to its start with fresh momentum.
+//
+// Layout: one walker per group of G lanes (G = 1..64, power of two), lane g
+// owning C consecutive coordinates [g*C, g*C + C) of x, p and the score in
+// registers for the whole walk.  Dot products (p.g, g.g) and the likelihood's
+// sums are xor-butterfly reductions inside the group.  The run's converted
+// parameters are staged in LDS once per block.  The only HBM traffic of a walk
+// is the gather of the start point and the reservoir writes.
+#include "ggns_device.h"
+
+namespace ggns {
+
+namespace {
+
+__device__ __forceinline__ float pick4(const float (&z)[4], int i) {
+    return i == 0 ? z[0] : (i == 1 ? z[1] : (i == 2 ? z[2] : z[3]));
+}
+__device__ __forceinline__ double pick4(const double (&z)[4], int i) {
+    return i == 0 ? z[0] : (i == 1 ? z[1] : (i == 2 ? z[2] : z[3]));
+}
+
+// Four normals from four stream words.
+template <typename T>
+__device__ __forceinline__ void normals4(const uint32_t (&w)[4], T (&z)[4]) {
+    normals2(w[0], w[1], z[0], z[1]);
+    normals2(w[2], w[3], z[2], z[3]);
+}
+
+// d standard normals of walker `m` from the counter-based stream (initial and
+// pruning momenta); this lane computes its own coordinates.
+template <typename T, int C>
+__device__ __forceinline__ void momentum_draw(uint64_t seed, uint32_t m, uint32_t it, uint32_t sub,
+                                              int a0, int d, T (&p)[C]) {
+    constexpr int NB = (C + 3) / 4;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = (a0 >> 2) + i;
+        uint32_t w[4];
+        draw4(seed, (uint32_t)b, m, it, TAG_P0, sub, w);
+        T z[4];
+        normals4(w, z);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int a = a0 + c;
+            if ((a >> 2) == b) p[c] = (a < d) ? pick4(z, a & 3) : T(0);
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T, int C, int KIND>
+__global__ void __launch_bounds__(kWalkThreads)
+walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles) {
+    constexpr int NB = (C + 3) / 4;
+    const Tile tile = tiles[blockIdx.x];
+    const RunDev &R = runs[tile.run];
+    Acc *acc = at<Acc>(arena, R.off_acc);
+    if (acc->state != GGNS_RUN_ACTIVE) return;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int next_walker;
+    __shared__ unsigned long long blk_cnt[4];
+
+    const int d = R.d, G = R.G, K = R.n_comp;
+    const int ngroups = blockDim.x / G;
+    const T *prm = at<T>(arena, R.off_prm);
+    if (R.nprm_bytes_lds > 0) {
+        T *sp = reinterpret_cast<T *>(smem);
+        for (int i = threadIdx.x; i < R.nprm; i += blockDim.x) sp[i] = prm[i];
+        prm = sp;
+    }
+    T *xch_all = reinterpret_cast<T *>(smem + ((R.nprm_bytes_lds + 15) & ~15));
+    if (threadIdx.x == 0) {
+        next_walker = tile.m_begin + ngroups;
+        blk_cnt[0] = blk_cnt[1] = blk_cnt[2] = blk_cnt[3] = 0ull;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int gbase = lane & ~(G - 1);
+    const int a0 = gl * C;
+    T *xch = xch_all + grp * (G * C);
+
+    const double lstar = acc->lstar;
+    const T dt = (T)acc->dt;
+    const uint32_t it = (uint32_t)acc->iter;
+    const T lo = (T)R.lo, hi = (T)R.hi, dp = (T)R.delta_p;
+    const uint64_t seed = R.seed;
+    const int nsurv = R.n_live - R.n_kill;
+    const int32_t *surv = at<int32_t>(arena, R.off_surv);
+    int32_t *start_arr = at<int32_t>(arena, R.off_start);
+    const T *live_x = at<T>(arena, R.off_live_x);
+    const double *live_logl = at<double>(arena, R.off_live_logl);
+    T *walk_x = at<T>(arena, R.off_walk_x);
+    double *walk_logl = at<double>(arena, R.off_walk_logl);
+    T *trace_x = reinterpret_cast<T *>(R.trace_x);
+    const int k = R.n_kill;
+
+    T x[C], p[C], g[C];
+    Xoshiro eps[NB];
+    Xoshiro res;
+    int m = tile.m_begin + grp;
+    bool active = m < tile.m_end;
+    int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0;
+    double out_l = 0.0;
+    unsigned long long c_outs = 0, c_steps = 0, c_prunes = 0, c_nosave = 0;
+
+    auto start_walker = [&](int mm) {
+        uint32_t w[4];
+        draw4(seed, 0u, (uint32_t)mm, it, TAG_START, 0u, w);
+        s = surv[(int)(((uint64_t)w[0] * (uint64_t)nsurv) >> 32)];
+        if (gl == 0) start_arr[mm] = s;
+        const T *xs = live_x + (int64_t)s * d;
+        T *wo = walk_x + (int64_t)mm * d;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int a = a0 + c;
+            x[c] = (a < d) ? xs[a] : T(0);
+            if (a < d) wo[a] = x[c];
+        }
+        out_l = live_logl[s];
+        momentum_draw<T, C>(seed, (uint32_t)mm, it, 0u, a0, d, p);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            draw4(seed, (uint32_t)((a0 >> 2) + i), (uint32_t)mm, it, TAG_EPS, 0u, w);
+            eps[i].seed(w);
+        }
+        draw4(seed, 0u, (uint32_t)mm, it, TAG_RES, 0u, w);
+        res.seed(w);
+        nref = streak = steps = outs = nprune = nsave = 0;
+    };
+
+    if (active) start_walker(m);
+
+    while (__any(active)) {
+        // drift (Algorithm GGNS HSS: x += p dt)
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = x[c] + dt * p[c];
+        // log L and the score at the new position
+        const T l = lik_eval<T, C, KIND>(K, prm, d, a0, G, x, g, xch);
+        // outside the slice: out of the prior box, or log L <= L* (compared in FP64)
+        bool vm[C];
+        bool vany = false;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            vm[c] = (a0 + c < d) && (x[c] < lo || x[c] > hi);
+            vany = vany || vm[c];
+        }
+        const bool viol = group_any(vany, G);
+        const bool out = viol || ((double)l <= lstar);
+        if (active && trace_x != nullptr && steps < R.trace_steps) {
+            const int64_t row = (int64_t)steps * k + m;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (a0 + c < d) trace_x[row * d + a0 + c] = x[c];
+            if (gl == 0) {
+                R.trace_logl[row] = (double)l;
+                R.trace_out[row] = out ? 1 : 0;
+            }
+        }
+        steps += 1;
+        // reflection (Eq. reflection with n = g / |g|; box faces flip their axis)
+        T pg = T(0), gg = T(0);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            pg += p[c] * g[c];
+            gg += g[c] * g[c];
+        }
+        pg = group_sum(pg, G);
+        gg = group_sum(gg, G);
+        if (out) {
+            if (viol) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) p[c] = vm[c] ? -p[c] : p[c];
+            } else if (isfinite(gg) && gg > T(0)) {
+                const T f = T(2) * pg / gg;
+#pragma unroll
+                for (int c = 0; c < C; ++c) p[c] = p[c] - f * g[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c) p[c] = -p[c];
+            }
+        }
+        // momentum noise, componentwise: p *= 1 + delta_p * eps
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            uint32_t w[4];
+            w[0] = eps[i].next();
+            w[1] = eps[i].next();
+            w[2] = eps[i].next();
+            w[3] = eps[i].next();
+            T z[4];
+            normals4(w, z);
+            const int b = (a0 >> 2) + i;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int a = a0 + c;
+                if ((a >> 2) == b) p[c] = p[c] * (T(1) + dp * pick4(z, a & 3));
+            }
+        }
+        const uint32_t ures = res.next();
+        nref += out ? 1 : 0;
+        outs += out ? 1 : 0;
+        streak = out ? streak + 1 : 0;
+        // trajectory preservation: size-one reservoir over the kept points
+        if (!out) {
+            bool take;
+            if (nref >= R.min_ref) {
+                nsave += 1;
+                take = (uint64_t)ures * (uint64_t)nsave < (1ull << 32);
+            } else {
+                take = (nsave == 0);
+            }
+            if (take && active) {
+                T *wo = walk_x + (int64_t)m * d;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (a0 + c < d) wo[a0 + c] = x[c];
+                out_l = (double)l;
+            }
+        }
+        // pruning: back to the start with fresh momentum
+        if (R.prune_streak > 0 && streak >= R.prune_streak) {
+            if (active) {
+                const T *xs = live_x + (int64_t)s * d;
+#pragma unroll
+                for (int c = 0; c < C; ++c) x[c] = (a0 + c < d) ? xs[a0 + c] : T(0);
+            }
+            nprune += 1;
+            momentum_draw<T, C>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
+            nref = 0;
+            streak = 0;
+        }
+        const bool done = !(steps < R.n_steps_max && (R.max_ref == 0 || nref < R.max_ref));
+        const bool need = active && done;
+        if (need && gl == 0) {
+            walk_logl[m] = out_l;
+            c_outs += outs;
+            c_steps += steps;
+            c_prunes += nprune;
+            c_nosave += (nsave == 0) ? 1 : 0;
+        }
+        // the group takes the next walker of the tile
+        int nm = 0;
+        if (need && gl == 0) nm = atomicAdd(&next_walker, 1);
+        nm = __shfl(nm, gbase, 64);
+        if (need) {
+            m = nm;
+            active = m < tile.m_end;
+            if (active) start_walker(m);
+        }
+    }
+
+    if (gl == 0 && c_steps > 0) {
+        atomicAdd(&blk_cnt[0], c_outs);
+        atomicAdd(&blk_cnt[1], c_steps);
+        atomicAdd(&blk_cnt[2], c_prunes);
+        atomicAdd(&blk_cnt[3], c_nosave);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && blk_cnt[1] > 0) {
+        atomicAdd(&acc->it_outs, blk_cnt[0]);
+        atomicAdd(&acc->it_steps, blk_cnt[1]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_out), blk_cnt[0]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_in), blk_cnt[1] - blk_cnt[0]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->evals), blk_cnt[1]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->prunes), blk_cnt[2]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->nosave), blk_cnt[3]);
+    }
+}
+
+template <typename T, int C>
+static hipError_t launch_walk_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
+                                int kind, size_t lds, hipStream_t s) {
+    GGNS_DISPATCH_KIND(kind, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_>), dim3(n_tiles),
+                                                dim3(kWalkThreads), lds, s, arena, runs, tiles));
+    return hipGetLastError();
+}
+
+int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int prec,
+                      int C, int kind, size_t lds, hipStream_t s) {
+    hipError_t e = hipErrorInvalidValue;
+    if (prec == GGNS_FP64) {
+        switch (C) {
+            case 1: e = launch_walk_t<double, 1>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 2: e = launch_walk_t<double, 2>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 4: e = launch_walk_t<double, 4>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+        }
+    } else {
+        switch (C) {
+            case 1: e = launch_walk_t<float, 1>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 2: e = launch_walk_t<float, 2>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 4: e = launch_walk_t<float, 4>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 8: e = launch_walk_t<float, 8>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+        }
+    }
+    return e == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+}  // namespace ggns

@@ -1,0 +1,258 @@
+"""Device-memory plumbing and the run loop on top of the C ABI.
+
+PyTorch provides the device memory (one arena tensor per engine, one FP64
+parameter tensor) and the stream; every step of the sampler runs in the HIP
+kernels of libggns.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from .inputs import RunConfig
+
+_TERM = {0: 0, 1: 1}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Engine:
+    """Many independent nested-sampling runs advanced together.
+
+    One iteration = ggns_evidence_update -> ggns_hss_walk -> ggns_replace_dead
+    for every active run; `run()` repeats it (optionally as a captured HIP
+    graph of `graph_iters` iterations) until every run has stopped.
+    """
+
+    def __init__(self, configs: Sequence[RunConfig], device: str = "cuda",
+                 tile_c: Optional[Sequence[int]] = None, attach_arena=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the GGNS engine needs a ROCm GPU; no CPU path exists")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.cfgs: List[RunConfig] = list(configs)
+        L = _lib.load()
+        self.L = L
+        n = len(self.cfgs)
+        self.descs = (_lib.ggns_run_desc * n)()
+        off = 0
+        blocks = []
+        for i, c in enumerate(self.cfgs):
+            D = self.descs[i]
+            D.d, D.n_live, D.n_kill = c.d, c.n_live, c.n_kill
+            D.lik_kind, D.precision, D.n_comp = c.kind_id, c.precision_id, c.n_comp
+            D.param_offset = off
+            D.prior_lo, D.prior_hi, D.dt_init = c.lo, c.hi, c.dt_init
+            D.n_steps_max, D.min_ref, D.max_ref = c.n_steps_max, c.min_ref, c.max_ref
+            D.prune_streak, D.delta_p = c.prune_streak, c.delta_p
+            D.out_hi, D.out_lo, D.dt_down, D.dt_up = c.out_hi, c.out_lo, c.dt_down, c.dt_up
+            D.term_kind, D.max_iter, D.term_tol = c.term_kind, c.max_iter, c.term_tol
+            D.seed = int(c.seed) & (2 ** 64 - 1)
+            D.tile_c = int(tile_c[i]) if tile_c is not None else 0
+            blocks.append(np.asarray(c.params, np.float64))
+            off += len(c.params)
+        self.params = torch.from_numpy(np.concatenate(blocks)).to(self.device)
+        nbytes = int(L.ggns_arena_bytes(self.descs, n))
+        if nbytes < 0:
+            _lib.check(nbytes, "ggns_arena_bytes")
+        self.arena_bytes = nbytes
+        if attach_arena is not None:
+            self.arena = attach_arena
+        else:
+            self.arena = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+        if self.arena.data_ptr() % 256:
+            raise RuntimeError("arena is not 256-byte aligned")
+        self.ctx = C.c_void_p()
+        fn = L.ggns_attach if attach_arena is not None else L.ggns_init
+        _lib.check(fn(C.byref(self.ctx), self.descs, n, self.params.data_ptr(),
+                      self.params.numel(), self.arena.data_ptr(), nbytes, self._stream()),
+                   "ggns_init")
+        self.layouts = []
+        for r in range(n):
+            lay = _lib.ggns_layout()
+            _lib.check(L.ggns_run_layout(self.ctx, r, C.byref(lay)), "ggns_run_layout")
+            self.layouts.append(lay)
+        self._graph = None
+        self._graph_iters = 0
+        self._trace = {}
+
+    # ------------------------------------------------------------------ plumbing
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _view(self, off, nbytes, dtype, shape):
+        return self.arena[off:off + nbytes].view(dtype).view(*shape)
+
+    def _fdtype(self, r):
+        return self.torch.float64 if self.layouts[r].elem_bytes == 8 else self.torch.float32
+
+    def close(self):
+        if self.ctx:
+            self.L.ggns_free(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ steps
+    def evidence_update(self, final_sweep: bool = False):
+        _lib.check(self.L.ggns_evidence_update(self.ctx, int(final_sweep), self._stream()),
+                   "ggns_evidence_update")
+
+    def hss_walk(self):
+        _lib.check(self.L.ggns_hss_walk(self.ctx, self._stream()), "ggns_hss_walk")
+
+    def replace_dead(self):
+        _lib.check(self.L.ggns_replace_dead(self.ctx, self._stream()), "ggns_replace_dead")
+
+    def iterate(self, n: int = 1):
+        for _ in range(n):
+            self.evidence_update()
+            self.hss_walk()
+            self.replace_dead()
+
+    def capture(self, iters: int):
+        """Capture `iters` iterations as one HIP graph (kernels only)."""
+        torch = self.torch
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                self.iterate(iters)
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        self._graph = g
+        self._graph_iters = iters
+
+    def step_block(self, iters: int, use_graph: bool):
+        if use_graph:
+            if self._graph is None or self._graph_iters != iters:
+                self.capture(iters)
+            self._graph.replay()
+        else:
+            self.iterate(iters)
+
+    def run(self, poll_every: int = 8, use_graph: bool = False, max_blocks: int = 10 ** 6):
+        """Iterate until every run stopped; returns the per-run stats."""
+        for _ in range(max_blocks):
+            self.step_block(poll_every, use_graph)
+            st = self.stats()
+            if all(s["state"] != _lib.RUN_ACTIVE for s in st):
+                return st
+        raise RuntimeError("runs did not terminate")
+
+    # ------------------------------------------------------------------ state
+    def stats(self) -> List[dict]:
+        n = len(self.cfgs)
+        out = (_lib.ggns_run_stats * n)()
+        _lib.check(self.L.ggns_read_stats(self.ctx, out, self._stream()), "ggns_read_stats")
+        res = []
+        for s in out:
+            res.append({f: getattr(s, f) for f, _ in _lib.ggns_run_stats._fields_
+                        if f != "reserved"})
+        return res
+
+    def write_vars(self, r: int, log_z: float, log_x: float, dt: float, iteration: int):
+        v = _lib.ggns_run_vars(log_z=log_z, log_x=log_x, dt=dt, iter=iteration)
+        _lib.check(self.L.ggns_write_vars(self.ctx, r, C.byref(v), self._stream()),
+                   "ggns_write_vars")
+
+    def tile_shape(self, r: int):
+        c, g = C.c_int32(), C.c_int32()
+        _lib.check(self.L.ggns_tile_shape(self.ctx, r, C.byref(c), C.byref(g)), "ggns_tile_shape")
+        return c.value, g.value
+
+    # views into the arena (device tensors)
+    def live_x(self, r):
+        c, lay = self.cfgs[r], self.layouts[r]
+        return self._view(lay.live_x, c.n_live * c.d * lay.elem_bytes, self._fdtype(r),
+                          (c.n_live, c.d))
+
+    def live_logl(self, r):
+        c, lay = self.cfgs[r], self.layouts[r]
+        return self._view(lay.live_logl, c.n_live * 8, self.torch.float64, (c.n_live,))
+
+    def killed(self, r):
+        c, lay = self.cfgs[r], self.layouts[r]
+        return self._view(lay.killed, c.n_kill * 4, self.torch.int32, (c.n_kill,))
+
+    def survivors(self, r):
+        c, lay = self.cfgs[r], self.layouts[r]
+        m = c.n_live - c.n_kill
+        return self._view(lay.survivors, m * 4, self.torch.int32, (m,))
+
+    def start(self, r):
+        c, lay = self.cfgs[r], self.layouts[r]
+        return self._view(lay.start, c.n_kill * 4, self.torch.int32, (c.n_kill,))
+
+    def walk_x(self, r):
+        c, lay = self.cfgs[r], self.layouts[r]
+        return self._view(lay.walk_x, c.n_kill * c.d * lay.elem_bytes, self._fdtype(r),
+                          (c.n_kill, c.d))
+
+    def walk_logl(self, r):
+        c, lay = self.cfgs[r], self.layouts[r]
+        return self._view(lay.walk_logl, c.n_kill * 8, self.torch.float64, (c.n_kill,))
+
+    def dead(self, r, n_dead: Optional[int] = None):
+        lay = self.layouts[r]
+        if n_dead is None:
+            n_dead = int(self.stats()[r]["n_dead"])
+        n_dead = min(n_dead, lay.dead_cap)
+        return (self._view(lay.dead_logl, n_dead * 8, self.torch.float64, (n_dead,)),
+                self._view(lay.dead_logw, n_dead * 8, self.torch.float64, (n_dead,)))
+
+    def set_trace(self, r: int, steps: int):
+        """Record the first `steps` steps of every walker of run r."""
+        torch = self.torch
+        c = self.cfgs[r]
+        if steps <= 0:
+            _lib.check(self.L.ggns_set_trace(self.ctx, r, None, None, None, 0), "ggns_set_trace")
+            self._trace.pop(r, None)
+            return None
+        tx = torch.zeros((steps, c.n_kill, c.d), dtype=self._fdtype(r), device=self.device)
+        tl = torch.zeros((steps, c.n_kill), dtype=torch.float64, device=self.device)
+        to = torch.zeros((steps, c.n_kill), dtype=torch.int32, device=self.device)
+        _lib.check(self.L.ggns_set_trace(self.ctx, r, tx.data_ptr(), tl.data_ptr(), to.data_ptr(),
+                                         steps), "ggns_set_trace")
+        self._trace[r] = (tx, tl, to)
+        return self._trace[r]
+
+    # ------------------------------------------------------------------ likelihood
+    def loglike(self, r: int, x, grad: bool = True):
+        torch = self.torch
+        x = x.to(device=self.device, dtype=self._fdtype(r)).contiguous()
+        n = x.shape[0]
+        logl = torch.empty(n, dtype=torch.float64, device=self.device)
+        g = torch.empty_like(x) if grad else None
+        _lib.check(self.L.ggns_loglike_grad(self.ctx, r, x.data_ptr(), n, logl.data_ptr(),
+                                            g.data_ptr() if g is not None else None,
+                                            self._stream()), "ggns_loglike_grad")
+        return logl, g
+
+    def loglike_vjp(self, r: int, x, gout):
+        torch = self.torch
+        x = x.to(device=self.device, dtype=self._fdtype(r)).contiguous()
+        gout = gout.to(device=self.device, dtype=torch.float64).contiguous()
+        gx = torch.empty_like(x)
+        _lib.check(self.L.ggns_loglike_vjp(self.ctx, r, x.data_ptr(), x.shape[0], gout.data_ptr(),
+                                           gx.data_ptr(), self._stream()), "ggns_loglike_vjp")
+        return gx
+
+
+def run_configs(configs: Sequence[RunConfig], poll_every: int = 8, use_graph: bool = False,
+                device: str = "cuda") -> List[dict]:
+    eng = Engine(configs, device=device)
+    st = eng.run(poll_every=poll_every, use_graph=use_graph)
+    eng.close()
+    return st

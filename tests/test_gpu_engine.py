@@ -1,0 +1,150 @@
+"""Engine behaviour on the GPU: batching, graph replay, determinism,
+checkpoint/resume, per-run failure states, end-to-end agreement with the
+oracle within the runs' own error."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2312_03911_amd import exact, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _engine(cfgs, **kw):
+    from paper_2312_03911_amd.engine import Engine
+    return Engine(cfgs, **kw)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _small_mix():
+    return [inputs.config_shells(d=8, n_live=300, seed=31),
+            inputs.config_gmm(d=8, n_live=200, n_comp=4, seed=32, param_seed=3),
+            inputs.RunConfig(kind="gauss_diag", d=4, n_live=120, lo=-4, hi=4, seed=33,
+                             params=inputs.gauss_diag_params([0.1, -0.2, 0.3, 0.0], [0.5, 0.7, 0.9, 1.1])),
+            inputs.config_gauss2d(seed=34)]
+
+
+def test_run_inside_batch_equals_run_alone(torch):
+    cfgs = _small_mix()
+    both = _engine(cfgs)
+    both.iterate(6)
+    for r, c in enumerate(cfgs):
+        one = _engine([c])
+        one.iterate(6)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(_np(both.live_x(r)), _np(one.live_x(0)))
+        np.testing.assert_array_equal(_np(both.live_logl(r)), _np(one.live_logl(0)))
+        a, b = both.stats()[r], one.stats()[0]
+        for key in ("log_z", "log_x", "dt", "lstar", "iter", "evals", "steps_out", "prunes"):
+            assert a[key] == b[key], key
+        one.close()
+    both.close()
+
+
+def test_same_seed_is_bitwise_reproducible(torch):
+    cfgs = _small_mix()
+    a, b = _engine(cfgs), _engine(cfgs)
+    a.iterate(5)
+    b.iterate(5)
+    torch.cuda.synchronize()
+    for r in range(len(cfgs)):
+        np.testing.assert_array_equal(_np(a.live_x(r)), _np(b.live_x(r)))
+        assert a.stats()[r] == b.stats()[r]
+
+
+def test_graph_replays_match_eager_iterations(torch):
+    cfgs = _small_mix()
+    eager, graph = _engine(cfgs), _engine(cfgs)
+    for block in range(4):
+        eager.iterate(3)
+        graph.step_block(3, use_graph=True)
+        torch.cuda.synchronize()
+        # eager work and synchronisation between replays
+        s_e, s_g = eager.stats(), graph.stats()
+        for r in range(len(cfgs)):
+            np.testing.assert_array_equal(_np(eager.live_x(r)), _np(graph.live_x(r)))
+            np.testing.assert_array_equal(_np(eager.live_logl(r)), _np(graph.live_logl(r)))
+            assert s_e[r] == s_g[r], (block, r)
+
+
+def test_checkpoint_and_resume_is_exact(torch):
+    cfgs = _small_mix()
+    a = _engine(cfgs)
+    a.iterate(3)
+    torch.cuda.synchronize()
+    saved = a.arena.cpu().clone()
+    a.iterate(4)
+    torch.cuda.synchronize()
+    restored = saved.to(a.device)
+    b = _engine(cfgs, attach_arena=restored)
+    b.iterate(4)
+    torch.cuda.synchronize()
+    for r in range(len(cfgs)):
+        np.testing.assert_array_equal(_np(a.live_x(r)), _np(b.live_x(r)))
+        assert a.stats()[r] == b.stats()[r]
+
+
+def test_nonfinite_run_stops_alone(torch):
+    good = inputs.config_shells(d=8, n_live=200, seed=41)
+    bad = inputs.config_gauss2d(seed=42)
+    bad.params = np.array([0.5, math.nan, 0.05, 0.05])
+    eng = _engine([good, bad])
+    alone = _engine([good])
+    eng.iterate(3)
+    alone.iterate(3)
+    torch.cuda.synchronize()
+    st = eng.stats()
+    assert st[1]["state"] == 3 and st[0]["state"] == 0
+    np.testing.assert_array_equal(_np(eng.live_x(0)), _np(alone.live_x(0)))
+
+
+def test_max_iter_state_and_final_sweep(torch):
+    cfg = inputs.config_gauss2d(seed=43, max_iter=4)
+    eng = _engine([cfg])
+    st = eng.run(poll_every=2)[0]
+    assert st["state"] == 2 and st["iter"] == 4
+    assert st["n_dead"] == 4 * cfg.n_kill + cfg.n_live
+    assert math.isfinite(st["sigma_kl"]) and st["sigma_kl"] > 0
+
+
+def test_forced_final_sweep(torch, orc):
+    cfg = inputs.config_gauss2d(seed=44)
+    eng = _engine([cfg])
+    eng.iterate(5)
+    eng.evidence_update(final_sweep=True)
+    o = orc.Oracle(cfg).init()
+    for _ in range(5):
+        o.iterate()
+    o.evidence_update(final_sweep=True)
+    st = eng.stats()[0]
+    assert st["state"] == 1 and o.st.state == 1
+    assert abs(st["log_z"] - o.st.lz) < 1e-9 and abs(st["h"] - o.st.h) < 1e-8
+
+
+def test_shells_end_to_end_agree_with_oracle_within_error(torch, orc):
+    """FP32 GPU and FP64 oracle runs of the shell problem: their log Z agree within
+    the combined statistical error (trajectories differ after FP32 roundings)."""
+    gz, oz, gs, os_ = [], [], [], []
+    cfgs = inputs.replicate(inputs.config_shells(d=16, n_live=200), 6, base_seed=500)
+    eng = _engine(cfgs)
+    st = eng.run(poll_every=8)
+    for c, s in zip(cfgs, st):
+        o = orc.Oracle(c).run()
+        gz.append(s["log_z"]); oz.append(o.st.lz)
+        gs.append(s["sigma_mom"]); os_.append(o.st.sigma_mom)
+        assert s["state"] == 1
+    diff = np.mean(gz) - np.mean(oz)
+    err = math.sqrt((np.mean(gs) ** 2 + np.mean(os_) ** 2) / len(cfgs))
+    assert abs(diff) < 4 * err, (diff, err)

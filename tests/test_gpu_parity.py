@@ -1,0 +1,184 @@
+"""GPU engine vs the FP64 oracle on identical seeded inputs, through the C ABI.
+
+Tolerances: FP64 runs 1e-10 relative (per-step positions), FP32 runs 1e-4
+relative to max(|x|, prior width), as stated for short walks.  Where floating
+point decides a branch (outside / inside, a box face), a walker is compared only
+up to the first step the oracle finds within tau of that decision (log L: tau
+relative to max(1, |L*|) with tau 1e-9 in FP64 and 1e-4 in FP32; faces: 0.1 tau
+times the prior width); the masked share must stay small.  Per-step log L is
+compared with the oracle's log L at the GPU's own positions, which separates
+the likelihood arithmetic from the (bounded) drift of FP32 trajectories."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2312_03911_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _engine(cfgs):
+    from paper_2312_03911_amd.engine import Engine
+    return Engine(cfgs)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _load_state(torch, eng, o, r, X):
+    """Same live set on both sides; each side evaluates its own log L."""
+    cfg = eng.cfgs[r]
+    xd = torch.from_numpy(X).to(eng.device, eng._fdtype(r))
+    eng.live_x(r).copy_(xd)
+    l, _ = eng.loglike(r, eng.live_x(r).clone(), grad=False)
+    eng.live_logl(r).copy_(l)
+    Xo = _np(xd).astype(np.float64)          # the rounded positions the GPU holds
+    o.set_state(live_x=Xo, log_z=-math.inf, log_x=0.0, dt=cfg.dt_init * (cfg.hi - cfg.lo),
+                iteration=0)
+    torch.cuda.synchronize()
+    return Xo
+
+
+CASES = [
+    ("gauss2d_fp64", lambda: inputs.config_gauss2d(seed=11), 1e-10, 1e-9),
+    ("shells32_fp32", lambda: inputs.config_shells(d=32, n_live=1000, seed=12), 1e-4, 1e-4),
+    ("gmm16_fp32", lambda: inputs.config_gmm(d=16, n_live=600, n_comp=8, seed=13, param_seed=5),
+     1e-4, 1e-4),
+    ("gauss_diag24_fp32", lambda: inputs.RunConfig(
+        kind="gauss_diag", d=24, n_live=400, lo=-5.0, hi=5.0, seed=14, n_steps_max=60,
+        params=inputs.gauss_diag_params(np.linspace(-1, 1, 24), np.linspace(0.3, 1.2, 24))),
+     1e-4, 1e-4),
+    ("corr12_fp32", lambda: inputs.config_corr_gauss(d=12, n_live=300, seed=15, param_seed=7,
+                                                     precision="fp32", n_steps_max=60), 1e-4, 1e-4),
+    ("shells5_fp64", lambda: inputs.config_shells(d=5, n_live=200, seed=16, precision="fp64"),
+     1e-10, 1e-9),
+]
+
+
+@pytest.mark.parametrize("name,make,tol,tau", CASES, ids=[c[0] for c in CASES])
+def test_init_matches_oracle(torch, orc, name, make, tol, tau):
+    cfg = make()
+    eng = _engine([cfg])
+    torch.cuda.synchronize()
+    o = orc.Oracle(cfg).init()
+    x = _np(eng.live_x(0)).astype(np.float64)
+    scale = max(abs(cfg.lo), abs(cfg.hi))
+    err = np.abs(x - o.live_x).max() / scale
+    assert err < (1e-15 if cfg.precision == "fp64" else 1e-7)
+    l = _np(eng.live_logl(0))
+    rel = np.abs(l - o.live_logl) / np.maximum(1.0, np.abs(o.live_logl))
+    assert rel.max() < (1e-12 if cfg.precision == "fp64" else 2e-5)
+    st = eng.stats()[0]
+    assert st["state"] == 0 and st["evals"] == cfg.n_live
+    assert abs(st["dt"] - cfg.dt_init * (cfg.hi - cfg.lo)) < 1e-15
+    eng.close()
+
+
+@pytest.mark.parametrize("name,make,tol,tau", CASES, ids=[c[0] for c in CASES])
+def test_kill_and_walk_trace_match_oracle(torch, orc, name, make, tol, tau):
+    cfg = make()
+    T = 20
+    eng = _engine([cfg])
+    o = orc.Oracle(cfg, trace_steps=T).init()
+    if cfg.kind == "shells":
+        X = inputs.uniform_points(cfg.n_live, cfg.d, -3.0, 3.0, seed=99)
+        X[:, 0] += np.where(np.arange(cfg.n_live) % 2 == 0, 2.5, -2.5)
+    else:
+        X = inputs.uniform_points(cfg.n_live, cfg.d, cfg.lo, cfg.hi, seed=99)
+    Xo = _load_state(torch, eng, o, 0, X)
+    tx, tl, to = eng.set_trace(0, T)
+    eng.evidence_update()
+    o.evidence_update()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
+    np.testing.assert_array_equal(_np(eng.survivors(0)), o.surv[:cfg.n_live - cfg.n_kill])
+    st = eng.stats()[0]
+    assert abs(st["lstar"] - o.st.lstar) <= tau * max(1.0, abs(o.st.lstar))
+    assert abs(st["log_z"] - o.st.lz) < (1e-12 if tol < 1e-6 else 2e-5) * max(1.0, abs(o.st.lz))
+    assert abs(st["log_x"] - o.st.lx) < 1e-13
+    eng.hss_walk()
+    o.hss_walk()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.start(0)), o.start)
+    gx, gl, go = _np(tx).astype(np.float64), _np(tl), _np(to)
+    width = cfg.hi - cfg.lo
+    lstar = o.st.lstar
+    masked, compared, worst = 0, 0, 0.0
+    for m in range(cfg.n_kill):
+        steps = int((o.trace_x[:, m] != 0).any(axis=1).sum())
+        cut = steps
+        for t in range(steps):
+            near_l = abs(o.trace_logl[t, m] - lstar) < tau * max(1.0, abs(lstar))
+            xo = o.trace_x[t, m]
+            near_f = np.any(np.minimum(np.abs(xo - cfg.lo), np.abs(xo - cfg.hi)) < 0.1 * tau * width)
+            if near_l or near_f:
+                cut = t
+                break
+        if cut < steps:
+            masked += 1
+        if cut == 0:
+            continue
+        ref = o.trace_x[:cut, m]
+        err = np.abs(gx[:cut, m] - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), width)
+        worst = max(worst, err.max())
+        np.testing.assert_array_equal(go[:cut, m], o.trace_out[:cut, m])
+        lref, _ = orc.loglike(cfg, gx[:cut, m])
+        lrel = np.abs(gl[:cut, m] - lref) / np.maximum(1.0, np.abs(lref))
+        assert lrel.max() < (1e-12 if tol < 1e-6 else 2e-5)
+        compared += 1
+    assert worst < tol, worst
+    assert masked <= max(2, 0.02 * cfg.n_kill), masked
+    assert compared >= 0.9 * cfg.n_kill
+
+
+@pytest.mark.parametrize("name,make,tol,tau", CASES, ids=[c[0] for c in CASES])
+def test_loglike_and_adjoint_match_oracle(torch, orc, name, make, tol, tau):
+    cfg = make()
+    eng = _engine([cfg])
+    X = inputs.uniform_points(257, cfg.d, 0.3 * cfg.lo, 0.3 * cfg.hi, seed=5)
+    xd = torch.from_numpy(X).to(eng.device, eng._fdtype(0))
+    Xr = _np(xd).astype(np.float64)
+    l, g = eng.loglike(0, xd)
+    lo_, go_ = orc.loglike(cfg, Xr)
+    torch.cuda.synchronize()
+    rel = 1e-12 if cfg.precision == "fp64" else 1e-5
+    assert np.all(np.abs(_np(l) - lo_) <= rel * np.maximum(1.0, np.abs(lo_)))
+    gs = np.abs(go_).max(axis=1, keepdims=True)
+    assert np.all(np.abs(_np(g) - go_) <= (1e-10 if cfg.precision == "fp64" else 2e-4) * np.maximum(gs, 1.0))
+    gout = torch.linspace(-2.0, 3.0, 257, dtype=torch.float64, device=eng.device)
+    gx = eng.loglike_vjp(0, xd, gout)
+    np.testing.assert_allclose(_np(gx), _np(g) * _np(gout)[:, None], rtol=1e-6, atol=1e-6 * gs.max())
+    # empty input is a no-op
+    l0, _ = eng.loglike(0, xd[:0])
+    assert l0.numel() == 0
+
+
+def test_gauss2d_fp64_full_run_matches_oracle(torch, orc):
+    """The whole FP64 run (init, iterations, final sweep) reproduces the oracle."""
+    for seed in (2100, 2101, 2102):
+        cfg = inputs.config_gauss2d(seed=seed)
+        eng = _engine([cfg])
+        st = eng.run(poll_every=4)[0]
+        o = orc.Oracle(cfg).run()
+        assert st["state"] == o.st.state == 1
+        assert st["iter"] == o.st.iter
+        assert st["evals"] == o.st.evals
+        assert abs(st["log_z"] - o.st.lz) < 1e-9
+        assert abs(st["sigma_kl"] - o.st.sigma_kl) < 1e-9
+        assert abs(st["sigma_mom"] - o.st.sigma_mom) < 1e-7
+        assert abs(st["log_z2"] - o.st.lz2) < 1e-9
+        dl, dw = eng.dead(0)
+        ol, ow = o.dead()
+        np.testing.assert_allclose(_np(dl), ol, rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(_np(dw), ow, rtol=1e-12, atol=1e-11)
+        eng.close()
