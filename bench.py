@@ -140,7 +140,8 @@ def main():
                 for a, b in evs:
                     walk_ms.append(a.elapsed_time(b))
             if all(s["state"] != 0 for s in st):
-                return st
+                eng.finalize()
+                return eng.stats()
 
     for _ in range(args.warmup):
         full_run(False)

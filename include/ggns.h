@@ -136,7 +136,7 @@ typedef struct {
     double dt;               /* current step (prior units) */
     double lstar;            /* current threshold log L* */
     double log_xl_max;       /* running max of log(X * L_max) (X*L peak criterion) */
-    double h;                /* information H = sum p_i log(L_i / Z), after the final sweep */
+    double h;                /* information H = sum p_i log(L_i / Z), after ggns_finalize */
     double sigma_kl;         /* sqrt(H / n_live) (Eq. logZ_error) */
     double sigma_mom;        /* sqrt(log Z2bar - 2 log Zbar) */
     int64_t iter;            /* iterations done */
@@ -178,8 +178,15 @@ int ggns_attach(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs,
 
 /* Termination test, kill and evidence update for every ACTIVE run; a run that
  * meets its criterion (or max_iter, or final_sweep != 0) gets the final sweep
- * and its summary (H, sigma_KL, sigma_mom) and leaves the ACTIVE state. */
+ * (its remaining live points become dead records and enter log Z) and leaves
+ * the ACTIVE state. */
 int ggns_evidence_update(ggns_ctx *ctx, int32_t final_sweep, void *stream);
+
+/* Summary of every run whose final sweep is done and not yet summarised: the
+ * information H, sigma_KL = sqrt(H / n_live) (Eq. logZ_error) and sigma_mom
+ * from the second moment of Z (Eqs. update0-update9, single cluster), over the
+ * whole dead sequence.  One launch for all runs; call it once they stopped. */
+int ggns_finalize(ggns_ctx *ctx, void *stream);
 
 /* The batched HSS walk for every ACTIVE run: n_kill walkers, started from
  * survivors drawn uniformly, write their outputs to walk_x / walk_logl. */

@@ -14,7 +14,7 @@ GGNS_OK, GGNS_EINVAL, GGNS_EHIP, GGNS_EUNSUPPORTED, GGNS_ESTATE = 0, -1, -2, -3,
 RUN_ACTIVE, RUN_DONE, RUN_MAXITER, RUN_NONFINITE = 0, 1, 2, 3
 
 # every symbol the header declares
-SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update",
+SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update", "ggns_finalize",
            "ggns_hss_walk", "ggns_replace_dead", "ggns_loglike_grad", "ggns_loglike_vjp",
            "ggns_run_layout", "ggns_read_stats", "ggns_write_vars", "ggns_set_trace",
            "ggns_tile_shape", "ggns_free", "ggns_status_string")
@@ -78,6 +78,7 @@ def load() -> C.CDLL:
             fn.restype = C.c_int
         L.ggns_evidence_update.argtypes = [vp, i32, vp]
         L.ggns_hss_walk.argtypes = [vp, vp]
+        L.ggns_finalize.argtypes = [vp, vp]
         L.ggns_replace_dead.argtypes = [vp, vp]
         L.ggns_loglike_grad.argtypes = [vp, i32, vp, i64, vp, vp, vp]
         L.ggns_loglike_vjp.argtypes = [vp, i32, vp, i64, vp, vp, vp]
@@ -90,7 +91,7 @@ def load() -> C.CDLL:
         L.ggns_free.restype = None
         L.ggns_status_string.argtypes = [C.c_int]
         L.ggns_status_string.restype = C.c_char_p
-        for name in ("ggns_evidence_update", "ggns_hss_walk", "ggns_replace_dead",
+        for name in ("ggns_evidence_update", "ggns_finalize", "ggns_hss_walk", "ggns_replace_dead",
                      "ggns_loglike_grad", "ggns_loglike_vjp", "ggns_run_layout",
                      "ggns_read_stats", "ggns_write_vars", "ggns_set_trace", "ggns_tile_shape"):
             getattr(L, name).restype = C.c_int

@@ -7,7 +7,7 @@
 #include <tuple>
 #include <vector>
 
-#include "ggns_common.h"
+#include "ggns_device.h"
 
 using namespace ggns;
 
@@ -96,8 +96,10 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         while (G > 64) { C *= 2; G = next_pow2((D.d + C - 1) / C); }
         if (C > 8 || (D.precision == GGNS_FP64 && C > 4)) return GGNS_EUNSUPPORTED;
         R.C = C; R.G = G;
+        R.dp = G * C;
+        R.var = lik_variant(D.lik_kind, R.n_comp);
         const int64_t es = (D.precision == GGNS_FP64) ? 8 : 4;
-        R.nprm = converted_params(D.lik_kind, D.d, R.n_comp);
+        R.nprm = (int32_t)converted_size(R.var, D.d, R.dp);
         const int64_t prm_bytes = (int64_t)R.nprm * es;
         R.nprm_bytes_lds = (prm_bytes <= 48 * 1024) ? (int32_t)prm_bytes : 0;
         R.dead_cap = (int64_t)D.n_kill * D.max_iter + D.n_live;
@@ -124,7 +126,7 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
 }
 
 struct Class {
-    int prec, C, kind;
+    int prec, C, kind;   // kind: kernel variant (lik_variant)
     bool mfma;
     int64_t tile_off;   // index of the first tile in the arena tile array
     int n_tiles;
@@ -161,7 +163,7 @@ void build_classes(ggns_ctx *c) {
         if (R.prec == GGNS_FP32_BF16MMA)
             mfma_runs.push_back(r);
         else
-            groups[std::make_tuple(R.prec, R.C, R.kind)].push_back(r);
+            groups[std::make_tuple(R.prec, R.C, R.var)].push_back(r);
         c->max_kd = std::max<int>(c->max_kd, R.n_kill * R.d);
     }
     c->tiles_host.clear();
@@ -284,6 +286,13 @@ int ggns_attach(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const
 int ggns_evidence_update(ggns_ctx *ctx, int32_t final_sweep, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
     launch_evidence(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), final_sweep ? 1 : 0,
+                    reinterpret_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+int ggns_finalize(ggns_ctx *ctx, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    launch_finalize(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(),
                     reinterpret_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }

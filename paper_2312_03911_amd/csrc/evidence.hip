@@ -127,73 +127,80 @@ __device__ int block_exscan_int(int v, int *buf) {
     return incl - v;
 }
 
-// Live-point count n_p in force when dead record i was killed: iterations
-// killed k points each with n_p = n, ..., n-k+1; the final sweep n points with
-// n_p = n, ..., 1.
-__device__ __forceinline__ double n_p_of(long long i, long long n_batch, int n, int k) {
-    if (i < n_batch) return (double)(n - (int)(i % k));
-    return (double)(n - (int)(i - n_batch));
-}
-
 // Run summary over the whole dead sequence: information H, and the second
 // moment of Z from the single-cluster recursion (update0, update2, update3,
-// update5, update8) written as scans: with X_i = prod n_p/(n_p+1) and
-// Y_i = prod n_p/(n_p+2) before record i, ZX_i = X_i sum_{j<i} Y_j L_j /
-// ((n_j+2) X_j), and Z2 = sum_i 2 ZX_i L_i/(n_i+1) + 2 Y_i L_i^2 /
-// ((n_i+1)(n_i+2)).
+// update5, update8).  Written as scans: with X_i = prod n_p/(n_p+1) and
+// Y_i = prod n_p/(n_p+2) over the records before i, ZX_i = X_i sum_{j<i}
+// Y_j L_j / ((n_j+2) X_j), and Z2 = sum_i 2 ZX_i L_i/(n_i+1) + 2 Y_i L_i^2 /
+// ((n_i+1)(n_i+2)).  The live count n_p of record i follows from the kill
+// pattern (iterations kill k points with n_p = n, ..., n-k+1; the final sweep
+// n points with n_p = n, ..., 1), so log n_p, log(n_p+1), log(n_p+2) come from a
+// table of log v, v = 0 .. n+2, held in LDS.
 __device__ void run_summary(const RunDev &R, Acc *acc, const double *dl, const double *dw,
-                            long long N, long long n_batch, double *buf, double *scratch) {
+                            long long N, long long n_batch, double *lg, double *buf,
+                            double *scratch) {
     const int n = R.n_live, k = R.n_kill;
     const int T = blockDim.x, t = threadIdx.x;
+    for (int v = t; v <= n + 2; v += T) lg[v] = (v > 0) ? log((double)v) : -INFINITY;
+    __syncthreads();
     const long long chunk = (N + T - 1) / T;
     const long long i0 = (long long)t * chunk;
     const long long i1 = (i0 + chunk < N) ? i0 + chunk : N;
     const double lz = acc->log_z;
+    // position of record i0 in its kill pattern
+    auto np_at = [&](long long i) -> int {
+        return (i < n_batch) ? n - (int)(i % k) : n - (int)(i - n_batch);
+    };
 
-    // H = sum p_i (log L_i - log Z), p_i = L_i w_i / Z
-    double hpart = 0.0;
-    for (long long i = i0; i < i1; ++i) {
-        const double lp = dl[i] + dw[i] - lz;
-        hpart += exp(lp) * (dl[i] - lz);
+    // H = sum p_i (log L_i - log Z), p_i = L_i w_i / Z; prefix sums of log X, log Y
+    double hpart = 0.0, sx = 0.0, sy = 0.0;
+    {
+        int np = (i0 < N) ? np_at(i0) : n;
+        for (long long i = i0; i < i1; ++i) {
+            const double lp = dl[i] + dw[i] - lz;
+            hpart += exp(lp) * (dl[i] - lz);
+            sx += lg[np] - lg[np + 1];
+            sy += lg[np] - lg[np + 2];
+            --np;
+            if (i + 1 == n_batch || (i + 1 < n_batch && np == n - k)) np = n;
+        }
     }
     const double h = block_sum(hpart, scratch);
-
-    // prefix sums of log X and log Y
-    double sx = 0.0, sy = 0.0;
-    for (long long i = i0; i < i1; ++i) {
-        const double np = n_p_of(i, n_batch, n, k);
-        sx += log(np) - log(np + 1.0);
-        sy += log(np) - log(np + 2.0);
-    }
-    double lx = block_exscan_sum(sx, buf);
-    double ly = block_exscan_sum(sy, buf);
+    const double lx0 = block_exscan_sum(sx, buf);
+    const double ly0 = block_exscan_sum(sy, buf);
     // local log-sum of c_j = Y_j L_j / ((n_j+2) X_j)
     double cm = -INFINITY, cs = 0.0;
     {
-        double x = lx, y = ly;
+        double x = lx0, y = ly0;
+        int np = (i0 < N) ? np_at(i0) : n;
         for (long long i = i0; i < i1; ++i) {
-            const double np = n_p_of(i, n_batch, n, k);
-            lse_push(y + dl[i] - log(np + 2.0) - x, cm, cs);
-            x += log(np) - log(np + 1.0);
-            y += log(np) - log(np + 2.0);
+            lse_push(y + dl[i] - lg[np + 2] - x, cm, cs);
+            x += lg[np] - lg[np + 1];
+            y += lg[np] - lg[np + 2];
+            --np;
+            if (i + 1 == n_batch || (i + 1 < n_batch && np == n - k)) np = n;
         }
     }
     const double lc_local = (cm == -INFINITY) ? -INFINITY : cm + log(cs);
-    double lsum = block_exscan_lae(lc_local, buf);
-    // terms of Z2 and of the recursion's Z
+    const double lsum = block_exscan_lae(lc_local, buf);
+    // terms of Z2 and of the recursion's own Z
     double am = -INFINITY, as = 0.0, zm = -INFINITY, zs = 0.0;
     {
-        double x = lx, y = ly, sc = lsum;
+        double x = lx0, y = ly0;
+        double sm = lsum, ss = (lsum == -INFINITY) ? 0.0 : 1.0;   // running S_j as (sm, ss)
         const double l2 = 0.69314718055994530942;
+        int np = (i0 < N) ? np_at(i0) : n;
         for (long long i = i0; i < i1; ++i) {
-            const double np = n_p_of(i, n_batch, n, k);
-            const double ln1 = log(np + 1.0), ln2 = log(np + 2.0);
-            lse_push(l2 + x + sc + dl[i] - ln1, am, as);
+            const double ln1 = lg[np + 1], ln2 = lg[np + 2];
+            const double ls = (sm == -INFINITY) ? -INFINITY : sm + log(ss);
+            lse_push(l2 + x + ls + dl[i] - ln1, am, as);
             lse_push(l2 + y + 2.0 * dl[i] - ln1 - ln2, am, as);
             lse_push(x + dl[i] - ln1, zm, zs);
-            sc = lae(sc, y + dl[i] - ln2 - x);
-            x += log(np) - ln1;
-            y += log(np) - ln2;
+            lse_push(y + dl[i] - ln2 - x, sm, ss);
+            x += lg[np] - ln1;
+            y += lg[np] - ln2;
+            --np;
+            if (i + 1 == n_batch || (i + 1 < n_batch && np == n - k)) np = n;
         }
     }
     const double lz2 = block_lse(am, as, scratch);
@@ -308,12 +315,12 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
         }
     }
     if (stop) {
-        __syncthreads();
-        __threadfence_block();
-        const long long N = (nd + nkill < R.dead_cap) ? nd + nkill : R.dead_cap;
-        __shared__ double buf[kEvThreads];
-        run_summary(R, acc, dead_l, dead_w, N, nd, buf, scratch);
-        if (t == 0) acc->state = stop;
+        // the summary (H, sigma_KL, sigma_mom) is left to the finalize launch,
+        // so runs that stop at different iterations do not serialise on it
+        if (t == 0) {
+            acc->summary_pending = 1;
+            acc->state = stop;
+        }
         return;
     }
     // killed slots in kill order; survivors in ascending slot order
@@ -339,7 +346,27 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
         if (!dead_flag[i]) surv[pos++] = i;
 }
 
+__global__ void __launch_bounds__(kEvThreads)
+finalize_kernel(void *arena, const RunDev *__restrict__ runs) {
+    const RunDev &R = runs[blockIdx.x];
+    Acc *acc = at<Acc>(arena, R.off_acc);
+    if (!acc->summary_pending) return;
+    __shared__ double lg[kMaxLive + 3];
+    __shared__ double buf[kEvThreads];
+    __shared__ double scratch[32];
+    const long long nd = acc->n_dead;
+    const long long N = (nd < R.dead_cap) ? nd : R.dead_cap;
+    const long long n_batch = nd - R.n_live;
+    run_summary(R, acc, at<double>(arena, R.off_dead_logl), at<double>(arena, R.off_dead_logw), N,
+                n_batch, lg, buf, scratch);
+    if (threadIdx.x == 0) acc->summary_pending = 0;
+}
+
 }  // namespace
+
+void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_runs), dim3(kEvThreads), 0, s, arena, runs_dev);
+}
 
 void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_sweep,
                      hipStream_t s) {

@@ -24,6 +24,7 @@ struct RunDev {
     int32_t n_steps_max, min_ref, max_ref, prune_streak;
     int32_t term_kind, max_iter;
     int32_t C, G;              // walk tile: coordinates per lane, lanes per walker
+    int32_t dp, var;           // padded dimension G*C; kernel variant (family / slots)
     int32_t nprm;              // elements of the converted parameter block
     int32_t nprm_bytes_lds;    // bytes staged to LDS by the walk (0: read from global)
     double lo, hi, dt_init, delta_p, out_hi, out_lo, dt_down, dt_up, term_tol;
@@ -44,7 +45,7 @@ struct Acc {
     double log_z, log_x, log_z2, dt, lstar, log_xl_max, h, sigma_kl, sigma_mom;
     long long iter, evals, n_dead, steps_out, steps_in, prunes, nosave;
     unsigned long long it_outs, it_steps;
-    int32_t state, pad;
+    int32_t state, summary_pending;
 };
 
 // A walk work item: walkers [m_begin, m_end) of one run.
@@ -57,18 +58,6 @@ __host__ __device__ inline T *at(void *arena, int64_t off) {
     return reinterpret_cast<T *>(reinterpret_cast<char *>(arena) + off);
 }
 
-// Size in elements of the converted parameter block (run precision), without
-// the BF16 copy of P.
-inline int32_t converted_params(int kind, int d, int K) {
-    switch (kind) {
-        case GGNS_LIK_GAUSS_DIAG: return 2 * d + 1;             // mu, 1/sigma^2, const
-        case GGNS_LIK_GAUSS_FULL: return d + 1 + d * d;          // mu, const, P
-        case GGNS_LIK_SHELLS: return K * (d + 3);                // {c, r, 1/w^2, lognorm}
-        case GGNS_LIK_GMM_DIAG: return K * (2 * d + 1);          // {mu, 1/sigma^2, lognorm}
-    }
-    return 0;
-}
-
 // Launchers (defined in the .hip files).
 void launch_prepare(void *arena, const RunDev *runs_dev, int n_runs, const double *params,
                     hipStream_t s, int init_state);
@@ -76,6 +65,7 @@ int launch_init_class(void *arena, const RunDev *runs_dev, const Tile *tiles, in
                       int C, int kind, hipStream_t s);
 void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_sweep,
                      hipStream_t s);
+void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, hipStream_t s);
 void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s);
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
                       int prec, int C, int kind, size_t lds_bytes, hipStream_t s);

@@ -94,12 +94,70 @@ __device__ __forceinline__ double u24_open(uint32_t a) {
 
 // ---------------------------------------------------------------------------
 // Lane-group reductions (group of G lanes, G a power of two <= 64, aligned).
+// Offsets 1, 2, 4, 8 use DPP lane swizzles (quad permutes, half-row and row
+// mirrors) so they stay in the vector ALU; 16 and 32 cross rows through the
+// LDS permute path.  The butterfly leaves the same, bitwise identical sum in
+// every lane of the group (each step adds a pair in either order).
 // ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
+
+// Sum N values over the group at once (independent chains interleave).  The
+// four in-row levels are always issued and kept or dropped by a select on the
+// uniform group size, so the step has no branch for them; the two cross-row
+// levels sit behind a uniform branch that only groups of 32 or 64 lanes take.
+template <typename T, int N>
+__device__ __forceinline__ void group_sum_n(T (&v)[N], int G) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const T a1 = v[i] + dpp_mov<kDppXor1>(v[i]);
+        v[i] = (G > 1) ? a1 : v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const T a2 = v[i] + dpp_mov<kDppXor2>(v[i]);
+        v[i] = (G > 2) ? a2 : v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const T a4 = v[i] + dpp_mov<kDppHalfMirror>(v[i]);
+        v[i] = (G > 4) ? a4 : v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const T a8 = v[i] + dpp_mov<kDppMirror>(v[i]);
+        v[i] = (G > 8) ? a8 : v[i];
+    }
+    if (G > 16) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 16, 64);
+        if (G > 32) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 32, 64);
+        }
+    }
+}
 
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {
-    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    T a[1] = {v};
+    group_sum_n<T, 1>(a, G);
+    return a[0];
 }
 
 __device__ __forceinline__ bool group_any(bool pred, int G) {
@@ -109,162 +167,227 @@ __device__ __forceinline__ bool group_any(bool pred, int G) {
     return (b & m) != 0ull;
 }
 
-template <typename T>
-__device__ __forceinline__ T fast_exp(T v) { return exp(v); }
-template <>
-__device__ __forceinline__ float fast_exp<float>(float v) { return __expf(v); }
-template <typename T>
-__device__ __forceinline__ T fast_log(T v) { return log(v); }
-template <>
-__device__ __forceinline__ float fast_log<float>(float v) { return __logf(v); }
+// Scalar math per precision: hardware approximations in FP32 (v_exp, v_log,
+// v_sqrt, v_rcp; about one ulp), correctly rounded library calls in FP64.
+__device__ __forceinline__ float m_exp(float v) { return __expf(v); }
+__device__ __forceinline__ double m_exp(double v) { return exp(v); }
+__device__ __forceinline__ float m_log(float v) { return __logf(v); }
+__device__ __forceinline__ double m_log(double v) { return log(v); }
+__device__ __forceinline__ float m_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ double m_sqrt(double v) { return sqrt(v); }
+__device__ __forceinline__ float m_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double m_div(double a, double b) { return a / b; }
 
 // ---------------------------------------------------------------------------
-// Log-likelihood and score in the lane-group layout.
+// Log-likelihood, score and the two reflection dot products p.g and g.g, in the
+// lane-group layout.
 //
-// Converted parameter blocks (run precision T):
-//   GAUSS_DIAG: mu[d], iv[d] = 1/sigma^2, cst = sum(-log(2 pi)/2 - log sigma)
-//   GAUSS_FULL: mu[d], cst = -d log(2 pi)/2 + log det P / 2, P[d*d]
-//   SHELLS:     K blocks {c[d], r, iw2 = 1/w^2, lognorm = -log(2 pi w^2)/2}
-//   GMM_DIAG:   K blocks {mu[d], iv[d], lognorm = -log K + sum(-log(2 pi)/2 - log sigma)}
-// Every lane returns the same log L (xor-butterfly sums are bitwise identical
-// across the group); g[] receives the score of the lane's own coordinates
-// (zero on padding coordinates a >= d).
+// Converted parameter blocks (run precision T), laid out over the padded
+// dimension dp = G*C and, for mixtures, over KM component slots:
+//   GAUSS_DIAG: mu[dp], iv[dp] = 1/sigma^2, cst = sum(-log(2 pi)/2 - log sigma)
+//   GAUSS_FULL: mu[d], cst = -d log(2 pi)/2 + log det P / 2, P[d*d]   (unpadded)
+//   SHELLS:     KM blocks {c[dp], r, iw2 = 1/w^2, lognorm = -log(2 pi w^2)/2}
+//   GMM_DIAG:   KM blocks {mu[dp], iv[dp], lognorm = -log K + sum(-log(2 pi)/2 - log sigma)}
+// Padding coordinates hold zeros (positions and momenta are zero there too) and
+// padding components have lognorm = -inf, so both contribute exactly nothing
+// and the arithmetic needs no per-coordinate or per-component branch.
+// Every lane returns the same log L, p.g and g.g; g[] receives the score of the
+// lane's own coordinates.  Where the score is a combination of per-component
+// vectors, p.g and g.g are assembled from per-component dot products reduced in
+// the same round as the likelihood sums, so each step needs a single reduction
+// round (two for the mixture).
 // ---------------------------------------------------------------------------
+
+template <typename T>
+struct LikOut {
+    T l, pg, gg;
+};
+
+// Each lane keeps its own slice of the converted parameters in registers for
+// the whole walk (they never change inside a launch); load() reads it from the
+// staged block once.
+template <typename T, int C>
+struct DiagParams {
+    T mu[C], iv[C], cst;
+    __device__ __forceinline__ void load(const T *prm, int dp, int a0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            mu[c] = prm[a0 + c];
+            iv[c] = prm[dp + a0 + c];
+        }
+        cst = prm[2 * dp];
+    }
+};
+
+template <typename T, int C, int KM>
+struct ShellParams {
+    T cen[KM][C], rad[KM], iw2[KM], lnrm[KM];
+    __device__ __forceinline__ void load(const T *prm, int dp, int a0) {
+        const int stride = dp + 3;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) cen[k][c] = prm[k * stride + a0 + c];
+            rad[k] = prm[k * stride + dp];
+            iw2[k] = prm[k * stride + dp + 1];
+            lnrm[k] = prm[k * stride + dp + 2];
+        }
+    }
+};
+
+template <typename T, int C, int KM>
+struct GmmParams {
+    T mu[KM][C], iv[KM][C], lnrm[KM];
+    __device__ __forceinline__ void load(const T *prm, int dp, int a0) {
+        const int stride = 2 * dp + 1;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                mu[k][c] = prm[k * stride + a0 + c];
+                iv[k][c] = prm[k * stride + dp + a0 + c];
+            }
+            lnrm[k] = prm[k * stride + 2 * dp];
+        }
+    }
+};
+
+// The correlated Gaussian keeps P where it was staged (LDS or global) and
+// reads rows of it every step.
+template <typename T>
+struct FullParams {
+    const T *prm;
+    __device__ __forceinline__ void load(const T *p, int, int) { prm = p; }
+};
 
 template <typename T, int C>
-__device__ __forceinline__ T lik_gauss_diag(const T *prm, int d, int a0, int G, const T (&x)[C],
-                                            T (&g)[C]) {
-    const T *mu = prm, *iv = prm + d;
-    T q = T(0);
+__device__ __forceinline__ LikOut<T> lik_gauss_diag(const DiagParams<T, C> &P, int G,
+                                                    const T (&x)[C], const T (&p)[C], T (&g)[C]) {
+    T acc[3] = {T(0), T(0), T(0)};   // r.iv.r, p.g, g.g
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int a = a0 + c;
-        if (a < d) {
-            const T r = x[c] - mu[a];
-            const T t = r * iv[a];
-            q += r * t;
-            g[c] = -t;
-        } else {
-            g[c] = T(0);
-        }
+        const T r = x[c] - P.mu[c];
+        const T t = r * P.iv[c];
+        acc[0] += r * t;
+        acc[1] -= p[c] * t;
+        acc[2] += t * t;
+        g[c] = -t;
     }
-    q = group_sum(q, G);
-    return prm[2 * d] - T(0.5) * q;
+    group_sum_n<T, 3>(acc, G);
+    return {P.cst - T(0.5) * acc[0], acc[1], acc[2]};
 }
 
-template <typename T, int C>
-__device__ __forceinline__ T lik_shells(const T *prm, int d, int K, int a0, int G, const T (&x)[C],
-                                        T (&g)[C]) {
-    const int stride = d + 3;
-    T s[kMaxComp];
+// Shells: with u_k = x - c_k, the score is g = sum_k coef_k u_k, so
+// p.g = sum_k coef_k (p.u_k) and g.g = sum_kl coef_k coef_l (u_k.u_l).
+template <typename T, int C, int KM>
+__device__ __forceinline__ LikOut<T> lik_shells(const ShellParams<T, C, KM> &P, int G,
+                                                const T (&x)[C], const T (&p)[C], T (&g)[C]) {
+    constexpr int NB = KM * (KM - 1) / 2;
+    T v[2 * KM + NB];   // |u_k|^2, p.u_k, u_k.u_l (k < l)
 #pragma unroll
-    for (int k = 0; k < kMaxComp; ++k) {
-        s[k] = T(0);
-        if (k < K) {
-            const T *ck = prm + k * stride;
+    for (int i = 0; i < 2 * KM + NB; ++i) v[i] = T(0);
+    T u[KM][C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int a = a0 + c;
-                if (a < d) {
-                    const T dd = x[c] - ck[a];
-                    s[k] += dd * dd;
-                }
-            }
-            s[k] = group_sum(s[k], G);
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            u[k][c] = x[c] - P.cen[k][c];
+            v[k] += u[k][c] * u[k][c];
+            v[KM + k] += p[c] * u[k][c];
         }
+        int q = 2 * KM;
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+#pragma unroll
+            for (int l = k + 1; l < KM; ++l) v[q++] += u[k][c] * u[l][c];
     }
-    T lp[kMaxComp], rho[kMaxComp];
+    group_sum_n<T, 2 * KM + NB>(v, G);
+    T lp[KM], rho[KM], coef[KM];
     T lmax = T(-INFINITY);
 #pragma unroll
-    for (int k = 0; k < kMaxComp; ++k) {
-        if (k < K) {
-            const T *ck = prm + k * stride;
-            rho[k] = sqrt(s[k]);
-            const T e = rho[k] - ck[d];
-            lp[k] = ck[d + 2] - T(0.5) * e * e * ck[d + 1];
-            lmax = lp[k] > lmax ? lp[k] : lmax;
-        }
+    for (int k = 0; k < KM; ++k) {
+        rho[k] = m_sqrt(v[k]);
+        const T e = rho[k] - P.rad[k];
+        lp[k] = P.lnrm[k] - T(0.5) * e * e * P.iw2[k];
+        lmax = lp[k] > lmax ? lp[k] : lmax;
     }
-    T acc = T(0);
+    T sum = T(0);
 #pragma unroll
-    for (int k = 0; k < kMaxComp; ++k)
-        if (k < K) acc += exp(lp[k] - lmax);
-    const T l = lmax + log(acc);
+    for (int k = 0; k < KM; ++k) sum += m_exp(lp[k] - lmax);
+    const T l = lmax + m_log(sum);
 #pragma unroll
-    for (int c = 0; c < C; ++c) g[c] = T(0);
-#pragma unroll
-    for (int k = 0; k < kMaxComp; ++k) {
-        if (k < K) {
-            const T *ck = prm + k * stride;
-            const T coef = (rho[k] > T(0))
-                               ? -exp(lp[k] - l) * (rho[k] - ck[d]) * ck[d + 1] / rho[k]
-                               : T(0);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int a = a0 + c;
-                if (a < d) g[c] += coef * (x[c] - ck[a]);
-            }
-        }
+    for (int k = 0; k < KM; ++k) {
+        const T c_k = -m_div(m_exp(lp[k] - l) * (rho[k] - P.rad[k]) * P.iw2[k], rho[k]);
+        coef[k] = (rho[k] > T(0)) ? c_k : T(0);
     }
-    return l;
+    T pg = T(0), gg = T(0);
+    int q = 2 * KM;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        pg += coef[k] * v[KM + k];
+        gg += coef[k] * coef[k] * v[k];
+#pragma unroll
+        for (int l = k + 1; l < KM; ++l) gg += T(2) * coef[k] * coef[l] * v[q++];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T s = T(0);
+#pragma unroll
+        for (int k = 0; k < KM; ++k) s += coef[k] * u[k][c];
+        g[c] = s;
+    }
+    return {l, pg, gg};
 }
 
-template <typename T, int C>
-__device__ __forceinline__ T lik_gmm(const T *prm, int d, int K, int a0, int G, const T (&x)[C],
-                                     T (&g)[C]) {
-    const int stride = 2 * d + 1;
-    T q[kMaxComp];
+template <typename T, int C, int KM>
+__device__ __forceinline__ LikOut<T> lik_gmm(const GmmParams<T, C, KM> &P, int G, const T (&x)[C],
+                                             const T (&p)[C], T (&g)[C]) {
+    T q[KM];
+    T u[KM][C];
 #pragma unroll
-    for (int k = 0; k < kMaxComp; ++k) {
+    for (int k = 0; k < KM; ++k) {
         q[k] = T(0);
-        if (k < K) {
-            const T *mu = prm + k * stride, *iv = mu + d;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int a = a0 + c;
-                if (a < d) {
-                    const T r = x[c] - mu[a];
-                    q[k] += r * r * iv[a];
-                }
-            }
-            q[k] = group_sum(q[k], G);
+        for (int c = 0; c < C; ++c) {
+            const T r = x[c] - P.mu[k][c];
+            u[k][c] = r * P.iv[k][c];
+            q[k] += r * u[k][c];
         }
     }
+    group_sum_n<T, KM>(q, G);
     T lmax = T(-INFINITY);
 #pragma unroll
-    for (int k = 0; k < kMaxComp; ++k) {
-        if (k < K) {
-            q[k] = prm[k * stride + 2 * d] - T(0.5) * q[k];   // now lp_k
-            lmax = q[k] > lmax ? q[k] : lmax;
-        }
+    for (int k = 0; k < KM; ++k) {
+        q[k] = P.lnrm[k] - T(0.5) * q[k];   // log of component k
+        lmax = q[k] > lmax ? q[k] : lmax;
     }
-    T acc = T(0);
+    T sum = T(0);
 #pragma unroll
-    for (int k = 0; k < kMaxComp; ++k)
-        if (k < K) acc += exp(q[k] - lmax);
-    const T l = lmax + log(acc);
+    for (int k = 0; k < KM; ++k) sum += m_exp(q[k] - lmax);
+    const T l = lmax + m_log(sum);
+    T resp[KM];
 #pragma unroll
-    for (int c = 0; c < C; ++c) g[c] = T(0);
+    for (int k = 0; k < KM; ++k) resp[k] = m_exp(q[k] - l);
+    T acc[2] = {T(0), T(0)};
 #pragma unroll
-    for (int k = 0; k < kMaxComp; ++k) {
-        if (k < K) {
-            const T *mu = prm + k * stride, *iv = mu + d;
-            const T resp = exp(q[k] - l);
+    for (int c = 0; c < C; ++c) {
+        T s = T(0);
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int a = a0 + c;
-                if (a < d) g[c] -= resp * (x[c] - mu[a]) * iv[a];
-            }
-        }
+        for (int k = 0; k < KM; ++k) s -= resp[k] * u[k][c];
+        g[c] = s;
+        acc[0] += p[c] * s;
+        acc[1] += s * s;
     }
-    return l;
+    group_sum_n<T, 2>(acc, G);
+    return {l, acc[0], acc[1]};
 }
 
 // Correlated Gaussian on the vector ALUs: r goes through the group's LDS slot
 // xch[d] so that every lane can form its rows of P r.
 template <typename T, int C>
-__device__ __forceinline__ T lik_gauss_full(const T *prm, int d, int a0, int G, const T (&x)[C],
-                                            T (&g)[C], T *xch) {
+__device__ __forceinline__ LikOut<T> lik_gauss_full(const T *prm, int d, int a0, int G,
+                                                    const T (&x)[C], const T (&p)[C], T (&g)[C],
+                                                    T *xch) {
     const T *mu = prm;
     const T cst = prm[d];
     const T *P = prm + d + 1;
@@ -278,7 +401,7 @@ __device__ __forceinline__ T lik_gauss_full(const T *prm, int d, int a0, int G, 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    T q = T(0);
+    T acc[3] = {T(0), T(0), T(0)};   // r.y, p.g, g.g with g = -y
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int a = a0 + c;
@@ -287,34 +410,78 @@ __device__ __forceinline__ T lik_gauss_full(const T *prm, int d, int a0, int G, 
             const T *row = P + (int64_t)a * d;
             for (int j = 0; j < d; ++j) y += row[j] * xch[j];
         }
-        q += r[c] * y;
+        acc[0] += r[c] * y;
+        acc[1] -= p[c] * y;
+        acc[2] += y * y;
         g[c] = -y;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    q = group_sum(q, G);
-    return cst - T(0.5) * q;
+    group_sum_n<T, 3>(acc, G);
+    return {cst - T(0.5) * acc[0], acc[1], acc[2]};
+}
+
+// Kernel variants: the four families, with shells split by component count
+// (two or fewer, else up to kMaxComp) so the fused reduction carries only the
+// dot products it needs.
+enum { VAR_GAUSS_DIAG = 0, VAR_GAUSS_FULL = 1, VAR_SHELLS2 = 2, VAR_GMM = 3, VAR_SHELLS8 = 4 };
+
+__host__ __device__ inline int lik_variant(int kind, int K) {
+    if (kind == GGNS_LIK_SHELLS) return K <= 2 ? VAR_SHELLS2 : VAR_SHELLS8;
+    return kind;
 }
 
 // Family chosen at compile time so that each kernel instance only carries the
 // registers of its own likelihood.
-template <typename T, int C, int KIND>
-__device__ __forceinline__ T lik_eval(int K, const T *prm, int d, int a0, int G, const T (&x)[C],
-                                      T (&g)[C], T *xch) {
-    if constexpr (KIND == GGNS_LIK_GAUSS_DIAG) return lik_gauss_diag<T, C>(prm, d, a0, G, x, g);
-    else if constexpr (KIND == GGNS_LIK_SHELLS) return lik_shells<T, C>(prm, d, K, a0, G, x, g);
-    else if constexpr (KIND == GGNS_LIK_GMM_DIAG) return lik_gmm<T, C>(prm, d, K, a0, G, x, g);
-    else return lik_gauss_full<T, C>(prm, d, a0, G, x, g, xch);
+template <typename T, int C, int VAR>
+struct ParamsOf;
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_GAUSS_DIAG> { using type = DiagParams<T, C>; };
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_GAUSS_FULL> { using type = FullParams<T>; };
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_SHELLS2> { using type = ShellParams<T, C, 2>; };
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_SHELLS8> { using type = ShellParams<T, C, kMaxComp>; };
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_GMM> { using type = GmmParams<T, C, kMaxComp>; };
+
+template <typename T, int C, int VAR>
+__device__ __forceinline__ LikOut<T> lik_step(const typename ParamsOf<T, C, VAR>::type &P, int d,
+                                              int a0, int G, const T (&x)[C], const T (&p)[C],
+                                              T (&g)[C], T *xch) {
+    if constexpr (VAR == VAR_GAUSS_DIAG) return lik_gauss_diag<T, C>(P, G, x, p, g);
+    else if constexpr (VAR == VAR_SHELLS2) return lik_shells<T, C, 2>(P, G, x, p, g);
+    else if constexpr (VAR == VAR_SHELLS8) return lik_shells<T, C, kMaxComp>(P, G, x, p, g);
+    else if constexpr (VAR == VAR_GMM) return lik_gmm<T, C, kMaxComp>(P, G, x, p, g);
+    else return lik_gauss_full<T, C>(P.prm, d, a0, G, x, p, g, xch);
 }
 
-// Instantiate F<KIND>() for a run-time family.
-#define GGNS_DISPATCH_KIND(kind, CALL)                                   \
-    switch (kind) {                                                      \
-        case GGNS_LIK_GAUSS_DIAG: { constexpr int KIND_ = 0; CALL; break; } \
-        case GGNS_LIK_GAUSS_FULL: { constexpr int KIND_ = 1; CALL; break; } \
-        case GGNS_LIK_SHELLS: { constexpr int KIND_ = 2; CALL; break; }     \
-        default: { constexpr int KIND_ = 3; CALL; break; }                  \
+// Component slots of a variant's converted block.
+__host__ __device__ inline int variant_slots(int var) {
+    return var == VAR_SHELLS2 ? 2 : ((var == VAR_SHELLS8 || var == VAR_GMM) ? kMaxComp : 1);
+}
+
+// Elements of the converted parameter block (run precision) for a variant.
+__host__ __device__ inline int64_t converted_size(int var, int d, int dp) {
+    switch (var) {
+        case VAR_GAUSS_DIAG: return 2 * (int64_t)dp + 1;
+        case VAR_GAUSS_FULL: return (int64_t)d + 1 + (int64_t)d * d;
+        case VAR_SHELLS2: return 2 * ((int64_t)dp + 3);
+        case VAR_SHELLS8: return kMaxComp * ((int64_t)dp + 3);
+        default: return kMaxComp * (2 * (int64_t)dp + 1);
+    }
+}
+
+// Instantiate a call for a run-time variant (KIND_ is the compile-time value).
+#define GGNS_DISPATCH_KIND(var, CALL)                                    \
+    switch (var) {                                                       \
+        case VAR_GAUSS_DIAG: { constexpr int KIND_ = VAR_GAUSS_DIAG; CALL; break; } \
+        case VAR_GAUSS_FULL: { constexpr int KIND_ = VAR_GAUSS_FULL; CALL; break; } \
+        case VAR_SHELLS2: { constexpr int KIND_ = VAR_SHELLS2; CALL; break; }       \
+        case VAR_SHELLS8: { constexpr int KIND_ = VAR_SHELLS8; CALL; break; }       \
+        default: { constexpr int KIND_ = VAR_GMM; CALL; break; }                    \
     }
 
 }  // namespace ggns

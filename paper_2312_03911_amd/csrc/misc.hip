@@ -9,49 +9,63 @@ namespace {
 
 constexpr double kLog2Pi = 1.83787706640934548356;
 
-// Converted parameters in the run's precision; constants in FP64 first.
+// Converted parameters in the run's precision over the padded layout (padding
+// coordinates zero, padding components with lognorm = -inf); constants in
+// FP64 first.
 template <typename T>
 __device__ void convert_params(const RunDev &R, const double *raw, T *out) {
-    const int d = R.d, K = R.n_comp, t = threadIdx.x, nt = blockDim.x;
+    const int d = R.d, dp = R.dp, K = R.n_comp, t = threadIdx.x, nt = blockDim.x;
+    const int slots = variant_slots(R.var);
     if (R.kind == GGNS_LIK_GAUSS_DIAG) {
         const double *mu = raw, *sg = raw + d;
-        for (int a = t; a < d; a += nt) {
-            out[a] = (T)mu[a];
-            out[d + a] = (T)(1.0 / (sg[a] * sg[a]));
+        for (int a = t; a < dp; a += nt) {
+            out[a] = (a < d) ? (T)mu[a] : T(0);
+            out[dp + a] = (a < d) ? (T)(1.0 / (sg[a] * sg[a])) : T(0);
         }
         if (t == 0) {
             double c = 0.0;
             for (int a = 0; a < d; ++a) c += -0.5 * kLog2Pi - log(sg[a]);
-            out[2 * d] = (T)c;
+            out[2 * dp] = (T)c;
         }
     } else if (R.kind == GGNS_LIK_GAUSS_FULL) {
         for (int a = t; a < d; a += nt) out[a] = (T)raw[a];
         for (int64_t e = t; e < (int64_t)d * d; e += nt) out[d + 1 + e] = (T)raw[d + e];
         if (t == 0) out[d] = (T)(-0.5 * d * kLog2Pi + 0.5 * raw[d + (int64_t)d * d]);
     } else if (R.kind == GGNS_LIK_SHELLS) {
-        for (int kk = 0; kk < K; ++kk) {
+        for (int kk = 0; kk < slots; ++kk) {
             const double *blk = raw + kk * (d + 2);
-            T *o = out + kk * (d + 3);
-            for (int a = t; a < d; a += nt) o[a] = (T)blk[a];
+            T *o = out + kk * (dp + 3);
+            for (int a = t; a < dp; a += nt) o[a] = (kk < K && a < d) ? (T)blk[a] : T(0);
             if (t == 0) {
-                const double w = blk[d + 1];
-                o[d] = (T)blk[d];
-                o[d + 1] = (T)(1.0 / (w * w));
-                o[d + 2] = (T)(-0.5 * kLog2Pi - log(w));
+                if (kk < K) {
+                    const double w = blk[d + 1];
+                    o[dp] = (T)blk[d];
+                    o[dp + 1] = (T)(1.0 / (w * w));
+                    o[dp + 2] = (T)(-0.5 * kLog2Pi - log(w));
+                } else {
+                    o[dp] = T(0);
+                    o[dp + 1] = T(0);
+                    o[dp + 2] = (T)(-INFINITY);
+                }
             }
         }
     } else {
-        for (int kk = 0; kk < K; ++kk) {
+        for (int kk = 0; kk < slots; ++kk) {
             const double *mu = raw + kk * 2 * d, *sg = mu + d;
-            T *o = out + kk * (2 * d + 1);
-            for (int a = t; a < d; a += nt) {
-                o[a] = (T)mu[a];
-                o[d + a] = (T)(1.0 / (sg[a] * sg[a]));
+            T *o = out + kk * (2 * dp + 1);
+            for (int a = t; a < dp; a += nt) {
+                const bool on = kk < K && a < d;
+                o[a] = on ? (T)mu[a] : T(0);
+                o[dp + a] = on ? (T)(1.0 / (sg[a] * sg[a])) : T(0);
             }
             if (t == 0) {
-                double c = -log((double)K);
-                for (int a = 0; a < d; ++a) c += -0.5 * kLog2Pi - log(sg[a]);
-                o[2 * d] = (T)c;
+                if (kk < K) {
+                    double c = -log((double)K);
+                    for (int a = 0; a < d; ++a) c += -0.5 * kLog2Pi - log(sg[a]);
+                    o[2 * dp] = (T)c;
+                } else {
+                    o[2 * dp] = (T)(-INFINITY);
+                }
             }
         }
     }
@@ -114,7 +128,7 @@ init_points_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__r
     T *xch = reinterpret_cast<T *>(smem) + grp * (G * C);
     const T *prm = at<T>(arena, R.off_prm);
     const double w = R.hi - R.lo;
-    T x[C], g[C];
+    T x[C], g[C], p0[C];
     uint32_t u[4];
     int last_b = -1;
 #pragma unroll
@@ -130,7 +144,11 @@ init_points_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__r
             x[c] = (T)(R.lo + w * u24_open(word));
         }
     }
-    const T l = lik_eval<T, C, KIND>(R.n_comp, prm, d, a0, G, x, g, xch);
+#pragma unroll
+    for (int c = 0; c < C; ++c) p0[c] = T(0);
+    typename ParamsOf<T, C, KIND>::type P;
+    P.load(prm, R.dp, a0);
+    const T l = lik_step<T, C, KIND>(P, d, a0, G, x, p0, g, xch).l;
     if (valid) {
         T *xo = at<T>(arena, R.off_live_x) + (int64_t)i * d;
 #pragma unroll
@@ -195,10 +213,15 @@ loglike_kernel(void *arena, const RunDev *__restrict__ run, const T *__restrict_
     const bool valid = i < n;
     T *xch = reinterpret_cast<T *>(smem) + grp * (G * C);
     const T *prm = at<T>(arena, R.off_prm);
-    T x[C], g[C];
+    T x[C], g[C], p0[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) x[c] = (valid && a0 + c < d) ? xs[i * d + a0 + c] : T(0);
-    const T l = lik_eval<T, C, KIND>(R.n_comp, prm, d, a0, G, x, g, xch);
+    for (int c = 0; c < C; ++c) {
+        x[c] = (valid && a0 + c < d) ? xs[i * d + a0 + c] : T(0);
+        p0[c] = T(0);
+    }
+    typename ParamsOf<T, C, KIND>::type P;
+    P.load(prm, R.dp, a0);
+    const T l = lik_step<T, C, KIND>(P, d, a0, G, x, p0, g, xch).l;
     if (!valid) return;
     if (logl != nullptr && gl == 0) logl[i] = (double)l;
     if (grad != nullptr) {
@@ -281,16 +304,16 @@ int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, c
     const int C = run_host.C, G = run_host.G;
     if (run_host.prec == GGNS_FP64) {
         switch (C) {
-            case 1: e = loglike_t<double, 1>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
-            case 2: e = loglike_t<double, 2>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
-            case 4: e = loglike_t<double, 4>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+            case 1: e = loglike_t<double, 1>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
+            case 2: e = loglike_t<double, 2>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
+            case 4: e = loglike_t<double, 4>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
         }
     } else {
         switch (C) {
-            case 1: e = loglike_t<float, 1>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
-            case 2: e = loglike_t<float, 2>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
-            case 4: e = loglike_t<float, 4>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
-            case 8: e = loglike_t<float, 8>(arena, run_dev, x, n, logl, grad, gout, G, run_host.kind, s); break;
+            case 1: e = loglike_t<float, 1>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
+            case 2: e = loglike_t<float, 2>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
+            case 4: e = loglike_t<float, 4>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
+            case 8: e = loglike_t<float, 8>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
         }
     }
     return e == hipSuccess ? GGNS_OK : GGNS_EHIP;

@@ -14,11 +14,18 @@
 //
 // Layout: one walker per group of G lanes (G = 1..64, power of two), lane g
 // owning C consecutive coordinates [g*C, g*C + C) of x, p and the score in
-// registers for the whole walk.  Dot products (p.g, g.g) and the likelihood's
-// sums are xor-butterfly reductions inside the group.  The run's converted
-// parameters are staged in LDS once per block.  The only HBM traffic of a walk
-// is the gather of the start point and the reservoir writes.
+// registers for the whole walk.  The run's converted parameters (zero-padded
+// to G*C coordinates) are staged in LDS once per block.  A step is branch-free
+// apart from the rare events (a reservoir write, a prune, the end of a walker):
+// one fused xor-butterfly reduction round in DPP, selects for the reflection,
+// and the noise generated first so that it overlaps the reduction latency.
+// The only HBM traffic of a walk is the gather of its start point and its
+// reservoir writes.
 #include "ggns_device.h"
+
+#ifndef GGNS_WALK_WAVES
+#define GGNS_WALK_WAVES 1
+#endif
 
 namespace ggns {
 
@@ -38,31 +45,42 @@ __device__ __forceinline__ void normals4(const uint32_t (&w)[4], T (&z)[4]) {
     normals2(w[2], w[3], z[2], z[3]);
 }
 
+// Scatter the normals of this lane's stream blocks onto its C coordinates.
+// With C a multiple of four every lane starts on a block boundary and the
+// mapping is static; with C < 4 the lane takes words (a0 & 3) ... of its block.
+template <typename T, int C>
+__device__ __forceinline__ void take_block(const T (&z)[4], int i, int a0, T (&out)[C]) {
+    if constexpr (C >= 4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[4 * i + j] = z[j];
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c] = pick4(z, (a0 & 3) + c);
+    }
+}
+
 // d standard normals of walker `m` from the counter-based stream (initial and
-// pruning momenta); this lane computes its own coordinates.
+// pruning momenta); this lane computes its own coordinates, zero on padding.
 template <typename T, int C>
 __device__ __forceinline__ void momentum_draw(uint64_t seed, uint32_t m, uint32_t it, uint32_t sub,
                                               int a0, int d, T (&p)[C]) {
     constexpr int NB = (C + 3) / 4;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const int b = (a0 >> 2) + i;
         uint32_t w[4];
-        draw4(seed, (uint32_t)b, m, it, TAG_P0, sub, w);
+        draw4(seed, (uint32_t)((a0 >> 2) + i), m, it, TAG_P0, sub, w);
         T z[4];
         normals4(w, z);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int a = a0 + c;
-            if ((a >> 2) == b) p[c] = (a < d) ? pick4(z, a & 3) : T(0);
-        }
+        take_block<T, C>(z, i, a0, p);
     }
+#pragma unroll
+    for (int c = 0; c < C; ++c) p[c] = (a0 + c < d) ? p[c] : T(0);
 }
 
 }  // namespace
 
-template <typename T, int C, int KIND>
-__global__ void __launch_bounds__(kWalkThreads)
+template <typename T, int C, int VAR>
+__global__ void __launch_bounds__(kWalkThreads, GGNS_WALK_WAVES)
 walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles) {
     constexpr int NB = (C + 3) / 4;
     const Tile tile = tiles[blockIdx.x];
@@ -74,7 +92,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     __shared__ int next_walker;
     __shared__ unsigned long long blk_cnt[4];
 
-    const int d = R.d, G = R.G, K = R.n_comp;
+    const int d = R.d, dp = R.dp, G = R.G;
     const int ngroups = blockDim.x / G;
     const T *prm = at<T>(arena, R.off_prm);
     if (R.nprm_bytes_lds > 0) {
@@ -95,13 +113,20 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     const int gbase = lane & ~(G - 1);
     const int a0 = gl * C;
     T *xch = xch_all + grp * (G * C);
+    bool valid[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) valid[c] = a0 + c < d;
+    typename ParamsOf<T, C, VAR>::type P;
+    P.load(prm, dp, a0);
 
     const double lstar = acc->lstar;
     const T dt = (T)acc->dt;
     const uint32_t it = (uint32_t)acc->iter;
-    const T lo = (T)R.lo, hi = (T)R.hi, dp = (T)R.delta_p;
+    const T lo = (T)R.lo, hi = (T)R.hi, dpn = (T)R.delta_p;
     const uint64_t seed = R.seed;
     const int nsurv = R.n_live - R.n_kill;
+    const int min_ref = R.min_ref, max_ref = R.max_ref, n_steps_max = R.n_steps_max;
+    const int prune_streak = R.prune_streak;
     const int32_t *surv = at<int32_t>(arena, R.off_surv);
     int32_t *start_arr = at<int32_t>(arena, R.off_start);
     const T *live_x = at<T>(arena, R.off_live_x);
@@ -129,9 +154,8 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         T *wo = walk_x + (int64_t)mm * d;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int a = a0 + c;
-            x[c] = (a < d) ? xs[a] : T(0);
-            if (a < d) wo[a] = x[c];
+            x[c] = valid[c] ? xs[a0 + c] : T(0);
+            if (valid[c]) wo[a0 + c] = x[c];
         }
         out_l = live_logl[s];
         momentum_draw<T, C>(seed, (uint32_t)mm, it, 0u, a0, d, p);
@@ -148,55 +172,9 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     if (active) start_walker(m);
 
     while (__any(active)) {
-        // drift (Algorithm GGNS HSS: x += p dt)
-#pragma unroll
-        for (int c = 0; c < C; ++c) x[c] = x[c] + dt * p[c];
-        // log L and the score at the new position
-        const T l = lik_eval<T, C, KIND>(K, prm, d, a0, G, x, g, xch);
-        // outside the slice: out of the prior box, or log L <= L* (compared in FP64)
-        bool vm[C];
-        bool vany = false;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            vm[c] = (a0 + c < d) && (x[c] < lo || x[c] > hi);
-            vany = vany || vm[c];
-        }
-        const bool viol = group_any(vany, G);
-        const bool out = viol || ((double)l <= lstar);
-        if (active && trace_x != nullptr && steps < R.trace_steps) {
-            const int64_t row = (int64_t)steps * k + m;
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (a0 + c < d) trace_x[row * d + a0 + c] = x[c];
-            if (gl == 0) {
-                R.trace_logl[row] = (double)l;
-                R.trace_out[row] = out ? 1 : 0;
-            }
-        }
-        steps += 1;
-        // reflection (Eq. reflection with n = g / |g|; box faces flip their axis)
-        T pg = T(0), gg = T(0);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            pg += p[c] * g[c];
-            gg += g[c] * g[c];
-        }
-        pg = group_sum(pg, G);
-        gg = group_sum(gg, G);
-        if (out) {
-            if (viol) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) p[c] = vm[c] ? -p[c] : p[c];
-            } else if (isfinite(gg) && gg > T(0)) {
-                const T f = T(2) * pg / gg;
-#pragma unroll
-                for (int c = 0; c < C; ++c) p[c] = p[c] - f * g[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < C; ++c) p[c] = -p[c];
-            }
-        }
-        // momentum noise, componentwise: p *= 1 + delta_p * eps
+        // this step's noise and reservoir draw do not depend on the step, so
+        // they are generated first and overlap the reduction latency
+        T eps_c[C];
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             uint32_t w[4];
@@ -206,47 +184,77 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             w[3] = eps[i].next();
             T z[4];
             normals4(w, z);
-            const int b = (a0 >> 2) + i;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int a = a0 + c;
-                if ((a >> 2) == b) p[c] = p[c] * (T(1) + dp * pick4(z, a & 3));
-            }
+            take_block<T, C>(z, i, a0, eps_c);
         }
         const uint32_t ures = res.next();
+        // drift (Algorithm GGNS HSS: x += p dt)
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = x[c] + dt * p[c];
+        // log L, the score at the new position and the reflection dot products
+        const LikOut<T> lk = lik_step<T, C, VAR>(P, d, a0, G, x, p, g, xch);
+        // outside the slice: out of the prior box, or log L <= L* (compared in FP64)
+        bool vm[C];
+        bool vany = false;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            vm[c] = valid[c] && (x[c] < lo || x[c] > hi);
+            vany = vany || vm[c];
+        }
+        const bool viol = group_any(vany, G);
+        const bool out = viol || ((double)lk.l <= lstar);
+        if (trace_x != nullptr) {
+            if (active && steps < R.trace_steps) {
+                const int64_t row = (int64_t)steps * k + m;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (valid[c]) trace_x[row * d + a0 + c] = x[c];
+                if (gl == 0) {
+                    R.trace_logl[row] = (double)lk.l;
+                    R.trace_out[row] = out ? 1 : 0;
+                }
+            }
+        }
+        steps += 1;
+        // reflection (Eq. reflection with n = g / |g|; box faces flip their
+        // axis; a zero or non-finite score flips the whole momentum), as selects
+        const bool use_g = out && !viol && isfinite(lk.gg) && lk.gg > T(0);
+        const bool flip_all = out && !viol && !use_g;
+        const T f = use_g ? m_div(T(2) * lk.pg, lk.gg) : T(0);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const bool flip = flip_all || (out && vm[c]);
+            const T pr = (flip ? -p[c] : p[c]) - f * g[c];
+            // momentum noise, componentwise: p *= 1 + delta_p * eps
+            p[c] = pr * (T(1) + dpn * eps_c[c]);
+        }
         nref += out ? 1 : 0;
         outs += out ? 1 : 0;
         streak = out ? streak + 1 : 0;
         // trajectory preservation: size-one reservoir over the kept points
-        if (!out) {
-            bool take;
-            if (nref >= R.min_ref) {
-                nsave += 1;
-                take = (uint64_t)ures * (uint64_t)nsave < (1ull << 32);
-            } else {
-                take = (nsave == 0);
-            }
-            if (take && active) {
-                T *wo = walk_x + (int64_t)m * d;
+        const bool keep = !out && nref >= min_ref;
+        nsave += keep ? 1 : 0;
+        const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32))
+                                        : (nsave == 0));
+        if (take && active) {
+            T *wo = walk_x + (int64_t)m * d;
 #pragma unroll
-                for (int c = 0; c < C; ++c)
-                    if (a0 + c < d) wo[a0 + c] = x[c];
-                out_l = (double)l;
-            }
+            for (int c = 0; c < C; ++c)
+                if (valid[c]) wo[a0 + c] = x[c];
+            out_l = (double)lk.l;
         }
         // pruning: back to the start with fresh momentum
-        if (R.prune_streak > 0 && streak >= R.prune_streak) {
+        if (prune_streak > 0 && streak >= prune_streak) {
             if (active) {
                 const T *xs = live_x + (int64_t)s * d;
 #pragma unroll
-                for (int c = 0; c < C; ++c) x[c] = (a0 + c < d) ? xs[a0 + c] : T(0);
+                for (int c = 0; c < C; ++c) x[c] = valid[c] ? xs[a0 + c] : T(0);
             }
             nprune += 1;
             momentum_draw<T, C>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
             nref = 0;
             streak = 0;
         }
-        const bool done = !(steps < R.n_steps_max && (R.max_ref == 0 || nref < R.max_ref));
+        const bool done = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
         const bool need = active && done;
         if (need && gl == 0) {
             walk_logl[m] = out_l;
@@ -286,27 +294,27 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 
 template <typename T, int C>
 static hipError_t launch_walk_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
-                                int kind, size_t lds, hipStream_t s) {
-    GGNS_DISPATCH_KIND(kind, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_>), dim3(n_tiles),
-                                                dim3(kWalkThreads), lds, s, arena, runs, tiles));
+                                int var, size_t lds, hipStream_t s) {
+    GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_>), dim3(n_tiles),
+                                               dim3(kWalkThreads), lds, s, arena, runs, tiles));
     return hipGetLastError();
 }
 
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int prec,
-                      int C, int kind, size_t lds, hipStream_t s) {
+                      int C, int var, size_t lds, hipStream_t s) {
     hipError_t e = hipErrorInvalidValue;
     if (prec == GGNS_FP64) {
         switch (C) {
-            case 1: e = launch_walk_t<double, 1>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
-            case 2: e = launch_walk_t<double, 2>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
-            case 4: e = launch_walk_t<double, 4>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 1: e = launch_walk_t<double, 1>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
+            case 2: e = launch_walk_t<double, 2>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
+            case 4: e = launch_walk_t<double, 4>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
         }
     } else {
         switch (C) {
-            case 1: e = launch_walk_t<float, 1>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
-            case 2: e = launch_walk_t<float, 2>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
-            case 4: e = launch_walk_t<float, 4>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
-            case 8: e = launch_walk_t<float, 8>(arena, runs_dev, tiles, n_tiles, kind, lds, s); break;
+            case 1: e = launch_walk_t<float, 1>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
+            case 2: e = launch_walk_t<float, 2>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
+            case 4: e = launch_walk_t<float, 4>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
+            case 8: e = launch_walk_t<float, 8>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
         }
     }
     return e == hipSuccess ? GGNS_OK : GGNS_EHIP;

@@ -109,6 +109,9 @@ class Engine:
         _lib.check(self.L.ggns_evidence_update(self.ctx, int(final_sweep), self._stream()),
                    "ggns_evidence_update")
 
+    def finalize(self):
+        _lib.check(self.L.ggns_finalize(self.ctx, self._stream()), "ggns_finalize")
+
     def hss_walk(self):
         _lib.check(self.L.ggns_hss_walk(self.ctx, self._stream()), "ggns_hss_walk")
 
@@ -148,7 +151,8 @@ class Engine:
             self.step_block(poll_every, use_graph)
             st = self.stats()
             if all(s["state"] != _lib.RUN_ACTIVE for s in st):
-                return st
+                self.finalize()
+                return self.stats()
         raise RuntimeError("runs did not terminate")
 
     # ------------------------------------------------------------------ state

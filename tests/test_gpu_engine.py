@@ -124,6 +124,7 @@ def test_forced_final_sweep(torch, orc):
     eng = _engine([cfg])
     eng.iterate(5)
     eng.evidence_update(final_sweep=True)
+    eng.finalize()
     o = orc.Oracle(cfg).init()
     for _ in range(5):
         o.iterate()

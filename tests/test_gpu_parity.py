@@ -52,6 +52,8 @@ def _load_state(torch, eng, o, r, X):
 CASES = [
     ("gauss2d_fp64", lambda: inputs.config_gauss2d(seed=11), 1e-10, 1e-9),
     ("shells32_fp32", lambda: inputs.config_shells(d=32, n_live=1000, seed=12), 1e-4, 1e-4),
+    ("shells32_fp64", lambda: inputs.config_shells(d=32, n_live=1000, seed=12, precision="fp64"),
+     1e-10, 1e-9),
     ("gmm16_fp32", lambda: inputs.config_gmm(d=16, n_live=600, n_comp=8, seed=13, param_seed=5),
      1e-4, 1e-4),
     ("gauss_diag24_fp32", lambda: inputs.RunConfig(
@@ -91,11 +93,23 @@ def test_kill_and_walk_trace_match_oracle(torch, orc, name, make, tol, tau):
     eng = _engine([cfg])
     o = orc.Oracle(cfg, trace_steps=T).init()
     if cfg.kind == "shells":
-        X = inputs.uniform_points(cfg.n_live, cfg.d, -3.0, 3.0, seed=99)
-        X[:, 0] += np.where(np.arange(cfg.n_live) % 2 == 0, 2.5, -2.5)
+        # a mid-run state: points around both shells and the step the run has
+        # adapted to by then.  (At the first iteration's step, 0.1 of the prior
+        # width times |p| ~ sqrt(d), the thin shell is a strongly chaotic
+        # billiard: each bounce multiplies the FP32-vs-FP64 difference several
+        # fold, which no short-walk tolerance can absorb.)
+        rng = np.random.default_rng(99)
+        v = rng.standard_normal((cfg.n_live, cfg.d))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        X = v * rng.uniform(1.7, 2.3, size=(cfg.n_live, 1))
+        X[:, 0] += np.where(np.arange(cfg.n_live) % 2 == 0, 3.5, -3.5)
+        dt = 0.005 * (cfg.hi - cfg.lo)
     else:
         X = inputs.uniform_points(cfg.n_live, cfg.d, cfg.lo, cfg.hi, seed=99)
+        dt = cfg.dt_init * (cfg.hi - cfg.lo)
     Xo = _load_state(torch, eng, o, 0, X)
+    eng.write_vars(0, -math.inf, 0.0, dt, 0)
+    o.set_state(dt=dt)
     tx, tl, to = eng.set_trace(0, T)
     eng.evidence_update()
     o.evidence_update()
