@@ -97,7 +97,7 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         if (C > 8 || (D.precision == GGNS_FP64 && C > 4)) return GGNS_EUNSUPPORTED;
         R.C = C; R.G = G;
         R.dp = G * C;
-        R.var = lik_variant(D.lik_kind, R.n_comp);
+        R.var = lik_variant(D.lik_kind, R.n_comp, D.precision);
         const int64_t es = (D.precision == GGNS_FP64) ? 8 : 4;
         R.nprm = (int32_t)converted_size(R.var, D.d, R.dp);
         const int64_t prm_bytes = (int64_t)R.nprm * es;
@@ -199,13 +199,20 @@ void build_classes(ggns_ctx *c) {
         c->init_classes.push_back(w);
     }
     if (!mfma_runs.empty()) {
-        Class w{GGNS_FP32_BF16MMA, 0, GGNS_LIK_GAUSS_FULL, true, (int64_t)c->tiles_host.size(), 0, 0};
-        for (int r : mfma_runs) add_tiles(r, c->plan.runs[r].n_kill, 16);
-        w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
-        c->walk_classes.push_back(w);
+        // matrix-core walk: one class per padded dimension (a multiple of 32),
+        // 64 walkers (four wavefronts of 16) per tile
+        std::map<int, std::vector<int>> by_dp;
+        for (int r : mfma_runs) by_dp[(c->plan.runs[r].d + 31) / 32 * 32].push_back(r);
+        for (auto &kv : by_dp) {
+            Class w{GGNS_FP32_BF16MMA, kv.first, GGNS_LIK_GAUSS_FULL, true,
+                    (int64_t)c->tiles_host.size(), 0, 0};
+            for (int r : kv.second) add_tiles(r, c->plan.runs[r].n_kill, 64);
+            w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
+            c->walk_classes.push_back(w);
+        }
         // prior draws of MMA runs on the FP32 vector path (one class per C)
         for (int r : mfma_runs) {
-            Class i{GGNS_FP32, c->plan.runs[r].C, GGNS_LIK_GAUSS_FULL, false,
+            Class i{GGNS_FP32, c->plan.runs[r].C, VAR_GAUSS_FULL_BF16, false,
                     (int64_t)c->tiles_host.size(), 0, 0};
             add_tiles(r, c->plan.runs[r].n_live, kWalkThreads / c->plan.runs[r].G);
             i.n_tiles = (int)(c->tiles_host.size() - i.tile_off);
@@ -234,11 +241,6 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
     c->params = params_dev;
     c->n_params = n_params;
     build_classes(c);
-    for (const Class &w : c->walk_classes)
-        if (w.mfma && launch_walk_mfma(nullptr, nullptr, nullptr, 0, 0, nullptr) == GGNS_EUNSUPPORTED) {
-            delete c;
-            return GGNS_EUNSUPPORTED;
-        }
     // MMA runs convert P to FP32 too: their prior draws and the stand-alone
     // likelihood use the FP32 vector path
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -304,7 +306,7 @@ int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
         int rc;
         if (w.mfma)
             rc = launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                  w.n_tiles, 0, s);
+                                  w.n_tiles, w.C, s);
         else
             rc = launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
                                    w.n_tiles, w.prec, w.C, w.kind, w.lds, s);
@@ -397,7 +399,6 @@ int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl
     if (ctx == nullptr) return GGNS_ESTATE;
     if (run < 0 || run >= (int)ctx->plan.runs.size() || trace_steps < 0) return GGNS_EINVAL;
     if (trace_x != nullptr && (trace_logl == nullptr || trace_out == nullptr)) return GGNS_EINVAL;
-    if (trace_x != nullptr && ctx->plan.runs[run].prec == GGNS_FP32_BF16MMA) return GGNS_EUNSUPPORTED;
     RunDev &R = ctx->plan.runs[run];
     R.trace_x = trace_x;
     R.trace_logl = trace_x ? trace_logl : nullptr;

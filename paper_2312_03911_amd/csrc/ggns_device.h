@@ -383,8 +383,13 @@ __device__ __forceinline__ LikOut<T> lik_gmm(const GmmParams<T, C, KM> &P, int G
 }
 
 // Correlated Gaussian on the vector ALUs: r goes through the group's LDS slot
-// xch[d] so that every lane can form its rows of P r.
-template <typename T, int C>
+// xch[d] so that every lane can form its rows of P r.  With BF16 set, the
+// product uses r rounded to BF16 (P was rounded when converted): the
+// arithmetic of the matrix-core walk, for the prior draws and stand-alone
+// evaluations of a BF16 run.
+__device__ __forceinline__ float round_bf16(float v) { return (float)(__bf16)v; }
+
+template <typename T, int C, bool BF16 = false>
 __device__ __forceinline__ LikOut<T> lik_gauss_full(const T *prm, int d, int a0, int G,
                                                     const T (&x)[C], const T (&p)[C], T (&g)[C],
                                                     T *xch) {
@@ -396,7 +401,11 @@ __device__ __forceinline__ LikOut<T> lik_gauss_full(const T *prm, int d, int a0,
     for (int c = 0; c < C; ++c) {
         const int a = a0 + c;
         r[c] = (a < d) ? x[c] - mu[a] : T(0);
-        if (a < d) xch[a] = r[c];
+        if constexpr (BF16) {
+            if (a < d) xch[a] = round_bf16(r[c]);
+        } else {
+            if (a < d) xch[a] = r[c];
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -425,10 +434,18 @@ __device__ __forceinline__ LikOut<T> lik_gauss_full(const T *prm, int d, int a0,
 // Kernel variants: the four families, with shells split by component count
 // (two or fewer, else up to kMaxComp) so the fused reduction carries only the
 // dot products it needs.
-enum { VAR_GAUSS_DIAG = 0, VAR_GAUSS_FULL = 1, VAR_SHELLS2 = 2, VAR_GMM = 3, VAR_SHELLS8 = 4 };
+enum {
+    VAR_GAUSS_DIAG = 0,
+    VAR_GAUSS_FULL = 1,
+    VAR_SHELLS2 = 2,
+    VAR_GMM = 3,
+    VAR_SHELLS8 = 4,
+    VAR_GAUSS_FULL_BF16 = 5
+};
 
-__host__ __device__ inline int lik_variant(int kind, int K) {
+__host__ __device__ inline int lik_variant(int kind, int K, int prec) {
     if (kind == GGNS_LIK_SHELLS) return K <= 2 ? VAR_SHELLS2 : VAR_SHELLS8;
+    if (kind == GGNS_LIK_GAUSS_FULL && prec == GGNS_FP32_BF16MMA) return VAR_GAUSS_FULL_BF16;
     return kind;
 }
 
@@ -440,6 +457,8 @@ template <typename T, int C>
 struct ParamsOf<T, C, VAR_GAUSS_DIAG> { using type = DiagParams<T, C>; };
 template <typename T, int C>
 struct ParamsOf<T, C, VAR_GAUSS_FULL> { using type = FullParams<T>; };
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_GAUSS_FULL_BF16> { using type = FullParams<T>; };
 template <typename T, int C>
 struct ParamsOf<T, C, VAR_SHELLS2> { using type = ShellParams<T, C, 2>; };
 template <typename T, int C>
@@ -455,6 +474,8 @@ __device__ __forceinline__ LikOut<T> lik_step(const typename ParamsOf<T, C, VAR>
     else if constexpr (VAR == VAR_SHELLS2) return lik_shells<T, C, 2>(P, G, x, p, g);
     else if constexpr (VAR == VAR_SHELLS8) return lik_shells<T, C, kMaxComp>(P, G, x, p, g);
     else if constexpr (VAR == VAR_GMM) return lik_gmm<T, C, kMaxComp>(P, G, x, p, g);
+    else if constexpr (VAR == VAR_GAUSS_FULL_BF16)
+        return lik_gauss_full<T, C, true>(P.prm, d, a0, G, x, p, g, xch);
     else return lik_gauss_full<T, C>(P.prm, d, a0, G, x, p, g, xch);
 }
 
@@ -467,7 +488,8 @@ __host__ __device__ inline int variant_slots(int var) {
 __host__ __device__ inline int64_t converted_size(int var, int d, int dp) {
     switch (var) {
         case VAR_GAUSS_DIAG: return 2 * (int64_t)dp + 1;
-        case VAR_GAUSS_FULL: return (int64_t)d + 1 + (int64_t)d * d;
+        case VAR_GAUSS_FULL:
+        case VAR_GAUSS_FULL_BF16: return (int64_t)d + 1 + (int64_t)d * d;
         case VAR_SHELLS2: return 2 * ((int64_t)dp + 3);
         case VAR_SHELLS8: return kMaxComp * ((int64_t)dp + 3);
         default: return kMaxComp * (2 * (int64_t)dp + 1);
@@ -481,6 +503,7 @@ __host__ __device__ inline int64_t converted_size(int var, int d, int dp) {
         case VAR_GAUSS_FULL: { constexpr int KIND_ = VAR_GAUSS_FULL; CALL; break; } \
         case VAR_SHELLS2: { constexpr int KIND_ = VAR_SHELLS2; CALL; break; }       \
         case VAR_SHELLS8: { constexpr int KIND_ = VAR_SHELLS8; CALL; break; }       \
+        case VAR_GAUSS_FULL_BF16: { constexpr int KIND_ = VAR_GAUSS_FULL_BF16; CALL; break; } \
         default: { constexpr int KIND_ = VAR_GMM; CALL; break; }                    \
     }
 

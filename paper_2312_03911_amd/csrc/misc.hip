@@ -28,8 +28,11 @@ __device__ void convert_params(const RunDev &R, const double *raw, T *out) {
             out[2 * dp] = (T)c;
         }
     } else if (R.kind == GGNS_LIK_GAUSS_FULL) {
+        // BF16 runs keep P rounded to BF16 (held in FP32) for their vector-ALU paths
+        const bool bf = R.prec == GGNS_FP32_BF16MMA;
         for (int a = t; a < d; a += nt) out[a] = (T)raw[a];
-        for (int64_t e = t; e < (int64_t)d * d; e += nt) out[d + 1 + e] = (T)raw[d + e];
+        for (int64_t e = t; e < (int64_t)d * d; e += nt)
+            out[d + 1 + e] = bf ? (T)round_bf16((float)raw[d + e]) : (T)raw[d + e];
         if (t == 0) out[d] = (T)(-0.5 * d * kLog2Pi + 0.5 * raw[d + (int64_t)d * d]);
     } else if (R.kind == GGNS_LIK_SHELLS) {
         for (int kk = 0; kk < slots; ++kk) {
@@ -80,14 +83,22 @@ __global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, con
     else
         convert_params<float>(R, raw, at<float>(arena, R.off_prm));
     if (R.prec == GGNS_FP32_BF16MMA && R.off_prm_bf16 >= 0) {
-        // P rounded to BF16 (round to nearest even, via FP32), stored row-major
-        // [d_pad][d_pad] with zero padding; the MMA walk stages it into LDS.
-        const int d = R.d, dp = (d + 31) & ~31;
+        // P rounded to BF16 (round to nearest even, via FP32) in the order the
+        // matrix-core walk reads it: tiles (mb, kb) of 64 lanes x 8 values, lane
+        // l holding row l%16 and columns 8(l/16)+j of the tile, with the rows and
+        // columns relabelled so that output row 4q+j of M-block mb is dimension
+        // qQ + 4mb + j and K row 8q+j of K-block kb is dimension qQ + 8kb + j
+        // (Q = dp/4).  Padding entries are zero.
+        const int d = R.d, dp = (d + 31) & ~31, Q = dp / 4, KB = dp / 32;
         uint16_t *pb = at<uint16_t>(arena, R.off_prm_bf16);
         const double *P = raw + d;
         for (int64_t e = threadIdx.x; e < (int64_t)dp * dp; e += blockDim.x) {
-            const int i = (int)(e / dp), j = (int)(e % dp);
-            float f = (i < d && j < d) ? (float)P[(int64_t)i * d + j] : 0.0f;
+            const int t = (int)(e / 512), lane = (int)((e / 8) % 64), j = (int)(e % 8);
+            const int mb = t / KB, kb = t % KB;
+            const int ro = lane % 16, qk = lane / 16;
+            const int o = (ro / 4) * Q + 4 * mb + (ro % 4);
+            const int i = qk * Q + 8 * kb + j;
+            const float f = (o < d && i < d) ? (float)P[(int64_t)o * d + i] : 0.0f;
             uint32_t b = __float_as_uint(f);
             b += 0x7FFFu + ((b >> 16) & 1u);
             pb[e] = (uint16_t)(b >> 16);
@@ -304,16 +315,16 @@ int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, c
     const int C = run_host.C, G = run_host.G;
     if (run_host.prec == GGNS_FP64) {
         switch (C) {
-            case 1: e = loglike_t<double, 1>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
-            case 2: e = loglike_t<double, 2>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
-            case 4: e = loglike_t<double, 4>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
+            case 1: e = loglike_t<double, 1>(arena, run_dev, x, n, logl, grad, gout, G, run_host.var, s); break;
+            case 2: e = loglike_t<double, 2>(arena, run_dev, x, n, logl, grad, gout, G, run_host.var, s); break;
+            case 4: e = loglike_t<double, 4>(arena, run_dev, x, n, logl, grad, gout, G, run_host.var, s); break;
         }
     } else {
         switch (C) {
-            case 1: e = loglike_t<float, 1>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
-            case 2: e = loglike_t<float, 2>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
-            case 4: e = loglike_t<float, 4>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
-            case 8: e = loglike_t<float, 8>(arena, run_dev, x, n, logl, grad, gout, G, lik_variant(run_host.kind, run_host.n_comp), s); break;
+            case 1: e = loglike_t<float, 1>(arena, run_dev, x, n, logl, grad, gout, G, run_host.var, s); break;
+            case 2: e = loglike_t<float, 2>(arena, run_dev, x, n, logl, grad, gout, G, run_host.var, s); break;
+            case 4: e = loglike_t<float, 4>(arena, run_dev, x, n, logl, grad, gout, G, run_host.var, s); break;
+            case 8: e = loglike_t<float, 8>(arena, run_dev, x, n, logl, grad, gout, G, run_host.var, s); break;
         }
     }
     return e == hipSuccess ? GGNS_OK : GGNS_EHIP;

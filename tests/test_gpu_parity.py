@@ -64,6 +64,11 @@ CASES = [
                                                      precision="fp32", n_steps_max=60), 1e-4, 1e-4),
     ("shells5_fp64", lambda: inputs.config_shells(d=5, n_live=200, seed=16, precision="fp64"),
      1e-10, 1e-9),
+    # BF16 matrix-core walk: compared with the oracle's BF16-operand emulation
+    ("corr40_bf16", lambda: inputs.config_corr_gauss(d=40, n_live=300, seed=17, param_seed=8,
+                                                     precision="bf16mma", n_steps_max=60), 1e-4, 1e-4),
+    ("corr128_bf16", lambda: inputs.config_corr_gauss(d=128, n_live=256, seed=18, param_seed=9,
+                                                      precision="bf16mma"), 1e-4, 1e-4),
 ]
 
 
@@ -79,7 +84,7 @@ def test_init_matches_oracle(torch, orc, name, make, tol, tau):
     assert err < (1e-15 if cfg.precision == "fp64" else 1e-7)
     l = _np(eng.live_logl(0))
     rel = np.abs(l - o.live_logl) / np.maximum(1.0, np.abs(o.live_logl))
-    assert rel.max() < (1e-12 if cfg.precision == "fp64" else 2e-5)
+    assert rel.max() < {"fp64": 1e-12, "fp32": 2e-5, "bf16mma": 1e-4}[cfg.precision]
     st = eng.stats()[0]
     assert st["state"] == 0 and st["evals"] == cfg.n_live
     assert abs(st["dt"] - cfg.dt_init * (cfg.hi - cfg.lo)) < 1e-15
@@ -146,9 +151,9 @@ def test_kill_and_walk_trace_match_oracle(torch, orc, name, make, tol, tau):
         err = np.abs(gx[:cut, m] - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), width)
         worst = max(worst, err.max())
         np.testing.assert_array_equal(go[:cut, m], o.trace_out[:cut, m])
-        lref, _ = orc.loglike(cfg, gx[:cut, m])
+        lref, _ = orc.loglike(cfg, gx[:cut, m], bf16=cfg.precision == "bf16mma")
         lrel = np.abs(gl[:cut, m] - lref) / np.maximum(1.0, np.abs(lref))
-        assert lrel.max() < (1e-12 if tol < 1e-6 else 2e-5)
+        assert lrel.max() < (1e-12 if tol < 1e-6 else (1e-4 if cfg.precision == "bf16mma" else 2e-5))
         compared += 1
     assert worst < tol, worst
     assert masked <= max(2, 0.02 * cfg.n_kill), masked
@@ -163,12 +168,14 @@ def test_loglike_and_adjoint_match_oracle(torch, orc, name, make, tol, tau):
     xd = torch.from_numpy(X).to(eng.device, eng._fdtype(0))
     Xr = _np(xd).astype(np.float64)
     l, g = eng.loglike(0, xd)
-    lo_, go_ = orc.loglike(cfg, Xr)
+    bf = cfg.precision == "bf16mma"
+    lo_, go_ = orc.loglike(cfg, Xr, bf16=bf)
     torch.cuda.synchronize()
-    rel = 1e-12 if cfg.precision == "fp64" else 1e-5
+    rel = {"fp64": 1e-12, "fp32": 1e-5, "bf16mma": 1e-4}[cfg.precision]
     assert np.all(np.abs(_np(l) - lo_) <= rel * np.maximum(1.0, np.abs(lo_)))
     gs = np.abs(go_).max(axis=1, keepdims=True)
-    assert np.all(np.abs(_np(g) - go_) <= (1e-10 if cfg.precision == "fp64" else 2e-4) * np.maximum(gs, 1.0))
+    assert np.all(np.abs(_np(g) - go_) <= {"fp64": 1e-10, "fp32": 2e-4, "bf16mma": 5e-3}[cfg.precision]
+                  * np.maximum(gs, 1.0))
     gout = torch.linspace(-2.0, 3.0, 257, dtype=torch.float64, device=eng.device)
     gx = eng.loglike_vjp(0, xd, gout)
     np.testing.assert_allclose(_np(gx), _np(g) * _np(gout)[:, None], rtol=1e-6, atol=1e-6 * gs.max())
