@@ -68,22 +68,66 @@ def flops_per_eval(cfg, out_frac: float) -> float:
 
 
 def cpu_baseline(cfgs, budget_s: float = 12.0):
-    """The oracle on the host cores, on a bounded sample: iterations of the
-    first run until the time budget is used."""
+    """The oracle on the host cores, on a bounded sample of the workload: its
+    runs in order (cycling if they finish early) until the time budget is used;
+    a run cut by the budget counts the iterations it completed."""
     import oracle.oracle as O
     O.build(force=False)
-    cfg = cfgs[0]
-    o = O.Oracle(cfg).init()
     t0 = time.perf_counter()
-    e0 = o.st.evals
-    it = 0
-    while o.active and time.perf_counter() - t0 < budget_s:
-        o.iterate()
-        it += 1
+    ev, whole, its, j = 0, 0, 0, 0
+    last = ""
+    while time.perf_counter() - t0 < budget_s:
+        cfg = cfgs[j % len(cfgs)]
+        o = O.Oracle(cfg).init()
+        it = 0
+        while o.active and time.perf_counter() - t0 < budget_s:
+            o.iterate()
+            it += 1
+        if not o.active:
+            whole += 1
+        else:
+            last = f" + {it} iterations of {cfg.name}"
+        ev += o.st.evals
+        its += it
+        j += 1
     dt = time.perf_counter() - t0
-    ev = o.st.evals - e0
     return {"value": ev / dt, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{it} iterations of run 0 ({cfg.name}), {ev} walker steps in {dt:.1f} s"}
+            "sample": f"{whole} whole runs{last} of the workload ({its} iterations, "
+                      f"{ev} evaluations) in {dt:.1f} s"}
+
+
+def plain_baseline(cfgs, fused_value: float, fused_ms_per_run: float, fused_stats, truth,
+                   budget_s: float = 20.0):
+    """The plain FP64 GPU method (one thread per walker, one launch per step,
+    state in HBM, runs one after another) on the workload's runs switched to
+    FP64, as many whole runs as fit the budget; its log Z next to the fused
+    FP32 estimate of the same runs."""
+    import torch
+
+    from paper_2312_03911_amd.engine import Engine
+    evals, secs, dz, dfz = 0, 0.0, [], []
+    n = 0
+    for j, c in enumerate(cfgs):
+        if secs > budget_s:
+            break
+        eng = Engine([c.replace(precision="fp64")], device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = eng.run(poll_every=8, plain=True)[0]
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        eng.close()
+        evals += st["evals"]
+        dz.append(st["log_z"] - truth[j])
+        dfz.append(st["log_z"] - fused_stats[j]["log_z"])
+        n += 1
+    value = evals / secs
+    return {"value": value, "unit": "evals/s", "kind": "plain FP64 per-step GPU walk",
+            "runs": n, "ms_per_run": 1e3 * secs / n, "fused_ms_per_run": fused_ms_per_run,
+            "speedup": fused_value / value,
+            "logz_minus_closed_form_mean": float(np.mean(dz)),
+            "logz_minus_fused_mean": float(np.mean(dfz)),
+            "logz_minus_fused_sd": float(np.std(dfz))}
 
 
 def main():
@@ -94,6 +138,7 @@ def main():
     ap.add_argument("--workload", default="shells32x10")
     ap.add_argument("--poll", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
@@ -110,7 +155,6 @@ def main():
     stream = torch.cuda.current_stream()
 
     walk_ms = []
-    walk_evals = []
 
     def full_run(record: bool):
         # re-initialise every run on the same arena, then iterate to the end
@@ -197,6 +241,9 @@ def main():
                      "sigma_kl_mean": float(np.mean([s["sigma_kl"] for s in stats])),
                      "sigma_mom_mean": float(np.mean([s["sigma_mom"] for s in stats]))},
     }
+    if not args.no_plain and all(c.kind != "gauss_full" for c in cfgs):
+        res["plain_baseline"] = plain_baseline(cfgs, value, ms_per_step / len(cfgs), stats,
+                                               truth)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(cfgs)
     print(json.dumps(res), flush=True)

@@ -206,6 +206,19 @@ int ggns_loglike_grad(ggns_ctx *ctx, int32_t run, const void *x_dev, int64_t n,
 int ggns_loglike_vjp(ggns_ctx *ctx, int32_t run, const void *x_dev, int64_t n,
                      const double *gout_dev, void *gx_dev, void *stream);
 
+/* The plain FP64 walk, the speed baseline of the fused walk: the same method,
+ * random streams and outputs as ggns_hss_walk (Algorithm GGNS HSS; the readings
+ * of the fused walk), executed as a per-step array program -- one thread per
+ * walker, the walk state in the caller's device workspace, one kernel launch
+ * per step, the number of active walkers read back by the host every 8 steps,
+ * runs walked one after another.  Every run of the context must be GGNS_FP64
+ * (else GGNS_EUNSUPPORTED).  `workspace_dev` (device, 256-byte aligned, caller
+ * owned, at least ggns_plain_workspace_bytes(ctx) bytes, contents need not be
+ * initialised) is scratch for the duration of the call.  Synchronises `stream`
+ * (it polls), so it cannot be captured in a graph. */
+int64_t ggns_plain_workspace_bytes(const ggns_ctx *ctx);
+int ggns_hss_walk_plain(ggns_ctx *ctx, void *workspace_dev, int64_t workspace_bytes, void *stream);
+
 int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out);
 
 /* Copy every run's stats to host memory `out` (n_runs entries); synchronises `stream`. */

@@ -17,7 +17,8 @@ RUN_ACTIVE, RUN_DONE, RUN_MAXITER, RUN_NONFINITE = 0, 1, 2, 3
 SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update", "ggns_finalize",
            "ggns_hss_walk", "ggns_replace_dead", "ggns_loglike_grad", "ggns_loglike_vjp",
            "ggns_run_layout", "ggns_read_stats", "ggns_write_vars", "ggns_set_trace",
-           "ggns_tile_shape", "ggns_free", "ggns_status_string")
+           "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
+           "ggns_free", "ggns_status_string")
 
 
 class ggns_run_desc(C.Structure):
@@ -87,13 +88,17 @@ def load() -> C.CDLL:
         L.ggns_write_vars.argtypes = [vp, i32, C.POINTER(ggns_run_vars), vp]
         L.ggns_set_trace.argtypes = [vp, i32, vp, vp, vp, i32]
         L.ggns_tile_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
+        L.ggns_plain_workspace_bytes.argtypes = [vp]
+        L.ggns_plain_workspace_bytes.restype = i64
+        L.ggns_hss_walk_plain.argtypes = [vp, vp, i64, vp]
         L.ggns_free.argtypes = [vp]
         L.ggns_free.restype = None
         L.ggns_status_string.argtypes = [C.c_int]
         L.ggns_status_string.restype = C.c_char_p
         for name in ("ggns_evidence_update", "ggns_finalize", "ggns_hss_walk", "ggns_replace_dead",
                      "ggns_loglike_grad", "ggns_loglike_vjp", "ggns_run_layout",
-                     "ggns_read_stats", "ggns_write_vars", "ggns_set_trace", "ggns_tile_shape"):
+                     "ggns_read_stats", "ggns_write_vars", "ggns_set_trace", "ggns_tile_shape",
+                     "ggns_hss_walk_plain"):
             getattr(L, name).restype = C.c_int
         _lib = L
         return L

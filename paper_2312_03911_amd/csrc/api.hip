@@ -315,6 +315,29 @@ int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
     return GGNS_OK;
 }
 
+int64_t ggns_plain_workspace_bytes(const ggns_ctx *ctx) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    int64_t b = 0;
+    for (const RunDev &R : ctx->plan.runs) b = std::max(b, plain_workspace_bytes(R));
+    return b;
+}
+
+int ggns_hss_walk_plain(ggns_ctx *ctx, void *workspace_dev, int64_t workspace_bytes, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    for (const RunDev &R : ctx->plan.runs)
+        if (R.prec != GGNS_FP64) return GGNS_EUNSUPPORTED;
+    if (workspace_dev == nullptr || (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign) != 0 ||
+        workspace_bytes < ggns_plain_workspace_bytes(ctx))
+        return GGNS_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int r = 0; r < (int)ctx->plan.runs.size(); ++r) {
+        const int rc = launch_walk_plain(ctx->arena, ctx->runs_dev(), r, ctx->plan.runs[r],
+                                         workspace_dev, 8, s);
+        if (rc != GGNS_OK) return rc;
+    }
+    return GGNS_OK;
+}
+
 int ggns_replace_dead(ggns_ctx *ctx, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
     launch_replace(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), ctx->max_kd,

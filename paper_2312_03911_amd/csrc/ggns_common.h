@@ -73,6 +73,9 @@ int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int
                      int d_pad, hipStream_t s);
 int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, const void *x,
                    int64_t n, double *logl, void *grad, const double *gout, hipStream_t s);
+int64_t plain_workspace_bytes(const RunDev &R);
+int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws,
+                      int poll_every, hipStream_t s);
 void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
                      long long iter, hipStream_t s);
 

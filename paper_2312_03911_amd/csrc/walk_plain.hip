@@ -1,0 +1,286 @@
+// The plain FP64 form of the same walk, kept as the speed baseline: the
+// execution model of a per-step tensor program (Algorithm GGNS HSS written as
+// whole-batch array operations).  One thread per walker, the walk state (x, p,
+// the score, the random-stream states and the counters) lives in HBM and is
+// read and written back by one kernel launch per step, the host polls the
+// number of active walkers between launches, and runs are walked one after
+// the other.  It draws the same random streams and takes the same decisions as
+// the fused walk (readings as there), so for FP64 runs the two agree up to the
+// order of floating-point sums.
+#include "ggns_device.h"
+
+namespace ggns {
+
+namespace {
+
+// Walk state of one run, carved from the caller's workspace.
+struct PlainState {
+    double *x, *p, *g, *out_l;
+    uint32_t *eps;  // [k][nb][4] xoshiro states, nb = ceil(d / 4)
+    uint32_t *res;  // [k][4]
+    int32_t *s, *nref, *streak, *steps, *outs, *nprune, *nsave, *done;
+    int32_t *active;  // [n_steps_max] walkers still walking after step t
+};
+
+__host__ __device__ inline int64_t plain_align(int64_t v) { return (v + 255) / 256 * 256; }
+
+__host__ __device__ inline int64_t plain_bytes(int k, int d, int n_steps_max, PlainState *st,
+                                               unsigned char *base) {
+    const int nb = (d + 3) / 4;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        unsigned char *p = base ? base + off : nullptr;
+        off = plain_align(off + bytes);
+        return p;
+    };
+    double *x = (double *)take((int64_t)k * d * 8);
+    double *p = (double *)take((int64_t)k * d * 8);
+    double *g = (double *)take((int64_t)k * d * 8);
+    double *ol = (double *)take((int64_t)k * 8);
+    uint32_t *eps = (uint32_t *)take((int64_t)k * nb * 16);
+    uint32_t *res = (uint32_t *)take((int64_t)k * 16);
+    int32_t *ints[8];
+    for (int i = 0; i < 8; ++i) ints[i] = (int32_t *)take((int64_t)k * 4);
+    int32_t *act = (int32_t *)take((int64_t)n_steps_max * 4);
+    if (st) {
+        st->x = x; st->p = p; st->g = g; st->out_l = ol; st->eps = eps; st->res = res;
+        st->s = ints[0]; st->nref = ints[1]; st->streak = ints[2]; st->steps = ints[3];
+        st->outs = ints[4]; st->nprune = ints[5]; st->nsave = ints[6]; st->done = ints[7];
+        st->active = act;
+    }
+    return off;
+}
+
+__device__ void plain_momentum(uint64_t seed, uint32_t m, uint32_t it, uint32_t sub, int d, double *p) {
+    for (int b = 0; b * 4 < d; ++b) {
+        uint32_t w[4];
+        draw4(seed, (uint32_t)b, m, it, TAG_P0, sub, w);
+        double z[4];
+        normals2(w[0], w[1], z[0], z[1]);
+        normals2(w[2], w[3], z[2], z[3]);
+        for (int j = 0; j < 4 && 4 * b + j < d; ++j) p[4 * b + j] = z[j];
+    }
+}
+
+// log L and its score at x (FP64, plain loops over the run's converted
+// parameters; padding entries are never read).
+__device__ double plain_loglike(const RunDev &R, const double *prm, const double *x, double *g) {
+    const int d = R.d, dp = R.dp;
+    if (R.kind == GGNS_LIK_GAUSS_DIAG) {
+        double q = 0.0;
+        for (int a = 0; a < d; ++a) {
+            const double r = x[a] - prm[a];
+            q += prm[dp + a] * r * r;
+            g[a] = -prm[dp + a] * r;
+        }
+        return prm[2 * dp] - 0.5 * q;
+    }
+    if (R.kind == GGNS_LIK_GAUSS_FULL) {
+        const double *P = prm + d + 1;
+        double q = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double y = 0.0;
+            for (int j = 0; j < d; ++j) y += P[(int64_t)i * d + j] * (x[j] - prm[j]);
+            q += (x[i] - prm[i]) * y;
+            g[i] = -y;
+        }
+        return prm[d] - 0.5 * q;
+    }
+    const int K = R.n_comp;
+    double lp[kMaxComp], aux[kMaxComp];
+    double l = -INFINITY;
+    if (R.kind == GGNS_LIK_SHELLS) {
+        for (int k = 0; k < K; ++k) {
+            const double *o = prm + k * (dp + 3);
+            double s = 0.0;
+            for (int a = 0; a < d; ++a) s += (x[a] - o[a]) * (x[a] - o[a]);
+            aux[k] = sqrt(s);
+            const double e = aux[k] - o[dp];
+            lp[k] = o[dp + 2] - 0.5 * e * e * o[dp + 1];
+            const double hi = fmax(l, lp[k]);
+            l = (hi == -INFINITY) ? hi : hi + log(exp(l - hi) + exp(lp[k] - hi));
+        }
+        for (int a = 0; a < d; ++a) g[a] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double *o = prm + k * (dp + 3);
+            if (!(aux[k] > 0.0)) continue;
+            const double coef = -exp(lp[k] - l) * (aux[k] - o[dp]) * o[dp + 1] / aux[k];
+            for (int a = 0; a < d; ++a) g[a] += coef * (x[a] - o[a]);
+        }
+        return l;
+    }
+    for (int k = 0; k < K; ++k) {
+        const double *o = prm + k * (2 * dp + 1);
+        double q = 0.0;
+        for (int a = 0; a < d; ++a) q += o[dp + a] * (x[a] - o[a]) * (x[a] - o[a]);
+        lp[k] = o[2 * dp] - 0.5 * q;
+        const double hi = fmax(l, lp[k]);
+        l = (hi == -INFINITY) ? hi : hi + log(exp(l - hi) + exp(lp[k] - hi));
+    }
+    for (int a = 0; a < d; ++a) g[a] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double *o = prm + k * (2 * dp + 1);
+        const double resp = exp(lp[k] - l);
+        for (int a = 0; a < d; ++a) g[a] += -resp * o[dp + a] * (x[a] - o[a]);
+    }
+    return l;
+}
+
+__global__ void plain_start_kernel(void *arena, const RunDev *__restrict__ runs, int run,
+                                   unsigned char *ws) {
+    const RunDev &R = runs[run];
+    const Acc *acc = at<Acc>(arena, R.off_acc);
+    PlainState S;
+    plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, ws);
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int t = m; t < R.n_steps_max; t += gridDim.x * blockDim.x) S.active[t] = 0;
+    if (acc->state != GGNS_RUN_ACTIVE || m >= R.n_kill) return;
+    const int d = R.d, nsurv = R.n_live - R.n_kill, nb = (d + 3) / 4;
+    const uint32_t it = (uint32_t)acc->iter;
+    uint32_t w[4];
+    draw4(R.seed, 0u, (uint32_t)m, it, TAG_START, 0u, w);
+    const int s = at<int32_t>(arena, R.off_surv)[(int)(((uint64_t)w[0] * (uint64_t)nsurv) >> 32)];
+    at<int32_t>(arena, R.off_start)[m] = s;
+    const double *xs = at<double>(arena, R.off_live_x) + (int64_t)s * d;
+    double *x = S.x + (int64_t)m * d;
+    double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
+    for (int a = 0; a < d; ++a) x[a] = wo[a] = xs[a];
+    S.out_l[m] = at<double>(arena, R.off_live_logl)[s];
+    plain_momentum(R.seed, (uint32_t)m, it, 0u, d, S.p + (int64_t)m * d);
+    for (int b = 0; b < nb; ++b) {
+        draw4(R.seed, (uint32_t)b, (uint32_t)m, it, TAG_EPS, 0u, w);
+        Xoshiro e;
+        e.seed(w);
+        uint32_t *st = S.eps + ((int64_t)m * nb + b) * 4;
+        st[0] = e.s0; st[1] = e.s1; st[2] = e.s2; st[3] = e.s3;
+    }
+    draw4(R.seed, 0u, (uint32_t)m, it, TAG_RES, 0u, w);
+    Xoshiro r;
+    r.seed(w);
+    S.res[4 * m] = r.s0; S.res[4 * m + 1] = r.s1; S.res[4 * m + 2] = r.s2; S.res[4 * m + 3] = r.s3;
+    S.s[m] = s;
+    S.nref[m] = S.streak[m] = S.steps[m] = S.outs[m] = S.nprune[m] = S.nsave[m] = S.done[m] = 0;
+}
+
+__global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, int run,
+                                  unsigned char *ws, int t) {
+    const RunDev &R = runs[run];
+    Acc *acc = at<Acc>(arena, R.off_acc);
+    if (acc->state != GGNS_RUN_ACTIVE) return;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= R.n_kill) return;
+    PlainState S;
+    plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, ws);
+    if (S.done[m]) return;
+    const int d = R.d, nb = (d + 3) / 4;
+    const double dt = acc->dt, lstar = acc->lstar, dpn = R.delta_p;
+    const uint32_t it = (uint32_t)acc->iter;
+    double *x = S.x + (int64_t)m * d, *p = S.p + (int64_t)m * d, *g = S.g + (int64_t)m * d;
+    const double *prm = at<double>(arena, R.off_prm);
+
+    // drift, log L and the score
+    for (int a = 0; a < d; ++a) x[a] += dt * p[a];
+    const double l = plain_loglike(R, prm, x, g);
+    bool viol = false;
+    for (int a = 0; a < d; ++a) viol = viol || x[a] < R.lo || x[a] > R.hi;
+    const bool out = viol || l <= lstar;
+    int steps = S.steps[m] + 1;
+    // reflection and the componentwise momentum noise of this step
+    double pg = 0.0, gg = 0.0;
+    for (int a = 0; a < d; ++a) {
+        pg += p[a] * g[a];
+        gg += g[a] * g[a];
+    }
+    const bool use_g = out && !viol && isfinite(gg) && gg > 0.0;
+    const bool flip_all = out && !viol && !use_g;
+    const double f = use_g ? 2.0 * pg / gg : 0.0;
+    for (int b = 0; b < nb; ++b) {
+        uint32_t *st = S.eps + ((int64_t)m * nb + b) * 4;
+        Xoshiro e{st[0], st[1], st[2], st[3]};
+        uint32_t w[4];
+        for (int j = 0; j < 4; ++j) w[j] = e.next();
+        st[0] = e.s0; st[1] = e.s1; st[2] = e.s2; st[3] = e.s3;
+        double z[4];
+        normals2(w[0], w[1], z[0], z[1]);
+        normals2(w[2], w[3], z[2], z[3]);
+        for (int j = 0; j < 4 && 4 * b + j < d; ++j) {
+            const int a = 4 * b + j;
+            const bool flip = flip_all || (out && (x[a] < R.lo || x[a] > R.hi));
+            const double pr = (flip ? -p[a] : p[a]) - f * g[a];
+            p[a] = pr * (1.0 + dpn * z[j]);
+        }
+    }
+    Xoshiro rs{S.res[4 * m], S.res[4 * m + 1], S.res[4 * m + 2], S.res[4 * m + 3]};
+    const uint32_t ures = rs.next();
+    S.res[4 * m] = rs.s0; S.res[4 * m + 1] = rs.s1; S.res[4 * m + 2] = rs.s2; S.res[4 * m + 3] = rs.s3;
+    // bookkeeping: reflections, the kept-point reservoir, pruning, the stop
+    int nref = S.nref[m] + (out ? 1 : 0);
+    const int outs = S.outs[m] + (out ? 1 : 0);
+    int streak = out ? S.streak[m] + 1 : 0;
+    const bool keep = !out && nref >= R.min_ref;
+    const int nsave = S.nsave[m] + (keep ? 1 : 0);
+    const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32)) : (nsave == 0));
+    if (take) {
+        double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
+        for (int a = 0; a < d; ++a) wo[a] = x[a];
+        S.out_l[m] = l;
+    }
+    int nprune = S.nprune[m];
+    if (R.prune_streak > 0 && streak >= R.prune_streak) {
+        const double *xs = at<double>(arena, R.off_live_x) + (int64_t)S.s[m] * d;
+        for (int a = 0; a < d; ++a) x[a] = xs[a];
+        nprune += 1;
+        plain_momentum(R.seed, (uint32_t)m, it, (uint32_t)nprune, d, p);
+        nref = 0;
+        streak = 0;
+    }
+    S.nref[m] = nref; S.outs[m] = outs; S.streak[m] = streak; S.steps[m] = steps;
+    S.nsave[m] = nsave; S.nprune[m] = nprune;
+    const bool done = !(steps < R.n_steps_max && (R.max_ref == 0 || nref < R.max_ref));
+    if (done) {
+        S.done[m] = 1;
+        at<double>(arena, R.off_walk_logl)[m] = S.out_l[m];
+        atomicAdd(&acc->it_outs, (unsigned long long)outs);
+        atomicAdd(&acc->it_steps, (unsigned long long)steps);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_out), (unsigned long long)outs);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_in),
+                  (unsigned long long)(steps - outs));
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->evals), (unsigned long long)steps);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->prunes), (unsigned long long)nprune);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->nosave),
+                  (unsigned long long)(nsave == 0 ? 1 : 0));
+    } else {
+        atomicAdd(&S.active[t], 1);
+    }
+}
+
+}  // namespace
+
+int64_t plain_workspace_bytes(const RunDev &R) {
+    return plain_bytes(R.n_kill, R.d, R.n_steps_max, nullptr, nullptr);
+}
+
+int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws,
+                      int poll_every, hipStream_t s) {
+    const int threads = 256, blocks = (R.n_kill + threads - 1) / threads;
+    unsigned char *w = reinterpret_cast<unsigned char *>(ws);
+    hipLaunchKernelGGL(plain_start_kernel, dim3(blocks), dim3(threads), 0, s, arena, runs_dev, run, w);
+    if (hipGetLastError() != hipSuccess) return GGNS_EHIP;
+    PlainState S;
+    plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, w);
+    for (int t = 0; t < R.n_steps_max; ++t) {
+        hipLaunchKernelGGL(plain_step_kernel, dim3(blocks), dim3(threads), 0, s, arena, runs_dev, run,
+                           w, t);
+        if (hipGetLastError() != hipSuccess) return GGNS_EHIP;
+        if ((t + 1) % poll_every == 0 && t + 1 < R.n_steps_max) {
+            int32_t n_active = 0;
+            if (hipMemcpyAsync(&n_active, S.active + t, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return GGNS_EHIP;
+            if (n_active == 0) break;
+        }
+    }
+    return GGNS_OK;
+}
+
+}  // namespace ggns

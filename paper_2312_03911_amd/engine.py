@@ -115,13 +115,26 @@ class Engine:
     def hss_walk(self):
         _lib.check(self.L.ggns_hss_walk(self.ctx, self._stream()), "ggns_hss_walk")
 
+    def hss_walk_plain(self):
+        """The plain FP64 per-step walk (speed baseline; FP64 runs only)."""
+        if getattr(self, "_plain_ws", None) is None:
+            nb = int(self.L.ggns_plain_workspace_bytes(self.ctx))
+            _lib.check(nb if nb < 0 else 0, "ggns_plain_workspace_bytes")
+            self._plain_ws = self.torch.empty(max(nb, 256), dtype=self.torch.uint8, device=self.device)
+        _lib.check(self.L.ggns_hss_walk_plain(self.ctx, self._plain_ws.data_ptr(),
+                                              self._plain_ws.numel(), self._stream()),
+                   "ggns_hss_walk_plain")
+
     def replace_dead(self):
         _lib.check(self.L.ggns_replace_dead(self.ctx, self._stream()), "ggns_replace_dead")
 
-    def iterate(self, n: int = 1):
+    def iterate(self, n: int = 1, plain: bool = False):
         for _ in range(n):
             self.evidence_update()
-            self.hss_walk()
+            if plain:
+                self.hss_walk_plain()
+            else:
+                self.hss_walk()
             self.replace_dead()
 
     def capture(self, iters: int):
@@ -137,18 +150,21 @@ class Engine:
         self._graph = g
         self._graph_iters = iters
 
-    def step_block(self, iters: int, use_graph: bool):
-        if use_graph:
+    def step_block(self, iters: int, use_graph: bool, plain: bool = False):
+        if plain:
+            self.iterate(iters, plain=True)
+        elif use_graph:
             if self._graph is None or self._graph_iters != iters:
                 self.capture(iters)
             self._graph.replay()
         else:
             self.iterate(iters)
 
-    def run(self, poll_every: int = 8, use_graph: bool = False, max_blocks: int = 10 ** 6):
+    def run(self, poll_every: int = 8, use_graph: bool = False, max_blocks: int = 10 ** 6,
+            plain: bool = False):
         """Iterate until every run stopped; returns the per-run stats."""
         for _ in range(max_blocks):
-            self.step_block(poll_every, use_graph)
+            self.step_block(poll_every, use_graph, plain)
             st = self.stats()
             if all(s["state"] != _lib.RUN_ACTIVE for s in st):
                 self.finalize()
