@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--poll", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tile", default="auto", choices=["auto", "default"],
+                    help="walk tile shape: autotuned per group of like runs, or the library default")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
@@ -151,7 +153,12 @@ def main():
 
     cfgs = workload(args.workload)
     truth = [exact.log_z(c) for c in cfgs]
-    eng = Engine(cfgs, device="cuda:0")
+    tile_c = None
+    if args.tile == "auto":
+        from paper_2312_03911_amd.autotune import tune
+        tile_c = tune(cfgs, device="cuda:0", verbose=True)
+    eng = Engine(cfgs, device="cuda:0", tile_c=tile_c)
+    shapes = sorted({eng.tile_shape(r) for r in range(len(cfgs))})
     stream = torch.cuda.current_stream()
 
     walk_ms = []
@@ -230,7 +237,8 @@ def main():
         "config": {"workload": args.workload, "runs": len(cfgs),
                    "d": sorted({c.d for c in cfgs}), "n_live": sorted({c.n_live for c in cfgs}),
                    "kinds": sorted({c.kind for c in cfgs}), "precision": sorted({c.precision for c in cfgs}),
-                   "evals_per_step": evals, "iterations": [s["iter"] for s in stats][:16]},
+                   "evals_per_step": evals, "iterations": [s["iter"] for s in stats][:16],
+                   "tile": {"mode": args.tile, "coords_per_lane_x_lanes": shapes}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "walk_valu_kernel", "walk_ms_per_step": 1e3 * walk_time_s,

@@ -188,8 +188,14 @@ int ggns_evidence_update(ggns_ctx *ctx, int32_t final_sweep, void *stream);
  * whole dead sequence.  One launch for all runs; call it once they stopped. */
 int ggns_finalize(ggns_ctx *ctx, void *stream);
 
-/* The batched HSS walk for every ACTIVE run: n_kill walkers, started from
- * survivors drawn uniformly, write their outputs to walk_x / walk_logl. */
+/* The batched HSS walk for every ACTIVE run (Algorithm GGNS HSS, with the
+ * trajectory preservation, pruning and parallel evolution of Section 3):
+ * n_kill walkers per run, started from survivors drawn uniformly, write their
+ * outputs to walk_x / walk_logl and the step counters dt adaptation uses.
+ * Runs are grouped into kernel classes (precision, tile shape, family); when
+ * there are several, the classes after the first run on side streams of the
+ * context that wait on `stream` and are joined back into it, so the call is
+ * ordered on `stream` like a single launch and can be graph-captured. */
 int ggns_hss_walk(ggns_ctx *ctx, void *stream);
 
 /* Scatter walker outputs into the killed slots, adapt dt, advance the

@@ -1,0 +1,89 @@
+"""Tile-shape autotuner of the vector-ALU walk.
+
+The walk kernel gives each walker a group of G lanes with C coordinates per
+lane (G = next power of two of ceil(d / C)).  Fewer coordinates per lane means
+more lanes per step and more wavefronts to hide latency with, but a longer
+reduction butterfly and more redundant stream work; the best C depends on the
+family, the dimension, the precision and on how many walkers the batch holds.
+The tuner times the walk of each group of like runs (same family, precision,
+dimension and component count) for every admissible C on the batch itself and
+keeps the fastest.  Results are independent of C up to floating-point
+summation order (the random streams are per coordinate block, not per lane).
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Sequence, Tuple
+
+from .inputs import RunConfig
+
+_CACHE: Dict[Tuple, int] = {}
+
+
+def candidates(cfg: RunConfig) -> List[int]:
+    if cfg.precision == "bf16mma":
+        return [0]
+    top = 4 if cfg.precision == "fp64" else 8
+    out = []
+    for c in (1, 2, 4, 8):
+        if c > top:
+            continue
+        g = 1
+        while g * c < cfg.d:
+            g *= 2
+        if g > 64:
+            continue
+        if c > 1 and g == 1 and c >= 2 * cfg.d:
+            continue        # lanes of padding only
+        out.append(c)
+    return out
+
+
+def _group_key(cfg: RunConfig) -> Tuple:
+    return (cfg.kind, cfg.precision, cfg.d, cfg.n_comp, cfg.max_ref, cfg.n_steps_max)
+
+
+def _time_walk(cfgs: Sequence[RunConfig], c: int, warm: int, reps: int, device: str) -> float:
+    import torch
+
+    from .engine import Engine
+    eng = Engine(cfgs, device=device, tile_c=[c] * len(cfgs))
+    eng.iterate(warm)
+    stream = torch.cuda.current_stream(eng.device)
+    t = 0.0
+    for _ in range(reps):
+        eng.evidence_update()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        eng.hss_walk()
+        b.record(stream)
+        eng.replace_dead()
+        b.synchronize()
+        t += a.elapsed_time(b)
+    eng.close()
+    return t / reps
+
+
+def tune(configs: Sequence[RunConfig], device: str = "cuda", warm: int = 2, reps: int = 3,
+         verbose: bool = False) -> List[int]:
+    """Coordinates per lane for every run of the batch (0 = library default)."""
+    groups: Dict[Tuple, List[int]] = {}
+    for i, c in enumerate(configs):
+        groups.setdefault(_group_key(c), []).append(i)
+    choice = [0] * len(configs)
+    for key, idx in groups.items():
+        sub = [configs[i] for i in idx]
+        cands = candidates(sub[0])
+        ckey = key + (len(sub), sum(c.n_live for c in sub))
+        if ckey not in _CACHE:
+            if cands == [0]:
+                _CACHE[ckey] = 0
+            else:
+                times = {c: _time_walk(sub, c, warm, reps, device) for c in cands}
+                _CACHE[ckey] = min(times, key=times.get)
+                if verbose:
+                    print("autotune", key, {c: round(t, 4) for c, t in times.items()},
+                          "->", _CACHE[ckey], flush=True)
+        for i in idx:
+            choice[i] = _CACHE[ckey]
+    return choice

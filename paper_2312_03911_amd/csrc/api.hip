@@ -146,6 +146,17 @@ struct ggns_ctx {
     std::vector<Class> walk_classes, init_classes;
     std::vector<Acc> acc_host;
     int max_kd = 1;
+    // walk classes after the first run on side streams forked from and joined
+    // back into the caller's stream (default priority; capturable)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+
+    ~ggns_ctx() {
+        for (hipStream_t s : side) (void)hipStreamDestroy(s);
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+    }
 
     RunDev *runs_dev() const { return at<RunDev>(arena, plan.off_runs); }
     Tile *tiles_dev() const { return at<Tile>(arena, plan.off_tiles); }
@@ -241,6 +252,19 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
     c->params = params_dev;
     c->n_params = n_params;
     build_classes(c);
+    for (size_t i = 1; i < c->walk_classes.size(); ++i) {
+        hipStream_t ss;
+        hipEvent_t e;
+        if (hipStreamCreateWithFlags(&ss, hipStreamNonBlocking) != hipSuccess) { delete c; return GGNS_EHIP; }
+        c->side.push_back(ss);
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { delete c; return GGNS_EHIP; }
+        c->join.push_back(e);
+    }
+    if (c->walk_classes.size() > 1 &&
+        hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return GGNS_EHIP;
+    }
     // MMA runs convert P to FP32 too: their prior draws and the stand-alone
     // likelihood use the FP32 vector path
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -302,17 +326,28 @@ int ggns_finalize(ggns_ctx *ctx, void *stream) {
 int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    for (const Class &w : ctx->walk_classes) {
-        int rc;
+    const size_t n = ctx->walk_classes.size();
+    auto launch = [&](const Class &w, hipStream_t st) {
         if (w.mfma)
-            rc = launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                  w.n_tiles, w.C, s);
-        else
-            rc = launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                   w.n_tiles, w.prec, w.C, w.kind, w.lds, s);
+            return launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
+                                    w.n_tiles, w.C, st);
+        return launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
+                                 w.n_tiles, w.prec, w.C, w.kind, w.lds, st);
+    };
+    if (n == 0) return GGNS_OK;
+    if (n == 1) return launch(ctx->walk_classes[0], s);
+    // classes are independent (disjoint runs): fork, run them concurrently, join
+    if (hipEventRecord(ctx->fork, s) != hipSuccess) return GGNS_EHIP;
+    for (size_t i = 1; i < n; ++i) {
+        if (hipStreamWaitEvent(ctx->side[i - 1], ctx->fork, 0) != hipSuccess) return GGNS_EHIP;
+        const int rc = launch(ctx->walk_classes[i], ctx->side[i - 1]);
         if (rc != GGNS_OK) return rc;
+        if (hipEventRecord(ctx->join[i - 1], ctx->side[i - 1]) != hipSuccess) return GGNS_EHIP;
     }
-    return GGNS_OK;
+    const int rc = launch(ctx->walk_classes[0], s);
+    for (size_t i = 1; i < n; ++i)
+        if (hipStreamWaitEvent(s, ctx->join[i - 1], 0) != hipSuccess) return GGNS_EHIP;
+    return rc;
 }
 
 int64_t ggns_plain_workspace_bytes(const ggns_ctx *ctx) {

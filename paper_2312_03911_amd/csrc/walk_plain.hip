@@ -13,11 +13,13 @@ namespace ggns {
 
 namespace {
 
-// Walk state of one run, carved from the caller's workspace.
+// Walk state of one run, carved from the caller's workspace.  Component-major
+// ([component][walker]) like the arrays of a batched tensor program, so that
+// consecutive threads touch consecutive addresses.
 struct PlainState {
-    double *x, *p, *g, *out_l;
-    uint32_t *eps;  // [k][nb][4] xoshiro states, nb = ceil(d / 4)
-    uint32_t *res;  // [k][4]
+    double *x, *p, *g, *out_l;  // x, p, g: [d][k]
+    uint32_t *eps;  // [nb * 4][k] xoshiro states, nb = ceil(d / 4)
+    uint32_t *res;  // [4][k]
     int32_t *s, *nref, *streak, *steps, *outs, *nprune, *nsave, *done;
     int32_t *active;  // [n_steps_max] walkers still walking after step t
 };
@@ -51,27 +53,32 @@ __host__ __device__ inline int64_t plain_bytes(int k, int d, int n_steps_max, Pl
     return off;
 }
 
-__device__ void plain_momentum(uint64_t seed, uint32_t m, uint32_t it, uint32_t sub, int d, double *p) {
+__device__ void plain_momentum(uint64_t seed, uint32_t m, uint32_t it, uint32_t sub, int d, int64_t k,
+                               double *p) {
     for (int b = 0; b * 4 < d; ++b) {
         uint32_t w[4];
         draw4(seed, (uint32_t)b, m, it, TAG_P0, sub, w);
         double z[4];
         normals2(w[0], w[1], z[0], z[1]);
         normals2(w[2], w[3], z[2], z[3]);
-        for (int j = 0; j < 4 && 4 * b + j < d; ++j) p[4 * b + j] = z[j];
+        for (int j = 0; j < 4 && 4 * b + j < d; ++j) p[(4 * b + j) * k + m] = z[j];
     }
 }
 
 // log L and its score at x (FP64, plain loops over the run's converted
-// parameters; padding entries are never read).
-__device__ double plain_loglike(const RunDev &R, const double *prm, const double *x, double *g) {
+// parameters; padding entries are never read).  x and g have stride k.
+__device__ double plain_loglike(const RunDev &R, const double *prm, const double *xm, double *gm,
+                                int64_t k) {
     const int d = R.d, dp = R.dp;
+    auto x = [&](int a) { return xm[a * k]; };
+    auto gset = [&](int a, double v) { gm[a * k] = v; };
+    auto gadd = [&](int a, double v) { gm[a * k] += v; };
     if (R.kind == GGNS_LIK_GAUSS_DIAG) {
         double q = 0.0;
         for (int a = 0; a < d; ++a) {
-            const double r = x[a] - prm[a];
+            const double r = x(a) - prm[a];
             q += prm[dp + a] * r * r;
-            g[a] = -prm[dp + a] * r;
+            gset(a, -prm[dp + a] * r);
         }
         return prm[2 * dp] - 0.5 * q;
     }
@@ -80,9 +87,9 @@ __device__ double plain_loglike(const RunDev &R, const double *prm, const double
         double q = 0.0;
         for (int i = 0; i < d; ++i) {
             double y = 0.0;
-            for (int j = 0; j < d; ++j) y += P[(int64_t)i * d + j] * (x[j] - prm[j]);
-            q += (x[i] - prm[i]) * y;
-            g[i] = -y;
+            for (int j = 0; j < d; ++j) y += P[(int64_t)i * d + j] * (x(j) - prm[j]);
+            q += (x(i) - prm[i]) * y;
+            gset(i, -y);
         }
         return prm[d] - 0.5 * q;
     }
@@ -90,38 +97,38 @@ __device__ double plain_loglike(const RunDev &R, const double *prm, const double
     double lp[kMaxComp], aux[kMaxComp];
     double l = -INFINITY;
     if (R.kind == GGNS_LIK_SHELLS) {
-        for (int k = 0; k < K; ++k) {
-            const double *o = prm + k * (dp + 3);
+        for (int c = 0; c < K; ++c) {
+            const double *o = prm + c * (dp + 3);
             double s = 0.0;
-            for (int a = 0; a < d; ++a) s += (x[a] - o[a]) * (x[a] - o[a]);
-            aux[k] = sqrt(s);
-            const double e = aux[k] - o[dp];
-            lp[k] = o[dp + 2] - 0.5 * e * e * o[dp + 1];
-            const double hi = fmax(l, lp[k]);
-            l = (hi == -INFINITY) ? hi : hi + log(exp(l - hi) + exp(lp[k] - hi));
+            for (int a = 0; a < d; ++a) s += (x(a) - o[a]) * (x(a) - o[a]);
+            aux[c] = sqrt(s);
+            const double e = aux[c] - o[dp];
+            lp[c] = o[dp + 2] - 0.5 * e * e * o[dp + 1];
+            const double hi = fmax(l, lp[c]);
+            l = (hi == -INFINITY) ? hi : hi + log(exp(l - hi) + exp(lp[c] - hi));
         }
-        for (int a = 0; a < d; ++a) g[a] = 0.0;
-        for (int k = 0; k < K; ++k) {
-            const double *o = prm + k * (dp + 3);
-            if (!(aux[k] > 0.0)) continue;
-            const double coef = -exp(lp[k] - l) * (aux[k] - o[dp]) * o[dp + 1] / aux[k];
-            for (int a = 0; a < d; ++a) g[a] += coef * (x[a] - o[a]);
+        for (int a = 0; a < d; ++a) gset(a, 0.0);
+        for (int c = 0; c < K; ++c) {
+            const double *o = prm + c * (dp + 3);
+            if (!(aux[c] > 0.0)) continue;
+            const double coef = -exp(lp[c] - l) * (aux[c] - o[dp]) * o[dp + 1] / aux[c];
+            for (int a = 0; a < d; ++a) gadd(a, coef * (x(a) - o[a]));
         }
         return l;
     }
-    for (int k = 0; k < K; ++k) {
-        const double *o = prm + k * (2 * dp + 1);
+    for (int c = 0; c < K; ++c) {
+        const double *o = prm + c * (2 * dp + 1);
         double q = 0.0;
-        for (int a = 0; a < d; ++a) q += o[dp + a] * (x[a] - o[a]) * (x[a] - o[a]);
-        lp[k] = o[2 * dp] - 0.5 * q;
-        const double hi = fmax(l, lp[k]);
-        l = (hi == -INFINITY) ? hi : hi + log(exp(l - hi) + exp(lp[k] - hi));
+        for (int a = 0; a < d; ++a) q += o[dp + a] * (x(a) - o[a]) * (x(a) - o[a]);
+        lp[c] = o[2 * dp] - 0.5 * q;
+        const double hi = fmax(l, lp[c]);
+        l = (hi == -INFINITY) ? hi : hi + log(exp(l - hi) + exp(lp[c] - hi));
     }
-    for (int a = 0; a < d; ++a) g[a] = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double *o = prm + k * (2 * dp + 1);
-        const double resp = exp(lp[k] - l);
-        for (int a = 0; a < d; ++a) g[a] += -resp * o[dp + a] * (x[a] - o[a]);
+    for (int a = 0; a < d; ++a) gset(a, 0.0);
+    for (int c = 0; c < K; ++c) {
+        const double *o = prm + c * (2 * dp + 1);
+        const double resp = exp(lp[c] - l);
+        for (int a = 0; a < d; ++a) gadd(a, -resp * o[dp + a] * (x(a) - o[a]));
     }
     return l;
 }
@@ -136,28 +143,28 @@ __global__ void plain_start_kernel(void *arena, const RunDev *__restrict__ runs,
     for (int t = m; t < R.n_steps_max; t += gridDim.x * blockDim.x) S.active[t] = 0;
     if (acc->state != GGNS_RUN_ACTIVE || m >= R.n_kill) return;
     const int d = R.d, nsurv = R.n_live - R.n_kill, nb = (d + 3) / 4;
+    const int64_t k = R.n_kill;
     const uint32_t it = (uint32_t)acc->iter;
     uint32_t w[4];
     draw4(R.seed, 0u, (uint32_t)m, it, TAG_START, 0u, w);
     const int s = at<int32_t>(arena, R.off_surv)[(int)(((uint64_t)w[0] * (uint64_t)nsurv) >> 32)];
     at<int32_t>(arena, R.off_start)[m] = s;
     const double *xs = at<double>(arena, R.off_live_x) + (int64_t)s * d;
-    double *x = S.x + (int64_t)m * d;
     double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
-    for (int a = 0; a < d; ++a) x[a] = wo[a] = xs[a];
+    for (int a = 0; a < d; ++a) S.x[a * k + m] = wo[a] = xs[a];
     S.out_l[m] = at<double>(arena, R.off_live_logl)[s];
-    plain_momentum(R.seed, (uint32_t)m, it, 0u, d, S.p + (int64_t)m * d);
+    plain_momentum(R.seed, (uint32_t)m, it, 0u, d, k, S.p);
     for (int b = 0; b < nb; ++b) {
         draw4(R.seed, (uint32_t)b, (uint32_t)m, it, TAG_EPS, 0u, w);
         Xoshiro e;
         e.seed(w);
-        uint32_t *st = S.eps + ((int64_t)m * nb + b) * 4;
-        st[0] = e.s0; st[1] = e.s1; st[2] = e.s2; st[3] = e.s3;
+        uint32_t *st = S.eps + (int64_t)(4 * b) * k + m;
+        st[0] = e.s0; st[k] = e.s1; st[2 * k] = e.s2; st[3 * k] = e.s3;
     }
     draw4(R.seed, 0u, (uint32_t)m, it, TAG_RES, 0u, w);
     Xoshiro r;
     r.seed(w);
-    S.res[4 * m] = r.s0; S.res[4 * m + 1] = r.s1; S.res[4 * m + 2] = r.s2; S.res[4 * m + 3] = r.s3;
+    S.res[m] = r.s0; S.res[k + m] = r.s1; S.res[2 * k + m] = r.s2; S.res[3 * k + m] = r.s3;
     S.s[m] = s;
     S.nref[m] = S.streak[m] = S.steps[m] = S.outs[m] = S.nprune[m] = S.nsave[m] = S.done[m] = 0;
 }
@@ -173,46 +180,47 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
     plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, ws);
     if (S.done[m]) return;
     const int d = R.d, nb = (d + 3) / 4;
+    const int64_t k = R.n_kill;
     const double dt = acc->dt, lstar = acc->lstar, dpn = R.delta_p;
     const uint32_t it = (uint32_t)acc->iter;
-    double *x = S.x + (int64_t)m * d, *p = S.p + (int64_t)m * d, *g = S.g + (int64_t)m * d;
+    double *x = S.x + m, *p = S.p + m, *g = S.g + m;  // component a at [a * k]
     const double *prm = at<double>(arena, R.off_prm);
 
     // drift, log L and the score
-    for (int a = 0; a < d; ++a) x[a] += dt * p[a];
-    const double l = plain_loglike(R, prm, x, g);
+    for (int a = 0; a < d; ++a) x[a * k] += dt * p[a * k];
+    const double l = plain_loglike(R, prm, x, g, k);
     bool viol = false;
-    for (int a = 0; a < d; ++a) viol = viol || x[a] < R.lo || x[a] > R.hi;
+    for (int a = 0; a < d; ++a) viol = viol || x[a * k] < R.lo || x[a * k] > R.hi;
     const bool out = viol || l <= lstar;
-    int steps = S.steps[m] + 1;
+    const int steps = S.steps[m] + 1;
     // reflection and the componentwise momentum noise of this step
     double pg = 0.0, gg = 0.0;
     for (int a = 0; a < d; ++a) {
-        pg += p[a] * g[a];
-        gg += g[a] * g[a];
+        pg += p[a * k] * g[a * k];
+        gg += g[a * k] * g[a * k];
     }
     const bool use_g = out && !viol && isfinite(gg) && gg > 0.0;
     const bool flip_all = out && !viol && !use_g;
     const double f = use_g ? 2.0 * pg / gg : 0.0;
     for (int b = 0; b < nb; ++b) {
-        uint32_t *st = S.eps + ((int64_t)m * nb + b) * 4;
-        Xoshiro e{st[0], st[1], st[2], st[3]};
+        uint32_t *st = S.eps + (int64_t)(4 * b) * k + m;
+        Xoshiro e{st[0], st[k], st[2 * k], st[3 * k]};
         uint32_t w[4];
         for (int j = 0; j < 4; ++j) w[j] = e.next();
-        st[0] = e.s0; st[1] = e.s1; st[2] = e.s2; st[3] = e.s3;
+        st[0] = e.s0; st[k] = e.s1; st[2 * k] = e.s2; st[3 * k] = e.s3;
         double z[4];
         normals2(w[0], w[1], z[0], z[1]);
         normals2(w[2], w[3], z[2], z[3]);
         for (int j = 0; j < 4 && 4 * b + j < d; ++j) {
-            const int a = 4 * b + j;
+            const int64_t a = (4 * b + j) * k;
             const bool flip = flip_all || (out && (x[a] < R.lo || x[a] > R.hi));
             const double pr = (flip ? -p[a] : p[a]) - f * g[a];
             p[a] = pr * (1.0 + dpn * z[j]);
         }
     }
-    Xoshiro rs{S.res[4 * m], S.res[4 * m + 1], S.res[4 * m + 2], S.res[4 * m + 3]};
+    Xoshiro rs{S.res[m], S.res[k + m], S.res[2 * k + m], S.res[3 * k + m]};
     const uint32_t ures = rs.next();
-    S.res[4 * m] = rs.s0; S.res[4 * m + 1] = rs.s1; S.res[4 * m + 2] = rs.s2; S.res[4 * m + 3] = rs.s3;
+    S.res[m] = rs.s0; S.res[k + m] = rs.s1; S.res[2 * k + m] = rs.s2; S.res[3 * k + m] = rs.s3;
     // bookkeeping: reflections, the kept-point reservoir, pruning, the stop
     int nref = S.nref[m] + (out ? 1 : 0);
     const int outs = S.outs[m] + (out ? 1 : 0);
@@ -222,15 +230,15 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
     const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32)) : (nsave == 0));
     if (take) {
         double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
-        for (int a = 0; a < d; ++a) wo[a] = x[a];
+        for (int a = 0; a < d; ++a) wo[a] = x[a * k];
         S.out_l[m] = l;
     }
     int nprune = S.nprune[m];
     if (R.prune_streak > 0 && streak >= R.prune_streak) {
         const double *xs = at<double>(arena, R.off_live_x) + (int64_t)S.s[m] * d;
-        for (int a = 0; a < d; ++a) x[a] = xs[a];
+        for (int a = 0; a < d; ++a) x[a * k] = xs[a];
         nprune += 1;
-        plain_momentum(R.seed, (uint32_t)m, it, (uint32_t)nprune, d, p);
+        plain_momentum(R.seed, (uint32_t)m, it, (uint32_t)nprune, d, k, S.p);
         nref = 0;
         streak = 0;
     }

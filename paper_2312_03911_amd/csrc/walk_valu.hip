@@ -182,9 +182,23 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             w[1] = eps[i].next();
             w[2] = eps[i].next();
             w[3] = eps[i].next();
-            T z[4];
-            normals4(w, z);
-            take_block<T, C>(z, i, a0, eps_c);
+            if constexpr (C >= 4) {
+                T z[4];
+                normals4(w, z);
+                take_block<T, C>(z, i, a0, eps_c);
+            } else {
+                // a lane owning one or two coordinates of the block transforms
+                // only the Box-Muller pair they come from
+                const bool upper = (a0 & 2) != 0;
+                T z0, z1;
+                normals2(upper ? w[2] : w[0], upper ? w[3] : w[1], z0, z1);
+                if constexpr (C == 2) {
+                    eps_c[0] = z0;
+                    eps_c[1] = z1;
+                } else {
+                    eps_c[0] = (a0 & 1) ? z1 : z0;
+                }
+            }
         }
         const uint32_t ures = res.next();
         // drift (Algorithm GGNS HSS: x += p dt)

@@ -31,13 +31,18 @@ class Engine:
     """
 
     def __init__(self, configs: Sequence[RunConfig], device: str = "cuda",
-                 tile_c: Optional[Sequence[int]] = None, attach_arena=None):
+                 tile_c=None, attach_arena=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("the GGNS engine needs a ROCm GPU; no CPU path exists")
         self.torch = torch
         self.device = torch.device(device)
         self.cfgs: List[RunConfig] = list(configs)
+        if isinstance(tile_c, str):
+            if tile_c != "auto":
+                raise ValueError("tile_c must be a list of ints or 'auto'")
+            from .autotune import tune
+            tile_c = tune(self.cfgs, device=str(self.device))
         L = _lib.load()
         self.L = L
         n = len(self.cfgs)

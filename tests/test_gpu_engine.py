@@ -149,3 +149,24 @@ def test_shells_end_to_end_agree_with_oracle_within_error(torch, orc):
     diff = np.mean(gz) - np.mean(oz)
     err = math.sqrt((np.mean(gs) ** 2 + np.mean(os_) ** 2) / len(cfgs))
     assert abs(diff) < 4 * err, (diff, err)
+
+
+def test_tile_shapes_agree_and_autotune_picks_one(torch):
+    """Every coordinates-per-lane choice computes the same walk (FP64: up to
+    summation order), and the autotuner returns an admissible choice."""
+    from paper_2312_03911_amd.autotune import candidates, tune
+    cfg = inputs.config_shells(d=12, n_live=160, seed=61, precision="fp64")
+    ref = None
+    for c in candidates(cfg):
+        eng = _engine([cfg], tile_c=[c])
+        assert eng.tile_shape(0)[0] == c
+        eng.iterate(3)
+        torch.cuda.synchronize()
+        x = _np(eng.live_x(0))
+        if ref is None:
+            ref = x
+        else:
+            assert np.abs(x - ref).max() < 1e-9, c
+        eng.close()
+    choice = tune([cfg, cfg.replace(seed=62)])
+    assert choice[0] == choice[1] and choice[0] in candidates(cfg)
