@@ -108,7 +108,12 @@ typedef struct {
     int32_t max_iter;        /* iteration cap; the dead-record capacity is n_kill*max_iter+n_live */
     double term_tol;         /* remaining evidence fraction, or the X*L fraction */
     uint64_t seed;           /* key of every random stream of the run */
-    int32_t tile_c;          /* coordinates per lane in the walk (1,2,4,8); 0 = library choice */
+    int32_t tile_c;          /* walk tile shape, 0 = library choice.  Vector-ALU runs: coordinates
+                                per lane (1,2,4,8).  GGNS_FP32_BF16MMA runs: wavefronts sharing a
+                                group of 16 walkers, W, with d_pad = d rounded up to 32 and
+                                d_pad / (4W) in {4, 8, 16} (d_pad 256: 8, 16; 96, 160, 192,
+                                224: 8 only); default
+                                d_pad / 32.  Other values: GGNS_EUNSUPPORTED. */
     int32_t reserved;
 } ggns_run_desc;
 
@@ -239,7 +244,8 @@ int ggns_write_vars(ggns_ctx *ctx, int32_t run, const ggns_run_vars *vars, void 
 int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl,
                    int32_t *trace_out, int32_t trace_steps);
 
-/* Coordinates per lane actually used for each run's walk (after defaults). */
+/* The walk tile of a run after defaults: coordinates per lane and lanes per
+ * walker (matrix-core runs: dimensions per lane and 4 W lanes per walker). */
 int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
                     int32_t *lanes_per_walker);
 

@@ -1,10 +1,13 @@
-"""Tile-shape autotuner of the vector-ALU walk.
+"""Tile-shape autotuner of the walk kernels.
 
-The walk kernel gives each walker a group of G lanes with C coordinates per
-lane (G = next power of two of ceil(d / C)).  Fewer coordinates per lane means
-more lanes per step and more wavefronts to hide latency with, but a longer
-reduction butterfly and more redundant stream work; the best C depends on the
-family, the dimension, the precision and on how many walkers the batch holds.
+The vector-ALU walk gives each walker a group of G lanes with C coordinates
+per lane (G = next power of two of ceil(d / C)).  Fewer coordinates per lane
+means more lanes per step and more wavefronts to hide latency with, but a
+longer reduction butterfly and more redundant stream work; the best C depends
+on the family, the dimension, the precision and on how many walkers the batch
+holds.  The matrix-core walk shares a group of 16 walkers between W wavefronts
+(dp / 4W dimensions per lane): more wavefronts spread the per-coordinate work
+but read the residuals from LDS once each and meet at more barriers.
 The tuner times the walk of each group of like runs (same family, precision,
 dimension and component count) for every admissible C on the batch itself and
 keeps the fastest.  Results are independent of C up to floating-point
@@ -20,21 +23,30 @@ _CACHE: Dict[Tuple, int] = {}
 
 
 def candidates(cfg: RunConfig) -> List[int]:
+    """Tile shapes the library accepts for this run.  Vector-ALU runs:
+    coordinates per lane (1, 2, 4, 8), leaving out shapes whose lanes would
+    hold padding only.  Matrix-core runs: wavefronts per group of 16 walkers
+    giving 16, 8 or 4 dimensions per lane."""
+    from . import _lib
+    from .engine import make_descs
+    L = _lib.load()
+
+    def ok(t):
+        descs, _ = make_descs([cfg], [t])
+        return L.ggns_arena_bytes(descs, 1) > 0
+
     if cfg.precision == "bf16mma":
-        return [0]
-    top = 4 if cfg.precision == "fp64" else 8
+        dp = (cfg.d + 31) // 32 * 32
+        return [w for w in (dp // 64, dp // 32, dp // 16) if w >= 1 and ok(w)]
     out = []
     for c in (1, 2, 4, 8):
-        if c > top:
-            continue
         g = 1
         while g * c < cfg.d:
             g *= 2
-        if g > 64:
-            continue
         if c > 1 and g == 1 and c >= 2 * cfg.d:
             continue        # lanes of padding only
-        out.append(c)
+        if ok(c):
+            out.append(c)
     return out
 
 
@@ -76,8 +88,8 @@ def tune(configs: Sequence[RunConfig], device: str = "cuda", warm: int = 2, reps
         cands = candidates(sub[0])
         ckey = key + (len(sub), sum(c.n_live for c in sub))
         if ckey not in _CACHE:
-            if cands == [0]:
-                _CACHE[ckey] = 0
+            if len(cands) <= 1:
+                _CACHE[ckey] = cands[0] if cands else 0
             else:
                 times = {c: _time_walk(sub, c, warm, reps, device) for c in cands}
                 _CACHE[ckey] = min(times, key=times.get)

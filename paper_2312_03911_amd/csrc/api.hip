@@ -37,8 +37,7 @@ bool valid_desc(const ggns_run_desc &r) {
     if (r.n_steps_max < 1 || r.min_ref < 0 || r.max_ref < 0 || r.prune_streak < 0) return false;
     if (!(r.term_tol > 0.0) || r.max_iter < 0) return false;
     if (r.param_offset < 0) return false;
-    if (r.tile_c != 0 && r.tile_c != 1 && r.tile_c != 2 && r.tile_c != 4 && r.tile_c != 8)
-        return false;
+    if (r.tile_c < 0 || r.tile_c > 16) return false;
     return true;
 }
 
@@ -91,7 +90,10 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.lo = D.prior_lo; R.hi = D.prior_hi; R.dt_init = D.dt_init; R.delta_p = D.delta_p;
         R.out_hi = D.out_hi; R.out_lo = D.out_lo; R.dt_down = D.dt_down; R.dt_up = D.dt_up;
         R.term_tol = D.term_tol; R.seed = D.seed; R.param_offset = D.param_offset;
-        int C = D.tile_c ? D.tile_c : default_c(D.d);
+        const bool mma = D.precision == GGNS_FP32_BF16MMA;
+        if (!mma && D.tile_c != 0 && D.tile_c != 1 && D.tile_c != 2 && D.tile_c != 4 && D.tile_c != 8)
+            return GGNS_EUNSUPPORTED;
+        int C = (D.tile_c && !mma) ? D.tile_c : default_c(D.d);
         int G = next_pow2((D.d + C - 1) / C);
         while (G > 64) { C *= 2; G = next_pow2((D.d + C - 1) / C); }
         if (C > 8 || (D.precision == GGNS_FP64 && C > 4)) return GGNS_EUNSUPPORTED;
@@ -107,6 +109,9 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.off_prm = off; off = align_up(off + prm_bytes);
         if (D.precision == GGNS_FP32_BF16MMA) {
             const int64_t dp = (D.d + 31) / 32 * 32;
+            // wavefronts per group of 16 walkers: by default eight dimensions per lane
+            R.mw = D.tile_c ? D.tile_c : (int32_t)(dp / 32);
+            if (!mfma_shape_ok((int)dp, R.mw)) return GGNS_EUNSUPPORTED;
             R.off_prm_bf16 = off; off = align_up(off + dp * dp * 2);
         } else {
             R.off_prm_bf16 = -1;
@@ -131,6 +136,7 @@ struct Class {
     int64_t tile_off;   // index of the first tile in the arena tile array
     int n_tiles;
     size_t lds;
+    int waves = 0;       // matrix-core classes: wavefronts per group of 16 walkers
 };
 
 }  // namespace
@@ -210,14 +216,16 @@ void build_classes(ggns_ctx *c) {
         c->init_classes.push_back(w);
     }
     if (!mfma_runs.empty()) {
-        // matrix-core walk: one class per padded dimension (a multiple of 32),
-        // 64 walkers (four wavefronts of 16) per tile
-        std::map<int, std::vector<int>> by_dp;
-        for (int r : mfma_runs) by_dp[(c->plan.runs[r].d + 31) / 32 * 32].push_back(r);
+        // matrix-core walk: one class per (padded dimension, wavefronts per
+        // group), 16 walkers per tile (one group of slots)
+        std::map<std::pair<int, int>, std::vector<int>> by_dp;
+        for (int r : mfma_runs)
+            by_dp[{(c->plan.runs[r].d + 31) / 32 * 32, c->plan.runs[r].mw}].push_back(r);
         for (auto &kv : by_dp) {
-            Class w{GGNS_FP32_BF16MMA, kv.first, GGNS_LIK_GAUSS_FULL, true,
+            Class w{GGNS_FP32_BF16MMA, kv.first.first, GGNS_LIK_GAUSS_FULL, true,
                     (int64_t)c->tiles_host.size(), 0, 0};
-            for (int r : kv.second) add_tiles(r, c->plan.runs[r].n_kill, 64);
+            w.waves = kv.first.second;
+            for (int r : kv.second) add_tiles(r, c->plan.runs[r].n_kill, 16);
             w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
             c->walk_classes.push_back(w);
         }
@@ -330,7 +338,7 @@ int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
     auto launch = [&](const Class &w, hipStream_t st) {
         if (w.mfma)
             return launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                    w.n_tiles, w.C, st);
+                                    w.n_tiles, w.C, w.waves, st);
         return launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
                                  w.n_tiles, w.prec, w.C, w.kind, w.lds, st);
     };
@@ -471,8 +479,15 @@ int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
                     int32_t *lanes_per_walker) {
     if (ctx == nullptr) return GGNS_ESTATE;
     if (run < 0 || run >= (int)ctx->plan.runs.size()) return GGNS_EINVAL;
-    if (coords_per_lane) *coords_per_lane = ctx->plan.runs[run].C;
-    if (lanes_per_walker) *lanes_per_walker = ctx->plan.runs[run].G;
+    const RunDev &R = ctx->plan.runs[run];
+    if (R.prec == GGNS_FP32_BF16MMA) {
+        const int dp = (R.d + 31) / 32 * 32;
+        if (coords_per_lane) *coords_per_lane = dp / (4 * R.mw);
+        if (lanes_per_walker) *lanes_per_walker = 4 * R.mw;
+    } else {
+        if (coords_per_lane) *coords_per_lane = R.C;
+        if (lanes_per_walker) *lanes_per_walker = R.G;
+    }
     return GGNS_OK;
 }
 

@@ -37,7 +37,7 @@ struct RunDev {
     void *trace_x;
     double *trace_logl;
     int32_t *trace_out;
-    int32_t trace_steps, pad;
+    int32_t trace_steps, mw;   // mw: wavefronts per group of 16 walkers (matrix-core walk)
 };
 
 // Mutable per-run state on the device.
@@ -69,8 +69,9 @@ void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, hipStream_
 void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s);
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
                       int prec, int C, int kind, size_t lds_bytes, hipStream_t s);
+bool mfma_shape_ok(int d_pad, int waves);
 int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                     int d_pad, hipStream_t s);
+                     int d_pad, int waves, hipStream_t s);
 int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, const void *x,
                    int64_t n, double *logl, void *grad, const double *gout, hipStream_t s);
 int64_t plain_workspace_bytes(const RunDev &R);

@@ -83,21 +83,24 @@ __global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, con
     else
         convert_params<float>(R, raw, at<float>(arena, R.off_prm));
     if (R.prec == GGNS_FP32_BF16MMA && R.off_prm_bf16 >= 0) {
-        // P rounded to BF16 (round to nearest even, via FP32) in the order the
-        // matrix-core walk reads it: tiles (mb, kb) of 64 lanes x 8 values, lane
-        // l holding row l%16 and columns 8(l/16)+j of the tile, with the rows and
-        // columns relabelled so that output row 4q+j of M-block mb is dimension
-        // qQ + 4mb + j and K row 8q+j of K-block kb is dimension qQ + 8kb + j
-        // (Q = dp/4).  Padding entries are zero.
-        const int d = R.d, dp = (d + 31) & ~31, Q = dp / 4, KB = dp / 32;
+        // P rounded to BF16 (round to nearest even, via FP32) as the A operands
+        // of the matrix-core walk: tiles (gmb, kb) of 64 lanes x 8 values, lane
+        // l holding row l%16 and columns 8(l/16)+j of the tile.  M-block gmb is
+        // block mb of wavefront w (gmb = w MBW + mb) and its row 4q+j is
+        // dimension w dp/W + q L + 4 mb + j (L = dp / 4W dimensions per lane,
+        // MBW = L / 4); column 8q+j of K-block kb is dimension 32 kb + 8q + j.
+        // Padding entries are zero.
+        const int d = R.d, dp = (d + 31) & ~31, W = R.mw, L = dp / (4 * W), MBW = L / 4;
+        const int KB = dp / 32;
         uint16_t *pb = at<uint16_t>(arena, R.off_prm_bf16);
         const double *P = raw + d;
         for (int64_t e = threadIdx.x; e < (int64_t)dp * dp; e += blockDim.x) {
             const int t = (int)(e / 512), lane = (int)((e / 8) % 64), j = (int)(e % 8);
-            const int mb = t / KB, kb = t % KB;
+            const int gmb = t / KB, kb = t % KB;
+            const int w = gmb / MBW, mb = gmb % MBW;
             const int ro = lane % 16, qk = lane / 16;
-            const int o = (ro / 4) * Q + 4 * mb + (ro % 4);
-            const int i = qk * Q + 8 * kb + j;
+            const int o = w * (dp / W) + (ro / 4) * L + 4 * mb + (ro % 4);
+            const int i = 32 * kb + 8 * qk + j;
             const float f = (o < d && i < d) ? (float)P[(int64_t)o * d + i] : 0.0f;
             uint32_t b = __float_as_uint(f);
             b += 0x7FFFu + ((b >> 16) & 1u);

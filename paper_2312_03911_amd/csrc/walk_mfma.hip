@@ -7,19 +7,21 @@
 // operands rounded to nearest even, FP32 accumulation); r.y, p.y and y.y and
 // everything else stay FP32 on the vector ALUs, the threshold compare FP64.
 //
-// Layout.  A wavefront advances 16 walkers; lane l serves walker slot l % 16
-// and owns the quarter q = l / 16 of its dimensions, [q*Q, q*Q + Q) with
-// Q = dp / 4 (dp = d padded to a multiple of 32), holding x, p and y = P r for
-// them in registers.  The MFMA's B operand (K rows of R^T for one walker
-// column, 8 per lane quarter) and its accumulator (4 output rows per lane
-// quarter) both land on a lane's own dimensions once the rows and columns of P
-// are relabelled: output row 4q'+j of M-block mb is dimension q'Q + 4mb + j and
-// K row 8q'+j of K-block kb is dimension q'Q + 8kb + j.  The prepare kernel
-// stores P in that relabelled, MFMA-tiled order (one 1 KB tile of 64 lanes x 8
-// BF16 per (mb, kb)), so every A operand is one contiguous 16-byte LDS read and
-// no data moves between lanes around the contraction.  Reductions over a
-// walker's dimensions are lane-local sums plus two cross-row exchanges
-// (lanes l, l^16, l^32, l^48).
+// Layout.  A workgroup of W wavefronts advances 16 walker slots together and
+// splits the output rows of P between its wavefronts: wavefront w owns the
+// dimensions [w dp/W, (w+1) dp/W) (dp = d padded to a multiple of 32) and holds
+// its dp/W rows of P, as ready-made BF16 A operands, in registers for the whole
+// walk.  Within a wavefront lane l serves walker slot l % 16 and owns the
+// L = dp / (4W) consecutive dimensions a0 = w dp/W + (l/16) L ... of it,
+// holding x, p, mu and y = P r for them in registers.  With the output rows
+// relabelled (row 4q+j of the wavefront's M-block mb is dimension
+// w dp/W + q L + 4 mb + j) the accumulator lands on the lane that owns those
+// dimensions.  Per step each lane writes its BF16 residuals to LDS, every
+// wavefront reads the 16 walkers' residuals back as B operands (16-byte reads,
+// rows padded against bank conflicts), and the per-wavefront partial sums of
+// r.y, p.y, y.y and the box test meet in LDS; two workgroup barriers a step.
+// All wavefronts take the same decisions for a walker from the same sums, and
+// refill finished slots from the tile in slot order, so no atomics are needed.
 #include "ggns_device.h"
 
 namespace ggns {
@@ -27,67 +29,69 @@ namespace ggns {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaThreads = 256;   // 4 wavefronts, 64 walker slots
-
+// sum over the four lane quarters (lanes l, l^16, l^32, l^48)
 __device__ __forceinline__ float sum4(float v) {
     v += __shfl_xor(v, 16, 64);
     v += __shfl_xor(v, 32, 64);
     return v;
 }
 
-template <int Q>
-__device__ __forceinline__ void momentum_quarter(uint64_t seed, uint32_t m, uint32_t it,
-                                                 uint32_t sub, int a0, int d, float (&p)[Q]) {
+template <int L>
+__device__ __forceinline__ void momentum_lane(uint64_t seed, uint32_t m, uint32_t it, uint32_t sub,
+                                              int a0, int d, float (&p)[L]) {
 #pragma unroll
-    for (int i = 0; i < Q / 4; ++i) {
+    for (int i = 0; i < L / 4; ++i) {
         uint32_t w[4];
         draw4(seed, (uint32_t)((a0 >> 2) + i), m, it, TAG_P0, sub, w);
         normals2(w[0], w[1], p[4 * i], p[4 * i + 1]);
         normals2(w[2], w[3], p[4 * i + 2], p[4 * i + 3]);
     }
 #pragma unroll
-    for (int c = 0; c < Q; ++c) p[c] = (a0 + c < d) ? p[c] : 0.0f;
+    for (int c = 0; c < L; ++c) p[c] = (a0 + c < d) ? p[c] : 0.0f;
 }
 
 }  // namespace
 
-// dp = 4Q; tiles: (dp/16) x (dp/32) of 512 BF16 each, then mu[dp] (FP32).
-template <int Q>
-__global__ void __launch_bounds__(kMfmaThreads)
+// L dimensions per lane, W wavefronts per group of 16 walkers; dp = 4 L W.
+template <int L, int W>
+__global__ void __launch_bounds__(64 * W, 1)
 walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles) {
-    constexpr int DP = 4 * Q, MB = DP / 16, KB = DP / 32;
+    constexpr int DP = 4 * L * W, MBW = L / 4, KB = DP / 32, RS = DP + 8;
     const Tile tile = tiles[blockIdx.x];
     const RunDev &R = runs[tile.run];
     Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
 
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int next_walker;
+    __shared__ __align__(16) __bf16 rbuf[16 * RS];       // residuals of the 16 slots
+    __shared__ __align__(16) floatx4 part[W * 16];       // per-wavefront partial sums
     __shared__ unsigned long long blk_cnt[4];
-    bf16x8 *ptile = reinterpret_cast<bf16x8 *>(smem);
-    float *mu_s = reinterpret_cast<float *>(smem + (size_t)MB * KB * 64 * 16);
-    {
-        const uint4 *src = at<uint4>(arena, R.off_prm_bf16);
-        uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        for (int i = threadIdx.x; i < MB * KB * 64; i += blockDim.x) dst[i] = src[i];
-        const float *prm = at<float>(arena, R.off_prm);
-        for (int i = threadIdx.x; i < DP; i += blockDim.x) mu_s[i] = (i < R.d) ? prm[i] : 0.0f;
-    }
-    if (threadIdx.x == 0) {
-        next_walker = tile.m_begin + kMfmaThreads / 4;
-        blk_cnt[0] = blk_cnt[1] = blk_cnt[2] = blk_cnt[3] = 0ull;
-    }
-    __syncthreads();
 
     const int d = R.d;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane & 15, quarter = lane >> 4;
-    const int a0 = quarter * Q;
-    const float cst = at<float>(arena, R.off_prm)[d];
-    // padding coordinates (a >= d) hold zero position and momentum
+    const int a0 = wave * (DP / W) + quarter * L;
+    const bool lead = wave == 0 && quarter == 0;   // the lane that writes per-walker results
 #define VALID(c) (a0 + (c) < d)
+
+    // this wavefront's rows of P as A operands, and mu for the lane's dimensions
+    bf16x8 amat[MBW][KB];
+    {
+        const bf16x8 *src = at<bf16x8>(arena, R.off_prm_bf16);
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                amat[mb][kb] = src[((wave * MBW + mb) * KB + kb) * 64 + lane];
+    }
+    const float *prm = at<float>(arena, R.off_prm);
+    float mu[L];
+#pragma unroll
+    for (int c = 0; c < L; ++c) mu[c] = VALID(c) ? prm[a0 + c] : 0.0f;
+    const float cst = prm[d];
+    if (threadIdx.x < 4) blk_cnt[threadIdx.x] = 0ull;
 
     const double lstar = acc->lstar;
     const float dt = (float)acc->dt;
@@ -105,12 +109,12 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     double *walk_logl = at<double>(arena, R.off_walk_logl);
     float *trace_x = reinterpret_cast<float *>(R.trace_x);
     const int k = R.n_kill;
-    const unsigned long long gmask = 0x0001000100010001ull << slot;
 
-    float x[Q], p[Q], y[Q];
-    Xoshiro eps[Q / 4];
+    float x[L], p[L], y[L];
+    Xoshiro eps[L / 4];
     Xoshiro res;
-    int m = tile.m_begin + (threadIdx.x >> 6) * 16 + slot;
+    int m = tile.m_begin + slot;
+    int next = tile.m_begin + 16;      // same in every lane: slots refill in slot order
     bool active = m < tile.m_end;
     int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0;
     double out_l = 0.0;
@@ -120,18 +124,18 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         uint32_t w[4];
         draw4(seed, 0u, (uint32_t)mm, it, TAG_START, 0u, w);
         s = surv[(int)(((uint64_t)w[0] * (uint64_t)nsurv) >> 32)];
-        if (quarter == 0) start_arr[mm] = s;
+        if (lead) start_arr[mm] = s;
         const float *xs = live_x + (int64_t)s * d;
         float *wo = walk_x + (int64_t)mm * d;
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
+        for (int c = 0; c < L; ++c) {
             x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
             if (VALID(c)) wo[a0 + c] = x[c];
         }
         out_l = live_logl[s];
-        momentum_quarter<Q>(seed, (uint32_t)mm, it, 0u, a0, d, p);
+        momentum_lane<L>(seed, (uint32_t)mm, it, 0u, a0, d, p);
 #pragma unroll
-        for (int i = 0; i < Q / 4; ++i) {
+        for (int i = 0; i < L / 4; ++i) {
             draw4(seed, (uint32_t)((a0 >> 2) + i), (uint32_t)mm, it, TAG_EPS, 0u, w);
             eps[i].seed(w);
         }
@@ -141,53 +145,72 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     };
 
     if (active) start_walker(m);
+    __syncthreads();
 
     while (__any(active)) {
         const uint32_t ures = res.next();
-        // drift and residuals; BF16 B operands of R^T straight from registers
-        bf16x8 bop[KB];
+        // drift; BF16 residuals of the lane's dimensions to LDS
+        bool vany = false;
+        {
+            __bf16 rb[L];
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int c = 8 * kb + j;
+            for (int c = 0; c < L; ++c) {
                 x[c] = x[c] + dt * p[c];
-                bop[kb][j] = (__bf16)(x[c] - mu_s[a0 + c]);
+                rb[c] = (__bf16)(x[c] - mu[c]);
+                vany = vany || (VALID(c) && (x[c] < lo || x[c] > hi));
             }
-        // Y^T = P R^T on the matrix cores, one 16x16 block of output rows at a time
+            __bf16 *dst = rbuf + slot * RS + a0;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            floatx4 c4 = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int c = 0; c < L; c += 4)
+                *reinterpret_cast<bf16x4 *>(dst + c) = bf16x4{rb[c], rb[c + 1], rb[c + 2], rb[c + 3]};
+        }
+        __syncthreads();
+        // Y^T = P R^T for this wavefront's rows; B operands: K rows 8q..8q+7 of each K-block
+        {
+            bf16x8 bop[KB];
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb)
-                c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ptile[(mb * KB + kb) * 64 + lane],
-                                                             bop[kb], c4, 0, 0, 0);
+                bop[kb] = *reinterpret_cast<const bf16x8 *>(rbuf + slot * RS + 32 * kb + 8 * quarter);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) y[4 * mb + j] = c4[j];
-        }
-        // r.y, p.g and g.g with g = -y
-        float qv = 0.0f, pg = 0.0f, gg = 0.0f;
-        bool vany = false;
+            for (int mb = 0; mb < MBW; ++mb) {
+                floatx4 c4 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            qv += (x[c] - mu_s[a0 + c]) * y[c];
-            pg -= p[c] * y[c];
-            gg += y[c] * y[c];
-            vany = vany || (VALID(c) && (x[c] < lo || x[c] > hi));
+                for (int kb = 0; kb < KB; ++kb)
+                    c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amat[mb][kb], bop[kb], c4, 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) y[4 * mb + j] = c4[j];
+            }
         }
-        qv = sum4(qv);
-        pg = sum4(pg);
-        gg = sum4(gg);
-        const float l = cst - 0.5f * qv;
-        const bool viol = (__ballot(vany) & gmask) != 0ull;
+        // r.y, p.g and g.g (g = -y) and the box test: lane sums, quarters, then wavefronts
+        {
+            float qv = 0.0f, pg = 0.0f, gg = 0.0f;
+#pragma unroll
+            for (int c = 0; c < L; ++c) {
+                qv += (x[c] - mu[c]) * y[c];
+                pg -= p[c] * y[c];
+                gg += y[c] * y[c];
+            }
+            qv = sum4(qv);
+            pg = sum4(pg);
+            gg = sum4(gg);
+            const bool vw = (__ballot(vany) & (0x0001000100010001ull << slot)) != 0ull;
+            if (quarter == 0) part[wave * 16 + slot] = floatx4{qv, pg, gg, vw ? 1.0f : 0.0f};
+        }
+        __syncthreads();
+        floatx4 tot = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int w = 0; w < W; ++w) tot += part[w * 16 + slot];
+        const float l = cst - 0.5f * tot[0];
+        const float pg = tot[1], gg = tot[2];
+        const bool viol = tot[3] > 0.0f;
         const bool out = viol || ((double)l <= lstar);
         if (trace_x != nullptr) {
             if (active && steps < R.trace_steps) {
                 const int64_t row = (int64_t)steps * k + m;
 #pragma unroll
-                for (int c = 0; c < Q; ++c)
+                for (int c = 0; c < L; ++c)
                     if (VALID(c)) trace_x[row * d + a0 + c] = x[c];
-                if (quarter == 0) {
+                if (lead) {
                     R.trace_logl[row] = (double)l;
                     R.trace_out[row] = out ? 1 : 0;
                 }
@@ -198,7 +221,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         const bool flip_all = out && !viol && !use_g;
         const float f = use_g ? m_div(2.0f * pg, gg) : 0.0f;
 #pragma unroll
-        for (int i = 0; i < Q / 4; ++i) {
+        for (int i = 0; i < L / 4; ++i) {
             // this step's noise for the block of four coordinates 4i..4i+3
             float z[4];
             const uint32_t w0 = eps[i].next(), w1 = eps[i].next(), w2 = eps[i].next(),
@@ -224,7 +247,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         if (take && active) {
             float *wo = walk_x + (int64_t)m * d;
 #pragma unroll
-            for (int c = 0; c < Q; ++c)
+            for (int c = 0; c < L; ++c)
                 if (VALID(c)) wo[a0 + c] = x[c];
             out_l = (double)l;
         }
@@ -232,34 +255,35 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             if (active) {
                 const float *xs = live_x + (int64_t)s * d;
 #pragma unroll
-                for (int c = 0; c < Q; ++c) x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
+                for (int c = 0; c < L; ++c) x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
             }
             nprune += 1;
-            momentum_quarter<Q>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
+            momentum_lane<L>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
             nref = 0;
             streak = 0;
         }
         const bool done = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
         const bool need = active && done;
-        if (need && quarter == 0) {
+        if (need && lead) {
             walk_logl[m] = out_l;
             c_outs += outs;
             c_steps += steps;
             c_prunes += nprune;
             c_nosave += (nsave == 0) ? 1 : 0;
         }
-        int nm = 0;
-        if (need && quarter == 0) nm = atomicAdd(&next_walker, 1);
-        nm = __shfl(nm, slot, 64);
+        // finished slots take the next walkers of the tile in slot order; every
+        // lane of every wavefront sees the same mask and computes the same ids
+        const uint32_t fin = (uint32_t)(__ballot(need) & 0xFFFFull);
         if (need) {
-            m = nm;
+            m = next + __popc(fin & ((1u << slot) - 1u));
             active = m < tile.m_end;
             if (active) start_walker(m);
         }
+        next += __popc(fin);
     }
 
 #undef VALID
-    if (quarter == 0 && c_steps > 0) {
+    if (lead && c_steps > 0) {
         atomicAdd(&blk_cnt[0], c_outs);
         atomicAdd(&blk_cnt[1], c_steps);
         atomicAdd(&blk_cnt[2], c_prunes);
@@ -277,35 +301,42 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     }
 }
 
-size_t mfma_lds_bytes(int dp) {
-    return (size_t)(dp / 16) * (dp / 32) * 64 * 16 + (size_t)dp * 4;
-}
-
-template <int Q>
+template <int L, int W>
 static hipError_t launch_mfma_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
                                 hipStream_t s) {
-    const size_t lds = mfma_lds_bytes(4 * Q);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&walk_mfma_kernel<Q>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
-    hipLaunchKernelGGL((walk_mfma_kernel<Q>), dim3(n_tiles), dim3(kMfmaThreads), lds, s, arena, runs,
+    hipLaunchKernelGGL((walk_mfma_kernel<L, W>), dim3(n_tiles), dim3(64 * W), 0, s, arena, runs,
                        tiles);
     return hipGetLastError();
 }
 
-int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int d_pad,
-                     hipStream_t s) {
-    hipError_t e = hipErrorInvalidValue;
+bool mfma_shape_ok(int d_pad, int waves) {
+    if (waves < 1 || d_pad % (16 * waves) != 0) return false;
+    const int L = d_pad / (4 * waves);
     switch (d_pad) {
-        case 32: e = launch_mfma_t<8>(arena, runs_dev, tiles, n_tiles, s); break;
-        case 64: e = launch_mfma_t<16>(arena, runs_dev, tiles, n_tiles, s); break;
-        case 128: e = launch_mfma_t<32>(arena, runs_dev, tiles, n_tiles, s); break;
-        case 256: e = launch_mfma_t<64>(arena, runs_dev, tiles, n_tiles, s); break;
-        default: return GGNS_EUNSUPPORTED;
+        case 32: return L == 8 || L == 4;
+        case 64: case 128: return L == 16 || L == 8 || L == 4;
+        case 256: return L == 16 || L == 8;
+        case 96: case 160: case 192: case 224: return L == 8;
+        default: return false;
     }
+}
+
+int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int d_pad,
+                     int waves, hipStream_t s) {
+    if (!mfma_shape_ok(d_pad, waves)) return GGNS_EUNSUPPORTED;
+    const int L = d_pad / (4 * waves);
+    hipError_t e = hipErrorInvalidValue;
+#define GGNS_MFMA_CASE(LL, WW) \
+    if (L == LL && waves == WW) e = launch_mfma_t<LL, WW>(arena, runs_dev, tiles, n_tiles, s);
+    GGNS_MFMA_CASE(8, 1) GGNS_MFMA_CASE(4, 2)                          // dp 32
+    GGNS_MFMA_CASE(16, 1) GGNS_MFMA_CASE(8, 2) GGNS_MFMA_CASE(4, 4)    // dp 64
+    GGNS_MFMA_CASE(8, 3)                                               // dp 96
+    GGNS_MFMA_CASE(16, 2) GGNS_MFMA_CASE(8, 4) GGNS_MFMA_CASE(4, 8)    // dp 128
+    GGNS_MFMA_CASE(8, 5)                                               // dp 160
+    GGNS_MFMA_CASE(8, 6)                                               // dp 192
+    GGNS_MFMA_CASE(8, 7)                                               // dp 224
+    GGNS_MFMA_CASE(16, 4) GGNS_MFMA_CASE(8, 8)                         // dp 256
+#undef GGNS_MFMA_CASE
     return e == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }
 

@@ -22,6 +22,29 @@ def _torch():
     return torch
 
 
+def make_descs(configs: Sequence[RunConfig], tile_c=None):
+    """The C run descriptors of a batch and its packed FP64 parameter blocks."""
+    n = len(configs)
+    descs = (_lib.ggns_run_desc * n)()
+    off = 0
+    blocks = []
+    for i, c in enumerate(configs):
+        D = descs[i]
+        D.d, D.n_live, D.n_kill = c.d, c.n_live, c.n_kill
+        D.lik_kind, D.precision, D.n_comp = c.kind_id, c.precision_id, c.n_comp
+        D.param_offset = off
+        D.prior_lo, D.prior_hi, D.dt_init = c.lo, c.hi, c.dt_init
+        D.n_steps_max, D.min_ref, D.max_ref = c.n_steps_max, c.min_ref, c.max_ref
+        D.prune_streak, D.delta_p = c.prune_streak, c.delta_p
+        D.out_hi, D.out_lo, D.dt_down, D.dt_up = c.out_hi, c.out_lo, c.dt_down, c.dt_up
+        D.term_kind, D.max_iter, D.term_tol = c.term_kind, c.max_iter, c.term_tol
+        D.seed = int(c.seed) & (2 ** 64 - 1)
+        D.tile_c = int(tile_c[i]) if tile_c is not None else 0
+        blocks.append(np.asarray(c.params, np.float64))
+        off += len(c.params)
+    return descs, blocks
+
+
 class Engine:
     """Many independent nested-sampling runs advanced together.
 
@@ -46,23 +69,7 @@ class Engine:
         L = _lib.load()
         self.L = L
         n = len(self.cfgs)
-        self.descs = (_lib.ggns_run_desc * n)()
-        off = 0
-        blocks = []
-        for i, c in enumerate(self.cfgs):
-            D = self.descs[i]
-            D.d, D.n_live, D.n_kill = c.d, c.n_live, c.n_kill
-            D.lik_kind, D.precision, D.n_comp = c.kind_id, c.precision_id, c.n_comp
-            D.param_offset = off
-            D.prior_lo, D.prior_hi, D.dt_init = c.lo, c.hi, c.dt_init
-            D.n_steps_max, D.min_ref, D.max_ref = c.n_steps_max, c.min_ref, c.max_ref
-            D.prune_streak, D.delta_p = c.prune_streak, c.delta_p
-            D.out_hi, D.out_lo, D.dt_down, D.dt_up = c.out_hi, c.out_lo, c.dt_down, c.dt_up
-            D.term_kind, D.max_iter, D.term_tol = c.term_kind, c.max_iter, c.term_tol
-            D.seed = int(c.seed) & (2 ** 64 - 1)
-            D.tile_c = int(tile_c[i]) if tile_c is not None else 0
-            blocks.append(np.asarray(c.params, np.float64))
-            off += len(c.params)
+        self.descs, blocks = make_descs(self.cfgs, tile_c)
         self.params = torch.from_numpy(np.concatenate(blocks)).to(self.device)
         nbytes = int(L.ggns_arena_bytes(self.descs, n))
         if nbytes < 0:

@@ -51,11 +51,18 @@ def test_arena_size_and_validation():
                + 16 * (c.n_kill * c.max_iter + c.n_live) for c in cfgs)
     assert nb >= need and nb % 256 == 0
     bad = [dict(d=0), dict(d=257), dict(n_live=1), dict(n_kill=0), dict(n_kill=100),
-           dict(lik_kind=7), dict(prior_hi=-1.0), dict(n_steps_max=0), dict(tile_c=3),
-           dict(precision=2)]  # BF16 only for the correlated Gaussian
+           dict(lik_kind=7), dict(prior_hi=-1.0), dict(n_steps_max=0), dict(tile_c=17),
+           dict(tile_c=-1), dict(precision=2)]  # BF16 only for the correlated Gaussian
     for kw in bad:
         one = (_lib.ggns_run_desc * 1)(_desc(cfgs[0], **kw))
         assert L.ggns_arena_bytes(one, 1) == _lib.GGNS_EINVAL, kw
+    # tile shapes the kernels do not have
+    for c, t in ((cfgs[1], 3), (cfgs[1], 16), (cfgs[3], 16), (cfgs[3], 2), (cfgs[0], 8)):
+        one = (_lib.ggns_run_desc * 1)(_desc(c, tile_c=t))
+        assert L.ggns_arena_bytes(one, 1) == _lib.GGNS_EUNSUPPORTED, (c.name, t)
+    for t in (4, 8):                  # d = 256 on the matrix cores: 16 or 8 dims per lane
+        one = (_lib.ggns_run_desc * 1)(_desc(cfgs[3], tile_c=t))
+        assert L.ggns_arena_bytes(one, 1) > 0
     assert L.ggns_arena_bytes(arr, 0) == _lib.GGNS_EINVAL
 
 
