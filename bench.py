@@ -27,6 +27,25 @@ from paper_2312_03911_amd import exact, inputs  # noqa: E402
 
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16mma": 2500.0}
 
+# HBM bytes per walk launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch, averaged over the launches of one pass), each scaled by
+# what the counter reads for a device copy of known size (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0), with the hash of the kernel sources they were taken on;
+# reported only while the sources still hash the same
+TRAFFIC = {"shells32x10": {"bytes": (616.46 * 2.0 + 655.17) * 1024,
+                            "sources_sha1": "ab4bf4392231c3d71bd507468a42f8d465a4262d"}}
+
+
+def traffic_for(workload: str):
+    import hashlib
+    t = TRAFFIC.get(workload)
+    if t is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2312_03911_amd", "csrc")
+    blob = b"".join(open(os.path.join(csrc, f), "rb").read()
+                    for f in ("walk_valu.hip", "ggns_device.h"))
+    return t["bytes"] if hashlib.sha1(blob).hexdigest() == t["sources_sha1"] else None
+
 
 def workload(name: str):
     if name == "shells32x10":
@@ -48,10 +67,11 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def flops_per_eval(cfg, out_frac: float) -> float:
-    """Algorithmic FP operations of one walker step (drift, log L and score,
-    reflection on outside steps, momentum noise with its Box-Muller normals;
-    a transcendental counts as one operation, integer RNG work counts zero)."""
+def valu_flops_per_eval(cfg, out_frac: float) -> float:
+    """Algorithmic vector-ALU FP operations of one walker step, the normals
+    excluded (they are costed at the generator's measured rate): drift, log L
+    and score, reflection on outside steps, p *= 1 + delta_p eps.  For matrix-
+    core runs the contraction P r is left out here (it is the MFMA term)."""
     d, K = cfg.d, cfg.n_comp
     drift = 2 * d
     if cfg.kind == "gauss_diag":
@@ -60,11 +80,39 @@ def flops_per_eval(cfg, out_frac: float) -> float:
         lik = 5 * K * d + 10 * K
     elif cfg.kind == "gmm_diag":
         lik = 7 * K * d + 10 * K
+    elif cfg.precision == "bf16mma":
+        lik = 3 * d + 2
     else:
         lik = 2 * d * d + 3 * d + 2
     reflect = 6 * d * out_frac
-    noise = 2 * d + 6 * d          # p *= 1 + dp*eps, plus ~6 ops per Box-Muller normal
+    noise = 2 * d
     return drift + lik + reflect + noise
+
+
+def mfma_flops_per_eval(cfg) -> float:
+    return 2.0 * cfg.d * cfg.d if cfg.precision == "bf16mma" else 0.0
+
+
+def rng_rate(torch, L) -> float:
+    """Normals per second of the walk's noise generator (xoshiro128++ words,
+    FP32 Box-Muller) alone at full occupancy: 2^20 threads, 512 steps."""
+    import ctypes as C
+    W, B, T = 1 << 16, 16, 512
+    cs = torch.empty(W * B, dtype=torch.float32, device="cuda:0")
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L.ggns_noise_normals(1, 0, W, B, 8, None, None, cs.data_ptr(), s)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    best = 0.0
+    for _ in range(3):
+        a.record()
+        rc = L.ggns_noise_normals(1, 0, W, B, T, None, None, cs.data_ptr(), s)
+        b.record()
+        b.synchronize()
+        if rc != 0:
+            raise RuntimeError("ggns_noise_normals failed")
+        best = max(best, W * B * T * 4 / (a.elapsed_time(b) / 1e3))
+    return best
 
 
 def cpu_baseline(cfgs, budget_s: float = 12.0):
@@ -141,7 +189,20 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tile", default="auto", choices=["auto", "default"],
                     help="walk tile shape: autotuned per group of like runs, or the library default")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device a few times (the reference kernel "
+                         "that scales HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -207,18 +268,40 @@ def main():
     evals = sum(s["evals"] for s in stats)
     ms_per_step = 1e3 * elapsed / args.steps
     value = evals * args.steps / elapsed
-    # roofline of the walk kernel: algorithmic operations / measured duration
+    # roofline of the walk: the time its algorithmic work needs at the chip's
+    # peaks (vector-ALU FP operations at the FP32 or FP64 vector peak, normals at
+    # the generator's measured rate, the BF16 contraction at the matrix-core
+    # peak; per run the larger of the vector and matrix terms, summed over runs)
+    # over the measured walk time
     steps_total = sum(s["steps_out"] + s["steps_in"] for s in stats)
     out_frac = sum(s["steps_out"] for s in stats) / max(steps_total, 1)
-    flops_walk = sum(flops_per_eval(c, s["steps_out"] / max(s["steps_out"] + s["steps_in"], 1))
-                     * (s["steps_out"] + s["steps_in"]) for c, s in zip(cfgs, stats))
+    r_rng = rng_rate(torch, eng.L)
+    t_valu = t_mfma = t_bound = 0.0
+    flops_valu = flops_mfma = normals = 0.0
+    for c, s in zip(cfgs, stats):
+        e = s["steps_out"] + s["steps_in"]
+        fo = s["steps_out"] / max(e, 1)
+        fv, fm = valu_flops_per_eval(c, fo) * e, mfma_flops_per_eval(c) * e
+        pv = PEAK_TFLOPS["fp64" if c.precision == "fp64" else "fp32"] * 1e12
+        rr = r_rng / 2 if c.precision == "fp64" else r_rng
+        tv = fv / pv + c.d * e / rr
+        tm = fm / (PEAK_TFLOPS["bf16mma"] * 1e12)
+        t_valu += tv
+        t_mfma += tm
+        t_bound += max(tv, tm)
+        flops_valu += fv
+        flops_mfma += fm
+        normals += c.d * e
     # only launches that did work (the trailing polled iterations of finished runs are no-ops)
     n_launch_work = max(1, max(s["iter"] for s in stats)) * args.steps
     wm = sorted(walk_ms, reverse=True)[:n_launch_work]
     walk_time_s = sum(wm) / 1e3 / args.steps
     prec = cfgs[0].precision
-    achieved = flops_walk / walk_time_s / 1e12
-    peak = PEAK_TFLOPS["fp64" if prec == "fp64" else "fp32"]
+    frac = t_bound / walk_time_s
+    bound = "mfma" if t_mfma > t_valu else "alu"
+    peak = PEAK_TFLOPS["bf16mma"] if bound == "mfma" else \
+        PEAK_TFLOPS["fp64" if all(c.precision == "fp64" for c in cfgs) else "fp32"]
+    achieved = frac * peak
     dz = [s["log_z"] - t for s, t in zip(stats, truth)]
     zs = [d / max(s["sigma_kl"], 1e-12) for d, s in zip(dz, stats)]
     res = {
@@ -239,10 +322,17 @@ def main():
                    "kinds": sorted({c.kind for c in cfgs}), "precision": sorted({c.precision for c in cfgs}),
                    "evals_per_step": evals, "iterations": [s["iter"] for s in stats][:16],
                    "tile": {"mode": args.tile, "coords_per_lane_x_lanes": shapes}},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "walk_valu_kernel", "walk_ms_per_step": 1e3 * walk_time_s,
-                     "walk_evals_per_s": steps_total / walk_time_s, "out_frac": out_frac},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": frac, "traffic": traffic_for(args.workload),
+                     "kernel": ("walk_mfma_kernel" if bound == "mfma" or
+                                all(c.precision == "bf16mma" for c in cfgs) else "walk_valu_kernel"),
+                     "walk_ms_per_step": 1e3 * walk_time_s,
+                     "walk_launch_us": 1e6 * walk_time_s / max(1, n_launch_work // args.steps),
+                     "walk_evals_per_s": steps_total / walk_time_s, "out_frac": out_frac,
+                     "valu_flops_per_step": flops_valu, "mfma_flops_per_step": flops_mfma,
+                     "normals_per_step": normals, "normals_per_s_peak": r_rng,
+                     "t_bound_ms": 1e3 * t_bound, "t_valu_ms": 1e3 * t_valu,
+                     "t_mfma_ms": 1e3 * t_mfma},
         "accuracy": {"logz_minus_closed_form_mean": float(np.mean(dz)),
                      "logz_minus_closed_form_sd": float(np.std(dz)),
                      "z_scores_max_abs": float(np.max(np.abs(zs))),

@@ -249,6 +249,21 @@ int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl
 int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
                     int32_t *lanes_per_walker);
 
+/* The walk's momentum-noise stream (the eps of p <- p (1 + delta_p eps),
+ * Algorithm GGNS HSS) on its own, for checking the stream and timing the
+ * generator.  Walker m's coordinate block b at iteration `iteration` seeds
+ * xoshiro128++ from Philox4x32-10(key seed; counter b, m, iteration,
+ * EPS << 24) and draws four words per step, turned into four normals by
+ * Box-Muller on 24-bit uniforms in FP32, as in the walk.  With
+ * i = ((t * n_walkers + m) * n_blocks + b) * 4 + j for step t < steps, j < 4:
+ *   normals_dev[i] (float) and words_dev[i] (uint32), each nullable;
+ *   checksum_dev[m * n_blocks + b] = sum of the thread's normals (nullable).
+ * Device pointers, caller-owned; enqueued on `stream`.  GGNS_EINVAL for
+ * negative sizes or more than 2^30 (walker, block) pairs. */
+int ggns_noise_normals(uint64_t seed, int32_t iteration, int32_t n_walkers, int32_t n_blocks,
+                       int32_t steps, float *normals_dev, uint32_t *words_dev, float *checksum_dev,
+                       void *stream);
+
 void ggns_free(ggns_ctx *ctx);
 
 const char *ggns_status_string(int code);

@@ -491,6 +491,16 @@ int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
     return GGNS_OK;
 }
 
+int ggns_noise_normals(uint64_t seed, int32_t iteration, int32_t n_walkers, int32_t n_blocks,
+                       int32_t steps, float *normals_dev, uint32_t *words_dev, float *checksum_dev,
+                       void *stream) {
+    if (n_walkers < 0 || n_blocks < 0 || steps < 0 || iteration < 0) return GGNS_EINVAL;
+    const int64_t total = (int64_t)n_walkers * n_blocks;
+    if (total > (int64_t)1 << 30 || total * steps * 4 > ((int64_t)1 << 40)) return GGNS_EINVAL;
+    return launch_noise_normals(seed, iteration, n_walkers, n_blocks, steps, normals_dev, words_dev,
+                                checksum_dev, reinterpret_cast<hipStream_t>(stream));
+}
+
 void ggns_free(ggns_ctx *ctx) { delete ctx; }
 
 const char *ggns_status_string(int code) {

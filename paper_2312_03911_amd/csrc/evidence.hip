@@ -265,22 +265,49 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
         if (!stop && acc->iter >= R.max_iter) stop = GGNS_RUN_MAXITER;
         flags[1] = stop;
     }
-    // bitonic sort of (log L, slot) ascending
-    for (int size = 2; size <= NP; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int i = t; i < (NP >> 1); i += T) {
-                const int lo = 2 * stride * (i / stride) + (i % stride);
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const unsigned long long ka = key[lo], kb = key[hi];
-                const int sa = slot[lo], sb = slot[hi];
-                const bool greater = (ka > kb) || (ka == kb && sa > sb);
-                if (greater == asc) {
-                    key[lo] = kb; key[hi] = ka;
-                    slot[lo] = sb; slot[hi] = sa;
+    // bitonic sort of (log L, slot) ascending.  A compare-exchange stage of
+    // stride j only touches blocks of 2j consecutive keys, so every stage with
+    // 2j <= CH runs inside one wavefront's chunk of CH keys with wavefront-level
+    // ordering only; workgroup barriers remain for the few wide stages.
+    {
+        const int wave = t >> 6, lane = t & 63;
+        const int CH = (NP / (T >> 6) > 128) ? NP / (T >> 6) : (NP < 128 ? NP : 128);
+        auto cas = [&](int i, int stride, int size) {
+            const int lo = 2 * stride * (i / stride) + (i % stride);
+            const int hi = lo + stride;
+            const bool asc = (lo & size) == 0;
+            const unsigned long long ka = key[lo], kb = key[hi];
+            const int sa = slot[lo], sb = slot[hi];
+            const bool greater = (ka > kb) || (ka == kb && sa > sb);
+            if (greater == asc) {
+                key[lo] = kb; key[hi] = ka;
+                slot[lo] = sb; slot[hi] = sa;
+            }
+        };
+        auto wave_sync = [] {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        // stages of stride <= CH/2 inside the wavefront's chunk [wave CH, wave CH + CH)
+        auto local_stages = [&](int size, int stride) {
+            if (wave * CH < NP) {
+                for (; stride > 0; stride >>= 1) {
+                    for (int q = lane; q < CH / 2; q += 64) cas(wave * (CH / 2) + q, stride, size);
+                    wave_sync();
                 }
             }
+        };
+        __syncthreads();
+        for (int size = 2; size <= CH; size <<= 1) local_stages(size, size >> 1);
+        for (int size = 2 * CH; size <= NP; size <<= 1) {
+            int stride = size >> 1;
+            for (; 2 * stride > CH; stride >>= 1) {
+                __syncthreads();
+                for (int i = t; i < (NP >> 1); i += T) cas(i, stride, size);
+            }
+            __syncthreads();
+            local_stages(size, stride);
         }
     }
     __syncthreads();

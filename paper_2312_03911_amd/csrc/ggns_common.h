@@ -77,6 +77,8 @@ int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, c
 int64_t plain_workspace_bytes(const RunDev &R);
 int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws,
                       int poll_every, hipStream_t s);
+int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_blocks, int steps,
+                         float *normals, uint32_t *words, float *checksum, hipStream_t s);
 void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
                      long long iter, hipStream_t s);
 

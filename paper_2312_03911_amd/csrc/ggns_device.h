@@ -171,7 +171,11 @@ __device__ __forceinline__ bool group_any(bool pred, int G) {
 // v_sqrt, v_rcp; about one ulp), correctly rounded library calls in FP64.
 __device__ __forceinline__ float m_exp(float v) { return __expf(v); }
 __device__ __forceinline__ double m_exp(double v) { return exp(v); }
-__device__ __forceinline__ float m_log(float v) { return __logf(v); }
+// natural log on v_log_f32 without the denormal rescaling: every caller passes
+// a log-sum-exp sum, which is at least one
+__device__ __forceinline__ float m_log(float v) {
+    return __builtin_amdgcn_logf(v) * 0.693147180559945309417f;
+}
 __device__ __forceinline__ double m_log(double v) { return log(v); }
 __device__ __forceinline__ float m_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ double m_sqrt(double v) { return sqrt(v); }

@@ -333,6 +333,49 @@ int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, c
     return e == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }
 
+// The walk's momentum-noise stream on its own: thread (m, b) seeds the
+// xoshiro128++ state of walker m's coordinate block b exactly as the walk does
+// and draws four words and four FP32 normals per step.
+__global__ void noise_normals_kernel(uint64_t seed, uint32_t it, int n_walkers, int n_blocks,
+                                     int steps, float *normals, uint32_t *words, float *checksum) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)n_walkers * n_blocks;
+    if (gid >= total) return;
+    const int m = (int)(gid / n_blocks), b = (int)(gid % n_blocks);
+    uint32_t w[4];
+    draw4(seed, (uint32_t)b, (uint32_t)m, it, TAG_EPS, 0u, w);
+    Xoshiro e;
+    e.seed(w);
+    float acc = 0.0f;
+    for (int t = 0; t < steps; ++t) {
+        w[0] = e.next();
+        w[1] = e.next();
+        w[2] = e.next();
+        w[3] = e.next();
+        float z[4];
+        normals2(w[0], w[1], z[0], z[1]);
+        normals2(w[2], w[3], z[2], z[3]);
+        const int64_t row = ((int64_t)t * total + gid) * 4;
+        if (normals != nullptr)
+            for (int j = 0; j < 4; ++j) normals[row + j] = z[j];
+        if (words != nullptr)
+            for (int j = 0; j < 4; ++j) words[row + j] = w[j];
+        acc += (z[0] + z[1]) + (z[2] + z[3]);
+    }
+    if (checksum != nullptr) checksum[gid] = acc;
+}
+
+int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_blocks, int steps,
+                         float *normals, uint32_t *words, float *checksum, hipStream_t s) {
+    const int64_t total = (int64_t)n_walkers * n_blocks;
+    if (total == 0) return GGNS_OK;
+    const int threads = 256;
+    const int64_t blocks = (total + threads - 1) / threads;
+    hipLaunchKernelGGL(noise_normals_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, seed,
+                       (uint32_t)iteration, n_walkers, n_blocks, steps, normals, words, checksum);
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
 void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
                      long long iter, hipStream_t s) {
     hipLaunchKernelGGL(set_vars_kernel, dim3(1), dim3(1), 0, s, arena, run_dev, log_z, log_x, dt,

@@ -157,7 +157,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             for (int c = 0; c < L; ++c) {
                 x[c] = x[c] + dt * p[c];
                 rb[c] = (__bf16)(x[c] - mu[c]);
-                vany = vany || (VALID(c) && (x[c] < lo || x[c] > hi));
+                vany = vany | (VALID(c) & ((x[c] < lo) | (x[c] > hi)));
             }
             __bf16 *dst = rbuf + slot * RS + a0;
 #pragma unroll
@@ -231,8 +231,8 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = 4 * i + j;
-                const bool vm = VALID(c) && (x[c] < lo || x[c] > hi);
-                const bool flip = flip_all || (out && vm);
+                const bool vm = VALID(c) & ((x[c] < lo) | (x[c] > hi));
+                const bool flip = flip_all | (out & vm);
                 const float pr = (flip ? -p[c] : p[c]) + f * y[c];   // p - f g with g = -y
                 p[c] = pr * (1.0f + dpn * z[j]);
             }

@@ -211,8 +211,9 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         bool vany = false;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            vm[c] = valid[c] && (x[c] < lo || x[c] > hi);
-            vany = vany || vm[c];
+            // bitwise, not short-circuit: no branches in the step
+            vm[c] = valid[c] & ((x[c] < lo) | (x[c] > hi));
+            vany = vany | vm[c];
         }
         const bool viol = group_any(vany, G);
         const bool out = viol || ((double)lk.l <= lstar);
@@ -236,7 +237,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         const T f = use_g ? m_div(T(2) * lk.pg, lk.gg) : T(0);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const bool flip = flip_all || (out && vm[c]);
+            const bool flip = flip_all | (out & vm[c]);
             const T pr = (flip ? -p[c] : p[c]) - f * g[c];
             // momentum noise, componentwise: p *= 1 + delta_p * eps
             p[c] = pr * (T(1) + dpn * eps_c[c]);
@@ -278,13 +279,15 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             c_nosave += (nsave == 0) ? 1 : 0;
         }
         // the group takes the next walker of the tile
-        int nm = 0;
-        if (need && gl == 0) nm = atomicAdd(&next_walker, 1);
-        nm = __shfl(nm, gbase, 64);
-        if (need) {
-            m = nm;
-            active = m < tile.m_end;
-            if (active) start_walker(m);
+        if (__any(need)) {
+            int nm = 0;
+            if (need && gl == 0) nm = atomicAdd(&next_walker, 1);
+            nm = __shfl(nm, gbase, 64);
+            if (need) {
+                m = nm;
+                active = m < tile.m_end;
+                if (active) start_walker(m);
+            }
         }
     }
 

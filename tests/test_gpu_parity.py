@@ -26,9 +26,9 @@ def torch():
     return t
 
 
-def _engine(cfgs):
+def _engine(cfgs, tile_c=None):
     from paper_2312_03911_amd.engine import Engine
-    return Engine(cfgs)
+    return Engine(cfgs, tile_c=tile_c)
 
 
 def _np(t):
@@ -93,9 +93,27 @@ def test_init_matches_oracle(torch, orc, name, make, tol, tau):
 
 @pytest.mark.parametrize("name,make,tol,tau", CASES, ids=[c[0] for c in CASES])
 def test_kill_and_walk_trace_match_oracle(torch, orc, name, make, tol, tau):
-    cfg = make()
-    T = 20
-    eng = _engine([cfg])
+    _trace_check(torch, orc, make(), tol, tau)
+
+
+# every tile shape of the matrix-core walk: (d, wavefronts per 16 walkers)
+MMA_SHAPES = [(20, 1), (20, 2), (64, 1), (64, 4), (72, 3), (128, 2), (128, 8), (150, 5),
+              (180, 6), (200, 7), (256, 4), (256, 8)]
+
+
+@pytest.mark.parametrize("d,waves", MMA_SHAPES, ids=[f"d{d}_w{w}" for d, w in MMA_SHAPES])
+def test_mma_walk_shapes_match_oracle(torch, orc, d, waves):
+    cfg = inputs.config_corr_gauss(d=d, n_live=96, seed=300 + d, param_seed=40 + d,
+                                   precision="bf16mma", n_steps_max=40)
+    _trace_check(torch, orc, cfg, 1e-4, 1e-4, tile_c=[waves], steps=12)
+
+
+def _trace_check(torch, orc, cfg, tol, tau, tile_c=None, steps=20):
+    T = steps
+    eng = _engine([cfg], tile_c)
+    if tile_c is not None:
+        c, g = eng.tile_shape(0)
+        assert g == (4 * tile_c[0] if cfg.precision == "bf16mma" else g)
     o = orc.Oracle(cfg, trace_steps=T).init()
     if cfg.kind == "shells":
         # a mid-run state: points around both shells and the step the run has
