@@ -187,6 +187,8 @@ def main():
     ap.add_argument("--poll", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-alt", action="store_true",
+                    help="skip the untimed pass under the per-walker noise reading")
     ap.add_argument("--tile", default="auto", choices=["auto", "default"],
                     help="walk tile shape: autotuned per group of like runs, or the library default")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -333,12 +335,29 @@ def main():
                      "normals_per_step": normals, "normals_per_s_peak": r_rng,
                      "t_bound_ms": 1e3 * t_bound, "t_valu_ms": 1e3 * t_valu,
                      "t_mfma_ms": 1e3 * t_mfma},
-        "accuracy": {"logz_minus_closed_form_mean": float(np.mean(dz)),
+        "accuracy": {"noise": "per component",
+                     "logz_minus_closed_form_mean": float(np.mean(dz)),
                      "logz_minus_closed_form_sd": float(np.std(dz)),
                      "z_scores_max_abs": float(np.max(np.abs(zs))),
                      "sigma_kl_mean": float(np.mean([s["sigma_kl"] for s in stats])),
                      "sigma_mom_mean": float(np.mean([s["sigma_mom"] for s in stats]))},
     }
+    # the same workload under the other reading of the momentum noise (one
+    # normal per walker and step), one untimed pass: its log Z against the
+    # closed form
+    if not args.no_alt:
+        eng.close()
+        alt = Engine([c.replace(noise="walker") for c in cfgs], device="cuda:0", tile_c=tile_c)
+        st_alt = alt.run(poll_every=args.poll)
+        alt.close()
+        dza = [s_["log_z"] - t for s_, t in zip(st_alt, truth)]
+        res["accuracy_walker_noise"] = {
+            "noise": "one normal per walker and step",
+            "logz_minus_closed_form_mean": float(np.mean(dza)),
+            "logz_minus_closed_form_sd": float(np.std(dza)),
+            "logz_minus_closed_form_sem": float(np.std(dza) / math.sqrt(max(1, len(dza) - 1))),
+            "sigma_kl_mean": float(np.mean([s_["sigma_kl"] for s_ in st_alt])),
+            "evals": int(sum(s_["evals"] for s_ in st_alt))}
     if not args.no_plain and all(c.kind != "gauss_full" for c in cfgs):
         res["plain_baseline"] = plain_baseline(cfgs, value, ms_per_step / len(cfgs), stats,
                                                truth)

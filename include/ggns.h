@@ -114,7 +114,9 @@ typedef struct {
                                 d_pad / (4W) in {4, 8, 16} (d_pad 256: 8, 16; 96, 160, 192,
                                 224: 8 only); default
                                 d_pad / 32.  Other values: GGNS_EUNSUPPORTED. */
-    int32_t reserved;
+    int32_t noise_mode;      /* the eps of p <- p (1 + delta_p eps) (Algorithm GGNS HSS):
+                                0 = one normal per coordinate (default reading),
+                                1 = one normal per walker and step, the first of its stream */
 } ggns_run_desc;
 
 /* Byte offsets (from the arena base) of one run's arrays. */

@@ -41,7 +41,10 @@
  *   R6  leaving the prior box counts as outside and takes precedence; the
  *       momentum component of every violated axis is negated.
  *   R7  eps is drawn per component and applied to every walker at every step,
- *       after any reflection.
+ *       after any reflection.  The algorithm writes eps ~ N(0,1); the other
+ *       reading, one normal per walker and step (the first normal of that
+ *       walker's step stream) scaling all components alike, is available as
+ *       noise_mode = 1.
  *   R8  a point is saved when it is inside the slice and this walker has made
  *       at least min_ref reflections (per walker, not the batch minimum).
  *   R9  the saved set is per walker and sampled uniformly by a size-one
@@ -314,6 +317,7 @@ typedef struct {
     int32_t term_kind, max_iter;
     double term_tol;
     uint64_t seed;
+    int32_t noise_mode, pad_;   /* R7: 0 per component, 1 one normal per walker */
 } orc_desc;
 
 enum { ST_ACTIVE = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3 };
@@ -551,7 +555,8 @@ static void walk_one(const orc_desc *D, const double *prm, orc_state *S, int m,
             for (int j = 0; j < 4; ++j) w[j] = orc_xoshiro_next(xs + 4 * b);
             orc_box_muller4(w, eps + 4 * b);
         }
-        for (int a = 0; a < d; ++a) p[a] = p[a] * (1.0 + D->delta_p * eps[a]);
+        for (int a = 0; a < d; ++a)
+            p[a] = p[a] * (1.0 + D->delta_p * (D->noise_mode ? eps[0] : eps[a]));
         uint32_t ures = orc_xoshiro_next(xr);
         nref += outside;
         outs += outside;

@@ -42,7 +42,8 @@ class _Desc(C.Structure):
                 ("delta_p", C.c_double), ("out_hi", C.c_double), ("out_lo", C.c_double),
                 ("dt_down", C.c_double), ("dt_up", C.c_double),
                 ("term_kind", C.c_int32), ("max_iter", C.c_int32),
-                ("term_tol", C.c_double), ("seed", C.c_uint64)]
+                ("term_tol", C.c_double), ("seed", C.c_uint64),
+                ("noise_mode", C.c_int32), ("pad", C.c_int32)]
 
 
 _PD = C.POINTER(C.c_double)
@@ -181,7 +182,8 @@ class Oracle:
                           delta_p=cfg.delta_p, out_hi=cfg.out_hi, out_lo=cfg.out_lo,
                           dt_down=cfg.dt_down, dt_up=cfg.dt_up, term_kind=cfg.term_kind,
                           max_iter=cfg.max_iter, term_tol=cfg.term_tol,
-                          seed=C.c_uint64(int(cfg.seed) & (2**64 - 1)))
+                          seed=C.c_uint64(int(cfg.seed) & (2**64 - 1)),
+                          noise_mode=cfg.noise_id)
         self.params = np.ascontiguousarray(cfg.params, dtype=np.float64)
         cap = k * cfg.max_iter + n
         self.live_x = np.zeros((n, d))

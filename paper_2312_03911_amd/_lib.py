@@ -31,7 +31,7 @@ class ggns_run_desc(C.Structure):
                 ("delta_p", C.c_double), ("out_hi", C.c_double), ("out_lo", C.c_double),
                 ("dt_down", C.c_double), ("dt_up", C.c_double),
                 ("term_kind", C.c_int32), ("max_iter", C.c_int32), ("term_tol", C.c_double),
-                ("seed", C.c_uint64), ("tile_c", C.c_int32), ("reserved", C.c_int32)]
+                ("seed", C.c_uint64), ("tile_c", C.c_int32), ("noise_mode", C.c_int32)]
 
 
 class ggns_layout(C.Structure):

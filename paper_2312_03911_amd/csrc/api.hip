@@ -38,6 +38,7 @@ bool valid_desc(const ggns_run_desc &r) {
     if (!(r.term_tol > 0.0) || r.max_iter < 0) return false;
     if (r.param_offset < 0) return false;
     if (r.tile_c < 0 || r.tile_c > 16) return false;
+    if (r.noise_mode != 0 && r.noise_mode != 1) return false;
     return true;
 }
 
@@ -61,7 +62,7 @@ int default_c(int d) {
 
 struct Plan {
     std::vector<RunDev> runs;
-    int64_t off_runs = 0, off_tiles = 0, n_tile_slots = 0, total = 0;
+    int64_t off_runs = 0, off_tiles = 0, n_tile_slots = 0, off_mirror = 0, total = 0;
 };
 
 // Lay out the arena: run table, tiles, then each run's arrays.
@@ -77,6 +78,9 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
     P.off_tiles = off;
     P.n_tile_slots = ntiles;
     off = align_up(off + (int64_t)sizeof(Tile) * ntiles);
+    // contiguous copy of every run's accumulators, gathered for one read-back
+    P.off_mirror = off;
+    off = align_up(off + (int64_t)sizeof(Acc) * n_runs);
     for (int r = 0; r < n_runs; ++r) {
         const ggns_run_desc &D = descs[r];
         if (!valid_desc(D)) return GGNS_EINVAL;
@@ -90,6 +94,7 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.lo = D.prior_lo; R.hi = D.prior_hi; R.dt_init = D.dt_init; R.delta_p = D.delta_p;
         R.out_hi = D.out_hi; R.out_lo = D.out_lo; R.dt_down = D.dt_down; R.dt_up = D.dt_up;
         R.term_tol = D.term_tol; R.seed = D.seed; R.param_offset = D.param_offset;
+        R.noise_mode = D.noise_mode;
         const bool mma = D.precision == GGNS_FP32_BF16MMA;
         if (!mma && D.tile_c != 0 && D.tile_c != 1 && D.tile_c != 2 && D.tile_c != 4 && D.tile_c != 8)
             return GGNS_EUNSUPPORTED;
@@ -433,12 +438,12 @@ int ggns_read_stats(ggns_ctx *ctx, ggns_run_stats *out, void *stream) {
     if (out == nullptr) return GGNS_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int n = (int)ctx->plan.runs.size();
-    for (int r = 0; r < n; ++r) {
-        if (hipMemcpyAsync(&ctx->acc_host[r], at<Acc>(ctx->arena, ctx->plan.runs[r].off_acc),
-                           sizeof(Acc), hipMemcpyDeviceToHost, s) != hipSuccess)
-            return GGNS_EHIP;
-    }
-    if (hipStreamSynchronize(s) != hipSuccess) return GGNS_EHIP;
+    Acc *mirror = at<Acc>(ctx->arena, ctx->plan.off_mirror);
+    if (launch_gather_acc(ctx->arena, ctx->runs_dev(), n, mirror, s) != GGNS_OK ||
+        hipMemcpyAsync(ctx->acc_host.data(), mirror, sizeof(Acc) * n, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return GGNS_EHIP;
     for (int r = 0; r < n; ++r) {
         const Acc &a = ctx->acc_host[r];
         ggns_run_stats &o = out[r];

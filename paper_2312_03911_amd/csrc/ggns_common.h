@@ -38,6 +38,7 @@ struct RunDev {
     double *trace_logl;
     int32_t *trace_out;
     int32_t trace_steps, mw;   // mw: wavefronts per group of 16 walkers (matrix-core walk)
+    int32_t noise_mode, pad;   // 1: one noise normal per walker and step
 };
 
 // Mutable per-run state on the device.
@@ -79,6 +80,7 @@ int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev
                       int poll_every, hipStream_t s);
 int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_blocks, int steps,
                          float *normals, uint32_t *words, float *checksum, hipStream_t s);
+int launch_gather_acc(void *arena, const RunDev *runs_dev, int n_runs, Acc *mirror, hipStream_t s);
 void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
                      long long iter, hipStream_t s);
 

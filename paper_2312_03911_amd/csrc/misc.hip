@@ -376,6 +376,19 @@ int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_bloc
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }
 
+__global__ void gather_acc_kernel(void *arena, const RunDev *__restrict__ runs, int n_runs,
+                                  Acc *mirror) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n_runs) mirror[r] = *at<Acc>(arena, runs[r].off_acc);
+}
+
+int launch_gather_acc(void *arena, const RunDev *runs_dev, int n_runs, Acc *mirror, hipStream_t s) {
+    if (n_runs <= 0) return GGNS_OK;
+    hipLaunchKernelGGL(gather_acc_kernel, dim3((n_runs + 63) / 64), dim3(64), 0, s, arena, runs_dev,
+                       n_runs, mirror);
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
 void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
                      long long iter, hipStream_t s) {
     hipLaunchKernelGGL(set_vars_kernel, dim3(1), dim3(1), 0, s, arena, run_dev, log_z, log_x, dt,

@@ -67,6 +67,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 
     __shared__ __align__(16) __bf16 rbuf[16 * RS];       // residuals of the 16 slots
     __shared__ __align__(16) floatx4 part[W * 16];       // per-wavefront partial sums
+    __shared__ float eps0s[16];                          // noise_mode 1: each slot's normal
     __shared__ unsigned long long blk_cnt[4];
 
     const int d = R.d;
@@ -196,6 +197,16 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             const bool vw = (__ballot(vany) & (0x0001000100010001ull << slot)) != 0ull;
             if (quarter == 0) part[wave * 16 + slot] = floatx4{qv, pg, gg, vw ? 1.0f : 0.0f};
         }
+        // this step's normals of the lane's first block; with one normal per walker
+        // the lane holding coordinate 0 publishes its first one
+        float zb0[4];
+        {
+            const uint32_t w0 = eps[0].next(), w1 = eps[0].next(), w2 = eps[0].next(),
+                           w3 = eps[0].next();
+            normals2(w0, w1, zb0[0], zb0[1]);
+            normals2(w2, w3, zb0[2], zb0[3]);
+            if (R.noise_mode && a0 == 0) eps0s[slot] = zb0[0];
+        }
         __syncthreads();
         floatx4 tot = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -220,14 +231,21 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         const bool use_g = out && !viol && isfinite(gg) && gg > 0.0f;
         const bool flip_all = out && !viol && !use_g;
         const float f = use_g ? m_div(2.0f * pg, gg) : 0.0f;
+        const bool scalar_noise = R.noise_mode != 0;
+        const float e0 = scalar_noise ? eps0s[slot] : 0.0f;
 #pragma unroll
         for (int i = 0; i < L / 4; ++i) {
             // this step's noise for the block of four coordinates 4i..4i+3
             float z[4];
-            const uint32_t w0 = eps[i].next(), w1 = eps[i].next(), w2 = eps[i].next(),
-                           w3 = eps[i].next();
-            normals2(w0, w1, z[0], z[1]);
-            normals2(w2, w3, z[2], z[3]);
+            if (i == 0) {
+                z[0] = zb0[0]; z[1] = zb0[1]; z[2] = zb0[2]; z[3] = zb0[3];
+            } else {
+                const uint32_t w0 = eps[i].next(), w1 = eps[i].next(), w2 = eps[i].next(),
+                               w3 = eps[i].next();
+                normals2(w0, w1, z[0], z[1]);
+                normals2(w2, w3, z[2], z[3]);
+            }
+            if (scalar_noise) z[0] = z[1] = z[2] = z[3] = e0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = 4 * i + j;

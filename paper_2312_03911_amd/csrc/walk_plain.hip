@@ -202,6 +202,7 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
     const bool use_g = out && !viol && isfinite(gg) && gg > 0.0;
     const bool flip_all = out && !viol && !use_g;
     const double f = use_g ? 2.0 * pg / gg : 0.0;
+    double e0 = 0.0;   // noise_mode 1: the walker's first normal of the step
     for (int b = 0; b < nb; ++b) {
         uint32_t *st = S.eps + (int64_t)(4 * b) * k + m;
         Xoshiro e{st[0], st[k], st[2 * k], st[3 * k]};
@@ -211,6 +212,9 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
         double z[4];
         normals2(w[0], w[1], z[0], z[1]);
         normals2(w[2], w[3], z[2], z[3]);
+        if (b == 0) e0 = z[0];
+        if (R.noise_mode)
+            for (int j = 0; j < 4; ++j) z[j] = e0;
         for (int j = 0; j < 4 && 4 * b + j < d; ++j) {
             const int64_t a = (4 * b + j) * k;
             const bool flip = flip_all || (out && (x[a] < R.lo || x[a] > R.hi));

@@ -200,6 +200,13 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 }
             }
         }
+        if (R.noise_mode) {
+            // one normal per walker and step: the first of its stream (coordinate 0,
+            // held by the group's first lane)
+            const T e0 = __shfl(eps_c[0], gbase, 64);
+#pragma unroll
+            for (int c = 0; c < C; ++c) eps_c[c] = e0;
+        }
         const uint32_t ures = res.next();
         // drift (Algorithm GGNS HSS: x += p dt)
 #pragma unroll

@@ -40,6 +40,7 @@ def make_descs(configs: Sequence[RunConfig], tile_c=None):
         D.term_kind, D.max_iter, D.term_tol = c.term_kind, c.max_iter, c.term_tol
         D.seed = int(c.seed) & (2 ** 64 - 1)
         D.tile_c = int(tile_c[i]) if tile_c is not None else 0
+        D.noise_mode = c.noise_id
         blocks.append(np.asarray(c.params, np.float64))
         off += len(c.params)
     return descs, blocks

@@ -27,6 +27,7 @@ import numpy as np
 
 KINDS = {"gauss_diag": 0, "gauss_full": 1, "shells": 2, "gmm_diag": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16mma": 2}
+NOISE = {"component": 0, "walker": 1}
 
 
 @dataclasses.dataclass
@@ -57,6 +58,7 @@ class RunConfig:
     max_iter: int = 0             # 0 -> a generous bound from d, width and n_live
     seed: int = 0
     name: str = ""
+    noise: str = "component"      # eps of p *= 1 + delta_p eps: "component" or "walker"
 
     def __post_init__(self):
         self.params = np.ascontiguousarray(self.params, dtype=np.float64)
@@ -76,6 +78,10 @@ class RunConfig:
     @property
     def precision_id(self) -> int:
         return PRECISIONS[self.precision]
+
+    @property
+    def noise_id(self) -> int:
+        return NOISE[self.noise]
 
     def replace(self, **kw) -> "RunConfig":
         return dataclasses.replace(self, **kw)

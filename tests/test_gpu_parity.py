@@ -69,6 +69,15 @@ CASES = [
                                                      precision="bf16mma", n_steps_max=60), 1e-4, 1e-4),
     ("corr128_bf16", lambda: inputs.config_corr_gauss(d=128, n_live=256, seed=18, param_seed=9,
                                                       precision="bf16mma"), 1e-4, 1e-4),
+    # one noise normal per walker and step (noise_mode 1)
+    ("gauss2d_fp64_wnoise", lambda: inputs.config_gauss2d(seed=19, noise="walker"), 1e-10, 1e-9),
+    ("shells32_fp32_wnoise", lambda: inputs.config_shells(d=32, n_live=1000, seed=20, noise="walker"),
+     1e-4, 1e-4),
+    ("gmm16_fp64_wnoise", lambda: inputs.config_gmm(d=16, n_live=300, n_comp=4, seed=21, param_seed=6,
+                                                    precision="fp64", noise="walker"), 1e-10, 1e-9),
+    ("corr72_bf16_wnoise", lambda: inputs.config_corr_gauss(d=72, n_live=200, seed=22, param_seed=10,
+                                                            precision="bf16mma", n_steps_max=60,
+                                                            noise="walker"), 1e-4, 1e-4),
 ]
 
 

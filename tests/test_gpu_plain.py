@@ -43,6 +43,8 @@ CASES = [
         params=inputs.gauss_diag_params(np.linspace(-1, 1, 13), np.linspace(0.4, 1.0, 13)))),
     ("corr10", lambda: inputs.config_corr_gauss(d=10, n_live=200, seed=84, param_seed=22,
                                                 precision="fp64", n_steps_max=50)),
+    ("shells6_wnoise", lambda: inputs.config_shells(d=6, n_live=400, seed=86, precision="fp64",
+                                                    noise="walker")),
 ]
 
 

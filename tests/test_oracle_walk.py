@@ -165,6 +165,24 @@ def test_noise_is_componentwise_multiplicative_from_eps_stream(orc):
         np.testing.assert_allclose(q[t + 1], q[t] * (1 + 0.05 * eps[t, :d]), rtol=1e-9)
 
 
+def test_walker_noise_scales_all_components_by_one_normal(orc):
+    """noise_mode 1: p is multiplied by the same (1 + delta_p eps0) in every
+    component, eps0 the first normal of the walker's step stream, so the
+    direction of p is unchanged by the noise."""
+    d = 6
+    cfg = _gauss(d, delta_p=0.05, n_steps_max=12).replace(noise="walker")
+    x0 = np.zeros((1, d))
+    o = one_walk(orc, cfg, killed_x=np.full((1, d), 50.0), surv_x=x0, dt=0.01, trace_steps=12,
+                 killed_logl=[-1e300])
+    q = momenta(o, x0)[:, 0, :]
+    w = orc.xoshiro_stream(orc.stream_words(cfg.seed, 0, 0, 0, TAG_EPS), 4 * 12).reshape(12, 4)
+    for t in range(11):
+        e0 = orc.box_muller4(w[t])[0]
+        np.testing.assert_allclose(q[t + 1], q[t] * (1 + 0.05 * e0), rtol=1e-9)
+        cos = q[t + 1] @ q[t] / np.linalg.norm(q[t + 1]) / np.linalg.norm(q[t])
+        assert abs(cos - 1.0) < 1e-12
+
+
 def test_reservoir_follows_res_stream_and_is_uniform(orc):
     d = 4
     cfg = _gauss(d, delta_p=0.05, n_steps_max=40, min_ref=1)
