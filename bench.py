@@ -32,8 +32,8 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16mma": 2500.0}
 # what the counter reads for a device copy of known size (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0), with the hash of the kernel sources they were taken on;
 # reported only while the sources still hash the same
-TRAFFIC = {"shells32x10": {"bytes": (616.46 * 2.0 + 655.17) * 1024,
-                            "sources_sha1": "ab4bf4392231c3d71bd507468a42f8d465a4262d"}}
+TRAFFIC = {"shells32x10": {"bytes": (620.68 * 2.0 + 655.17) * 1024,
+                            "sources_sha1": "4cd49d7a300055c7a42496c1daa2eb1c54f82374"}}
 
 
 def traffic_for(workload: str):
@@ -342,6 +342,28 @@ def main():
                      "sigma_kl_mean": float(np.mean([s["sigma_kl"] for s in stats])),
                      "sigma_mom_mean": float(np.mean([s["sigma_mom"] for s in stats]))},
     }
+    # mode recovery of the mixture runs (one untimed pass with the dead points'
+    # positions kept)
+    if not args.no_alt and any(c.kind == "gmm_diag" for c in cfgs):
+        from paper_2312_03911_amd.posterior import gmm_mode_report, normalized_log_weights
+        eng.close()
+        me = Engine(cfgs, device="cuda:0", tile_c=tile_c)
+        idx = [i for i, c in enumerate(cfgs) if c.kind == "gmm_diag"]
+        for i in idx:
+            me.keep_dead_x(i)
+        st_m = me.run(poll_every=args.poll)
+        reps = []
+        for i in idx:
+            dl, dw = me.dead(i)
+            reps.append(gmm_mode_report(me.dead_x(i).cpu().numpy(),
+                                        normalized_log_weights(dl.cpu().numpy(), dw.cpu().numpy(),
+                                                               st_m[i]["log_z"]), cfgs[i]))
+        me.close()
+        res["accuracy"]["modes"] = {
+            "runs": len(reps), "recovered": sum(r["recovered"] for r in reps),
+            "of": sum(r["modes"] for r in reps),
+            "weight_max_abs_err": max(r["weight_max_abs_err"] for r in reps),
+            "weights_run0": [round(w, 4) for w in reps[0]["weights"]]}
     # the same workload under the other reading of the momentum noise (one
     # normal per walker and step), one untimed pass: its log Z against the
     # closed form

@@ -246,6 +246,15 @@ int ggns_write_vars(ggns_ctx *ctx, int32_t run, const ggns_run_vars *vars, void 
 int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl,
                    int32_t *trace_out, int32_t trace_steps);
 
+/* Keep the positions of a run's dead points (the weighted posterior samples
+ * of Appendix A's importance weights) from now on: every later
+ * ggns_evidence_update writes the position of each dead point it records to
+ * row n_dead of dead_x_dev ([capacity_rows][d], the run's precision, device,
+ * caller-owned; rows beyond capacity_rows are not written), in the order of the
+ * dead records (log L, log w).  NULL or capacity 0 switches it off.
+ * Synchronous with respect to the host. */
+int ggns_set_dead_x(ggns_ctx *ctx, int32_t run, void *dead_x_dev, int64_t capacity_rows);
+
 /* The walk tile of a run after defaults: coordinates per lane and lanes per
  * walker (matrix-core runs: dimensions per lane and 4 W lanes per walker). */
 int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,

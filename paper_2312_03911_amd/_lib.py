@@ -18,7 +18,7 @@ SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update
            "ggns_hss_walk", "ggns_replace_dead", "ggns_loglike_grad", "ggns_loglike_vjp",
            "ggns_run_layout", "ggns_read_stats", "ggns_write_vars", "ggns_set_trace",
            "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
-           "ggns_noise_normals", "ggns_free", "ggns_status_string")
+           "ggns_noise_normals", "ggns_set_dead_x", "ggns_free", "ggns_status_string")
 
 
 class ggns_run_desc(C.Structure):
@@ -93,6 +93,8 @@ def load() -> C.CDLL:
         L.ggns_hss_walk_plain.argtypes = [vp, vp, i64, vp]
         L.ggns_noise_normals.argtypes = [C.c_uint64, i32, i32, i32, i32, vp, vp, vp, vp]
         L.ggns_noise_normals.restype = C.c_int
+        L.ggns_set_dead_x.argtypes = [vp, i32, vp, i64]
+        L.ggns_set_dead_x.restype = C.c_int
         L.ggns_free.argtypes = [vp]
         L.ggns_free.restype = None
         L.ggns_status_string.argtypes = [C.c_int]

@@ -480,6 +480,17 @@ int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl
     return GGNS_OK;
 }
 
+int ggns_set_dead_x(ggns_ctx *ctx, int32_t run, void *dead_x_dev, int64_t capacity_rows) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size() || capacity_rows < 0) return GGNS_EINVAL;
+    RunDev &R = ctx->plan.runs[run];
+    R.dead_x = (capacity_rows > 0) ? dead_x_dev : nullptr;
+    R.dead_x_cap = (dead_x_dev != nullptr) ? capacity_rows : 0;
+    if (hipMemcpy(ctx->runs_dev() + run, &R, sizeof(RunDev), hipMemcpyHostToDevice) != hipSuccess)
+        return GGNS_EHIP;
+    return GGNS_OK;
+}
+
 int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
                     int32_t *lanes_per_walker) {
     if (ctx == nullptr) return GGNS_ESTATE;

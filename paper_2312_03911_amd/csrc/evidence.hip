@@ -81,50 +81,38 @@ __device__ double block_lse(double lmax_local, double sum_local, double *scratch
     return gmax + log(block_sum(part, scratch));
 }
 
-// Exclusive scans over the block's 1024 per-thread values (Hillis-Steele in LDS).
-__device__ double block_exscan_sum(double v, double *buf) {
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        const double a = (t >= o) ? buf[t - o] : 0.0;
-        __syncthreads();
-        buf[t] += a;
-        __syncthreads();
+// Exclusive scans over the block's per-thread values: an inclusive scan
+// inside each wavefront with lane shuffles, the wavefront totals through LDS
+// (one barrier), each thread adding the totals of the wavefronts before it.
+template <typename T, typename Op>
+__device__ __forceinline__ T block_exscan(T v, T ident, Op op, T *wtot) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T a = __shfl_up(incl, o, 64);
+        if (lane >= o) incl = op(a, incl);
     }
-    const double incl = buf[t];
+    T excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = ident;
+    if (lane == 63) wtot[w] = incl;
     __syncthreads();
-    return incl - v;
+    T pre = ident;
+    for (int i = 0; i < w; ++i) pre = op(pre, wtot[i]);
+    __syncthreads();   // wtot may be reused by the next scan
+    return op(pre, excl);
+}
+
+__device__ double block_exscan_sum(double v, double *buf) {
+    return block_exscan<double>(v, 0.0, [](double a, double b) { return a + b; }, buf);
 }
 
 __device__ double block_exscan_lae(double v, double *buf) {
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        const double a = (t >= o) ? buf[t - o] : -INFINITY;
-        __syncthreads();
-        buf[t] = lae(buf[t], a);
-        __syncthreads();
-    }
-    const double r = (t > 0) ? buf[t - 1] : -INFINITY;
-    __syncthreads();
-    return r;
+    return block_exscan<double>(v, -INFINITY, [](double a, double b) { return lae(a, b); }, buf);
 }
 
 __device__ int block_exscan_int(int v, int *buf) {
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        const int a = (t >= o) ? buf[t - o] : 0;
-        __syncthreads();
-        buf[t] += a;
-        __syncthreads();
-    }
-    const int incl = buf[t];
-    __syncthreads();
-    return incl - v;
+    return block_exscan<int>(v, 0, [](int a, int b) { return a + b; }, buf);
 }
 
 // Run summary over the whole dead sequence: information H, and the second
@@ -327,6 +315,23 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
             dead_w[nd + j] = lw;
         }
         lse_push(v, m_loc, s_loc);
+    }
+    // positions of the dead points in the same order (posterior samples)
+    if (R.dead_x != nullptr) {
+        const int d = R.d;
+        const int es = (R.prec == GGNS_FP64) ? 8 : 4;
+        const unsigned char *lx = at<unsigned char>(arena, R.off_live_x);
+        unsigned char *dx = reinterpret_cast<unsigned char *>(R.dead_x);
+        const long long rows = (nd + nkill <= R.dead_x_cap) ? nkill
+                               : (nd < R.dead_x_cap ? R.dead_x_cap - nd : 0);
+        for (long long e = t; e < rows * d; e += T) {
+            const long long j = e / d, a = e % d;
+            const long long src = ((long long)slot[j] * d + a) * es, dst = ((nd + j) * d + a) * es;
+            if (es == 8)
+                *reinterpret_cast<double *>(dx + dst) = *reinterpret_cast<const double *>(lx + src);
+            else
+                *reinterpret_cast<float *>(dx + dst) = *reinterpret_cast<const float *>(lx + src);
+        }
     }
     const double lse = block_lse(m_loc, s_loc, scratch);
     if (t == 0) {

@@ -39,6 +39,9 @@ struct RunDev {
     int32_t *trace_out;
     int32_t trace_steps, mw;   // mw: wavefronts per group of 16 walkers (matrix-core walk)
     int32_t noise_mode, pad;   // 1: one noise normal per walker and step
+    // positions of the dead points (posterior samples), caller-owned; null when off
+    void *dead_x;
+    int64_t dead_x_cap;        // rows of dead_x
 };
 
 // Mutable per-run state on the device.

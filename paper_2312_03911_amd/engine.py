@@ -95,6 +95,7 @@ class Engine:
         self._graph = None
         self._graph_iters = 0
         self._trace = {}
+        self._dead_x = {}
 
     # ------------------------------------------------------------------ plumbing
     def _stream(self):
@@ -260,6 +261,20 @@ class Engine:
                                          steps), "ggns_set_trace")
         self._trace[r] = (tx, tl, to)
         return self._trace[r]
+
+    def keep_dead_x(self, r: int):
+        """Record the positions of run r's dead points from now on (a device
+        tensor [dead_cap, d] in the run's precision)."""
+        c, lay = self.cfgs[r], self.layouts[r]
+        buf = self.torch.zeros((lay.dead_cap, c.d), dtype=self._fdtype(r), device=self.device)
+        _lib.check(self.L.ggns_set_dead_x(self.ctx, r, buf.data_ptr(), lay.dead_cap), "ggns_set_dead_x")
+        self._dead_x[r] = buf
+        return buf
+
+    def dead_x(self, r: int, n_dead: Optional[int] = None):
+        if n_dead is None:
+            n_dead = int(self.stats()[r]["n_dead"])
+        return self._dead_x[r][:min(n_dead, self.layouts[r].dead_cap)]
 
     # ------------------------------------------------------------------ likelihood
     def loglike(self, r: int, x, grad: bool = True):

@@ -170,3 +170,35 @@ def test_tile_shapes_agree_and_autotune_picks_one(torch):
         eng.close()
     choice = tune([cfg, cfg.replace(seed=62)])
     assert choice[0] == choice[1] and choice[0] in candidates(cfg)
+
+
+def test_dead_positions_follow_the_dead_records(torch):
+    """With positions kept, row j of dead_x is the live point the j-th dead
+    record came from: after one kill the killed rows in kill order, after the
+    final sweep every remaining live point, and their log L are the records'."""
+    cfg = inputs.config_gmm(d=12, n_live=200, n_comp=4, seed=45, param_seed=12)
+    eng = _engine([cfg])
+    eng.keep_dead_x(0)
+    lx = _np(eng.live_x(0)).copy()
+    ll = _np(eng.live_logl(0)).copy()
+    eng.evidence_update()
+    torch.cuda.synchronize()
+    killed = _np(eng.killed(0))
+    dl, _ = eng.dead(0)
+    dx = _np(eng.dead_x(0))
+    assert dx.shape == (cfg.n_kill, cfg.d)
+    np.testing.assert_array_equal(dx, lx[killed])
+    np.testing.assert_array_equal(_np(dl), ll[killed])
+    eng.hss_walk()
+    eng.replace_dead()
+    st = eng.run(poll_every=4)[0]
+    n_dead = st["n_dead"]
+    dl, dw = eng.dead(0)
+    dx = _np(eng.dead_x(0))
+    assert dx.shape[0] == n_dead
+    l_re, _ = eng.loglike(0, eng.dead_x(0)[-cfg.n_live:].clone(), grad=False)
+    np.testing.assert_allclose(_np(l_re), _np(dl)[-cfg.n_live:], rtol=2e-6, atol=1e-6)
+    # the mode report runs on the samples and finds the mixture's modes
+    from paper_2312_03911_amd.posterior import gmm_mode_report, normalized_log_weights
+    rep = gmm_mode_report(dx, normalized_log_weights(_np(dl), _np(dw), st["log_z"]), cfg)
+    assert rep["recovered"] >= 1 and abs(sum(rep["weights"]) - 1.0) < 1e-9
