@@ -317,7 +317,9 @@ typedef struct {
     int32_t term_kind, max_iter;
     double term_tol;
     uint64_t seed;
-    int32_t noise_mode, pad_;   /* R7: 0 per component, 1 one normal per walker */
+    int32_t noise_mode;         /* R7: 0 per component, 1 one normal per walker */
+    int32_t cluster_mode;       /* C1-C10: 0 one cluster, 1 cluster recognition and spawning */
+    int32_t cluster_kmax, pad_; /* C2: largest neighbour count tried */
 } orc_desc;
 
 enum { ST_ACTIVE = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3 };
@@ -343,6 +345,14 @@ typedef struct {
     double *trace_logl;   /* [trace_steps * n_kill] */
     int32_t *trace_out;   /* [trace_steps * n_kill] */
     int32_t trace_steps, pad2;
+    /* clusters (cluster_mode 1): label of each live slot; per cluster its
+     * log Xbar_p and live count; survivors grouped by cluster with offsets */
+    int32_t *label;        /* [n_live] */
+    double *clx;           /* [ORC_CL_MAX] */
+    int32_t *cn;           /* [ORC_CL_MAX] */
+    int32_t *surv_off;     /* [ORC_CL_MAX + 1] */
+    int32_t *start_cl;     /* [n_kill] cluster of each walker */
+    int32_t n_clusters, n_splits;
 } orc_state;
 
 /* Step 1 of the outer loop: n_live uniform prior draws and their likelihoods
@@ -370,6 +380,13 @@ int orc_init(const orc_desc *D, const double *prm, orc_state *S)
     S->it_outs = S->it_steps = 0;
     S->state = ST_ACTIVE;
     S->h = S->sigma_kl = S->sigma_mom = 0.0;
+    if (D->cluster_mode) {
+        for (int i = 0; i < n; ++i) S->label[i] = 0;
+        S->n_clusters = 1;
+        S->n_splits = 0;
+        S->clx[0] = 0.0;
+        S->cn[0] = n;
+    }
     return 0;
 }
 
@@ -421,6 +438,9 @@ static void sort_slots(const double *logl, int n, int32_t *order)
     free(tmp);
 }
 
+static void kill_one_cluster(orc_state *S, double l, int p);
+static double log_sum_clusters(const orc_state *S);
+
 /* Final sweep (Algorithm GGNS, closing loop; reading R17) and the run
  * summary: posterior weights p_i = L_i w_i / Z, H = sum p_i log(L_i / Z),
  * sigma_KL = sqrt(H / n_live), sigma_mom from the moments. */
@@ -429,8 +449,14 @@ static void final_sweep(const orc_desc *D, orc_state *S)
     int n = D->n_live;
     int32_t *order = (int32_t *)malloc(sizeof(int32_t) * n);
     sort_slots(S->live_logl, n, order);
-    for (int j = 0; j < n; ++j) kill_one(S, S->live_logl[order[j]], (int64_t)n - j);
+    for (int j = 0; j < n; ++j) {
+        if (D->cluster_mode)
+            kill_one_cluster(S, S->live_logl[order[j]], S->label[order[j]]);
+        else
+            kill_one(S, S->live_logl[order[j]], (int64_t)n - j);
+    }
     free(order);
+    if (D->cluster_mode) S->lx = log_sum_clusters(S);
     int64_t nd = S->n_dead < S->dead_cap ? S->n_dead : S->dead_cap;
     double h = 0.0;
     for (int64_t i = 0; i < nd; ++i) {
@@ -440,7 +466,190 @@ static void final_sweep(const orc_desc *D, orc_state *S)
     S->h = h;
     S->sigma_kl = sqrt(h > 0.0 ? h / n : 0.0);
     double v = S->lz2 - 2.0 * S->lz;
-    S->sigma_mom = sqrt(v > 0.0 ? v : 0.0);
+    S->sigma_mom = D->cluster_mode ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
+}
+
+/* ------------------------------------------------------------------------
+ * Clusters (cluster_mode 1): recognition by k-nearest neighbours, per-cluster
+ * prior volumes, spawning in proportion to them (Section 3, mode collapse
+ * mitigation; Algorithm GGNS with its cluster-finding algorithm; Eqs. new0,
+ * new4 for the split of the volume).  Readings:
+ *   C1  cluster finding runs at the start of every iteration that goes on,
+ *       once for each existing cluster (clusters created in this iteration
+ *       are not re-examined in it);
+ *   C2  for k = 2, 3, ...: link every point of the cluster to its k nearest
+ *       other points of the cluster (squared Euclidean distance, ties by slot),
+ *       take the connected components of the undirected graph and their
+ *       sizes; stop at the first k whose sorted sizes equal those of k - 1 and
+ *       use that k's components.  k runs up to min(cluster_kmax, m - 1) for m
+ *       points; if it never stops, or m < 3, the cluster stays whole;
+ *   C3  the components, ordered by their smallest slot, become clusters: the
+ *       first keeps the old index, the others take new indices (at most
+ *       ORC_CL_MAX clusters; a split that would exceed it is not made); the
+ *       volume splits as Xbar_i = (n_i / n) Xbar_p (Eq. new0);
+ *   C4  a killed point of cluster p with n_p live points before its removal
+ *       has weight Xbar_p / (n_p + 1) and Xbar_p <- n_p Xbar_p / (n_p + 1)
+ *       (Eqs. update0, update2); a cluster left without points is removed;
+ *       the run's Xbar is the sum over clusters;
+ *   C5  each walker draws its cluster p with probability Xbar_p / sum_q Xbar_q
+ *       over the clusters with survivors (start stream word 1, inverse CDF in
+ *       cluster order), then a start uniformly among that cluster's survivors
+ *       (word 0); the new point joins that cluster;
+ *   C6  the second-moment recursion is single-cluster only: sigma_mom is not
+ *       computed in cluster mode (sigma_KL is).
+ * ------------------------------------------------------------------------ */
+#define ORC_CL_MAX 64
+
+static double dist2(const double *a, const double *b, int d)
+{
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double t = a[i] - b[i];
+        s = s + t * t;
+    }
+    return s;
+}
+
+/* the K nearest other points of each of the m points idx[0..m) (local
+ * indices into idx), ordered by (squared distance, slot) */
+static void knn_lists(const double *X, int d, const int32_t *idx, int m, int K, int32_t *nb)
+{
+    double *bd = (double *)malloc(sizeof(double) * (K > 0 ? K : 1));
+    int32_t *bi = (int32_t *)malloc(sizeof(int32_t) * (K > 0 ? K : 1));
+    for (int i = 0; i < m; ++i) {
+        int cnt = 0;
+        const double *xi = X + (int64_t)idx[i] * d;
+        for (int j = 0; j < m; ++j) {
+            if (j == i) continue;
+            double dd = dist2(xi, X + (int64_t)idx[j] * d, d);
+            /* insertion into the sorted list of the best K so far */
+            int pos = cnt;
+            while (pos > 0 && (dd < bd[pos - 1] || (dd == bd[pos - 1] && idx[j] < idx[bi[pos - 1]])))
+                --pos;
+            if (pos >= K) continue;
+            int last = cnt < K ? cnt : K - 1;
+            for (int t = last; t > pos; --t) { bd[t] = bd[t - 1]; bi[t] = bi[t - 1]; }
+            bd[pos] = dd;
+            bi[pos] = j;
+            if (cnt < K) ++cnt;
+        }
+        for (int t = 0; t < K; ++t) nb[(int64_t)i * K + t] = bi[t];
+    }
+    free(bd);
+    free(bi);
+}
+
+static int uf_find(int32_t *par, int i)
+{
+    while (par[i] != i) i = par[i];
+    return i;
+}
+
+/* connected components of the graph linking each point to its first k
+ * neighbours; root[i] = smallest local index of i's component; the sizes,
+ * sorted in decreasing order, go to sizes[0..returned count) */
+static int components(int m, int k, int K, const int32_t *nb, int32_t *root, int32_t *sizes)
+{
+    int32_t *par = (int32_t *)malloc(sizeof(int32_t) * m);
+    for (int i = 0; i < m; ++i) par[i] = i;
+    for (int i = 0; i < m; ++i)
+        for (int t = 0; t < k; ++t) {
+            int a = uf_find(par, i), b = uf_find(par, nb[(int64_t)i * K + t]);
+            if (a != b) { if (a < b) par[b] = a; else par[a] = b; }
+        }
+    int nc = 0;
+    int32_t *count = (int32_t *)calloc((size_t)m, sizeof(int32_t));
+    for (int i = 0; i < m; ++i) { root[i] = uf_find(par, i); count[root[i]] += 1; }
+    for (int i = 0; i < m; ++i)
+        if (count[i] > 0) sizes[nc++] = count[i];
+    /* decreasing order (insertion sort; nc is small in practice) */
+    for (int a = 1; a < nc; ++a) {
+        int v = sizes[a], b = a;
+        while (b > 0 && sizes[b - 1] < v) { sizes[b] = sizes[b - 1]; --b; }
+        sizes[b] = v;
+    }
+    free(par);
+    free(count);
+    return nc;
+}
+
+/* Cluster finding for every cluster that exists now (C1-C3). */
+static void find_clusters(const orc_desc *D, orc_state *S)
+{
+    int n = D->n_live, d = D->d;
+    int n_before = S->n_clusters;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *root = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *best = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *sz = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * n);
+    for (int p = 0; p < n_before; ++p) {
+        int m = 0;
+        for (int i = 0; i < n; ++i)
+            if (S->label[i] == p) idx[m++] = i;
+        if (m < 3) continue;
+        int K = D->cluster_kmax < m - 1 ? D->cluster_kmax : m - 1;
+        if (K < 2) continue;
+        int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * K);
+        knn_lists(S->live_x, d, idx, m, K, nb);
+        int nprev = -1, found = 0, nc = 0;
+        for (int k = 2; k <= K; ++k) {
+            nc = components(m, k, K, nb, root, sz);
+            int same = (nc == nprev);
+            for (int t = 0; same && t < nc; ++t) same = (sz[t] == prev[t]);
+            if (same) { found = 1; break; }
+            memcpy(prev, sz, sizeof(int32_t) * nc);
+            nprev = nc;
+        }
+        free(nb);
+        if (!found || nc < 2 || S->n_clusters + nc - 1 > ORC_CL_MAX) continue;
+        /* components in order of their smallest slot (= their root, local) */
+        for (int i = 0; i < m; ++i) best[i] = -1;
+        int next = 0;
+        for (int i = 0; i < m; ++i)
+            if (root[i] == i) best[i] = next++;
+        double lxp = S->clx[p], lm = log((double)m);
+        int32_t *cnt = (int32_t *)calloc((size_t)nc, sizeof(int32_t));
+        for (int i = 0; i < m; ++i) cnt[best[root[i]]] += 1;
+        for (int c = 0; c < nc; ++c) {
+            int q = (c == 0) ? p : S->n_clusters + c - 1;
+            S->clx[q] = lxp + log((double)cnt[c]) - lm;
+            S->cn[q] = cnt[c];
+        }
+        for (int i = 0; i < m; ++i) {
+            int c = best[root[i]];
+            S->label[idx[i]] = (c == 0) ? p : S->n_clusters + c - 1;
+        }
+        S->n_clusters += nc - 1;
+        S->n_splits += 1;
+        free(cnt);
+    }
+    free(idx); free(root); free(best); free(sz); free(prev);
+}
+
+static double log_sum_clusters(const orc_state *S)
+{
+    double r = -INFINITY;
+    for (int p = 0; p < S->n_clusters; ++p)
+        if (S->cn[p] > 0) r = logaddexp(r, S->clx[p]);
+    return r;
+}
+
+/* Kill one point of cluster p (C4): dead record, evidence, volume. */
+static void kill_one_cluster(orc_state *S, double l, int p)
+{
+    int n_p = S->cn[p];
+    double ln = log((double)n_p), ln1 = log((double)n_p + 1.0);
+    double logw = S->clx[p] - ln1;
+    if (S->n_dead < S->dead_cap) {
+        S->dead_logl[S->n_dead] = l;
+        S->dead_logw[S->n_dead] = logw;
+    }
+    S->n_dead += 1;
+    S->lz = logaddexp(S->lz, logw + l);
+    S->clx[p] = S->clx[p] + ln - ln1;
+    S->cn[p] = n_p - 1;
+    if (S->cn[p] == 0) S->clx[p] = -INFINITY;
 }
 
 /* Termination test, kill step and evidence update of one iteration
@@ -465,18 +674,33 @@ int orc_evidence_update(const orc_desc *D, orc_state *S, int force_final)
     if (!stop && S->iter >= D->max_iter) { final_sweep(D, S); S->state = ST_MAXITER; return 0; }
     if (stop) { final_sweep(D, S); S->state = ST_DONE; return 0; }
 
+    if (D->cluster_mode) find_clusters(D, S);
     int32_t *order = (int32_t *)malloc(sizeof(int32_t) * n);
     sort_slots(S->live_logl, n, order);
     for (int j = 0; j < k; ++j) {
         S->killed[j] = order[j];
-        kill_one(S, S->live_logl[order[j]], (int64_t)n - j);
+        if (D->cluster_mode)
+            kill_one_cluster(S, S->live_logl[order[j]], S->label[order[j]]);
+        else
+            kill_one(S, S->live_logl[order[j]], (int64_t)n - j);
     }
     S->lstar = S->live_logl[order[k - 1]];
     char *dead = (char *)calloc((size_t)n, 1);
     for (int j = 0; j < k; ++j) dead[order[j]] = 1;
     int m = 0;
-    for (int i = 0; i < n; ++i)
-        if (!dead[i]) S->surv[m++] = i;
+    if (D->cluster_mode) {
+        /* survivors grouped by cluster, ascending slot within each */
+        for (int p = 0; p < S->n_clusters; ++p) {
+            S->surv_off[p] = m;
+            for (int i = 0; i < n; ++i)
+                if (!dead[i] && S->label[i] == p) S->surv[m++] = i;
+        }
+        S->surv_off[S->n_clusters] = m;
+        S->lx = log_sum_clusters(S);
+    } else {
+        for (int i = 0; i < n; ++i)
+            if (!dead[i]) S->surv[m++] = i;
+    }
     free(dead);
     free(order);
     return 0;
@@ -492,7 +716,28 @@ static void walk_one(const orc_desc *D, const double *prm, orc_state *S, int m,
     uint32_t it = (uint32_t)S->iter;
     uint32_t u[4];
     stream_draw(D->seed, 0u, (uint32_t)m, it, TAG_START, 0u, u);
-    int s = S->surv[(int)(((uint64_t)u[0] * (uint64_t)nsurv) >> 32)];
+    int s;
+    if (D->cluster_mode) {
+        /* C5: the walker's cluster in proportion to Xbar_p, then a survivor of it */
+        double cmax = -INFINITY, tot = 0.0;
+        for (int p = 0; p < S->n_clusters; ++p)
+            if (S->surv_off[p + 1] > S->surv_off[p] && S->clx[p] > cmax) cmax = S->clx[p];
+        for (int p = 0; p < S->n_clusters; ++p)
+            if (S->surv_off[p + 1] > S->surv_off[p]) tot += exp(S->clx[p] - cmax);
+        double target = ((double)u[1] + 0.5) * 0x1p-32 * tot, cum = 0.0;
+        int pc = -1;
+        for (int p = 0; p < S->n_clusters; ++p) {
+            if (S->surv_off[p + 1] == S->surv_off[p]) continue;
+            cum += exp(S->clx[p] - cmax);
+            pc = p;
+            if (target < cum) break;
+        }
+        int cnt = S->surv_off[pc + 1] - S->surv_off[pc];
+        s = S->surv[S->surv_off[pc] + (int)(((uint64_t)u[0] * (uint64_t)cnt) >> 32)];
+        S->start_cl[m] = pc;
+    } else {
+        s = S->surv[(int)(((uint64_t)u[0] * (uint64_t)nsurv) >> 32)];
+    }
     S->start[m] = s;
     double *x = (double *)malloc(sizeof(double) * d);
     double *x0 = (double *)malloc(sizeof(double) * d);
@@ -621,6 +866,11 @@ int orc_replace_dead(const orc_desc *D, orc_state *S)
         int slot = S->killed[m];
         memcpy(S->live_x + (int64_t)slot * d, S->out_x + (int64_t)m * d, sizeof(double) * d);
         S->live_logl[slot] = S->out_logl[m];
+        if (D->cluster_mode) {
+            int p = S->start_cl[m];
+            S->label[slot] = p;
+            S->cn[p] += 1;
+        }
     }
     if (S->it_steps > 0) {
         double out_frac = (double)S->it_outs / (double)S->it_steps;

@@ -43,7 +43,8 @@ class _Desc(C.Structure):
                 ("dt_down", C.c_double), ("dt_up", C.c_double),
                 ("term_kind", C.c_int32), ("max_iter", C.c_int32),
                 ("term_tol", C.c_double), ("seed", C.c_uint64),
-                ("noise_mode", C.c_int32), ("pad", C.c_int32)]
+                ("noise_mode", C.c_int32), ("cluster_mode", C.c_int32),
+                ("cluster_kmax", C.c_int32), ("pad", C.c_int32)]
 
 
 _PD = C.POINTER(C.c_double)
@@ -64,7 +65,11 @@ class _State(C.Structure):
                 ("state", C.c_int32), ("pad", C.c_int32),
                 ("h", C.c_double), ("sigma_kl", C.c_double), ("sigma_mom", C.c_double),
                 ("trace_x", _PD), ("trace_logl", _PD), ("trace_out", _PI),
-                ("trace_steps", C.c_int32), ("pad2", C.c_int32)]
+                ("trace_steps", C.c_int32), ("pad2", C.c_int32),
+                ("label", _PI), ("clx", _PD), ("cn", _PI), ("surv_off", _PI), ("start_cl", _PI),
+                ("n_clusters", C.c_int32), ("n_splits", C.c_int32)]
+
+CL_MAX = 64
 
 
 def lib():
@@ -183,7 +188,8 @@ class Oracle:
                           dt_down=cfg.dt_down, dt_up=cfg.dt_up, term_kind=cfg.term_kind,
                           max_iter=cfg.max_iter, term_tol=cfg.term_tol,
                           seed=C.c_uint64(int(cfg.seed) & (2**64 - 1)),
-                          noise_mode=cfg.noise_id)
+                          noise_mode=cfg.noise_id, cluster_mode=int(cfg.cluster),
+                          cluster_kmax=int(cfg.cluster_kmax))
         self.params = np.ascontiguousarray(cfg.params, dtype=np.float64)
         cap = k * cfg.max_iter + n
         self.live_x = np.zeros((n, d))
@@ -207,6 +213,13 @@ class Oracle:
                          trace_x=_dp(self.trace_x) if trace_steps else None,
                          trace_logl=_dp(self.trace_logl), trace_out=_ip(self.trace_out),
                          trace_steps=self.trace_steps)
+        self.label = np.zeros(n, np.int32)
+        self.clx = np.full(CL_MAX, -np.inf)
+        self.cn = np.zeros(CL_MAX, np.int32)
+        self.surv_off = np.zeros(CL_MAX + 1, np.int32)
+        self.start_cl = np.zeros(k, np.int32)
+        self.st.label, self.st.clx, self.st.cn = _ip(self.label), _dp(self.clx), _ip(self.cn)
+        self.st.surv_off, self.st.start_cl = _ip(self.surv_off), _ip(self.start_cl)
 
     # -- steps
     def init(self):
