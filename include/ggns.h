@@ -117,6 +117,11 @@ typedef struct {
     int32_t noise_mode;      /* the eps of p <- p (1 + delta_p eps) (Algorithm GGNS HSS):
                                 0 = one normal per coordinate (default reading),
                                 1 = one normal per walker and step, the first of its stream */
+    int32_t cluster_mode;    /* 1: cluster recognition and spawning in proportion to the clusters'
+                                prior volumes (Section 3, mode collapse mitigation; Algorithm GGNS
+                                with its cluster-finding algorithm; Eqs. update0, update2, new0);
+                                0: one cluster.  sigma_mom is not computed in cluster mode. */
+    int32_t cluster_kmax;    /* largest neighbour count the cluster finding tries, 2..16 */
 } ggns_run_desc;
 
 /* Byte offsets (from the arena base) of one run's arrays. */
@@ -133,6 +138,11 @@ typedef struct {
     int64_t dead_cap;        /* capacity (elements) */
     int32_t elem_bytes;      /* 8 (FP64) or 4 */
     int32_t reserved;
+    int64_t label;           /* cluster mode: [n_live] int32 cluster of each live slot; else -1 */
+    int64_t cluster_table;   /* cluster mode: double log_xbar[64], double spawn_cdf[64],
+                                int32 n_live[64], int32 survivor_offsets[65],
+                                int32 member_offsets[65], int32 n_clusters, n_splits, stopping,
+                                pad; survivors are grouped by cluster; else -1 */
 } ggns_layout;
 
 /* Per-run results and counters. */
@@ -145,7 +155,7 @@ typedef struct {
     double log_xl_max;       /* running max of log(X * L_max) (X*L peak criterion) */
     double h;                /* information H = sum p_i log(L_i / Z), after ggns_finalize */
     double sigma_kl;         /* sqrt(H / n_live) (Eq. logZ_error) */
-    double sigma_mom;        /* sqrt(log Z2bar - 2 log Zbar) */
+    double sigma_mom;        /* sqrt(log Z2bar - 2 log Zbar); 0 in cluster mode */
     int64_t iter;            /* iterations done */
     int64_t evals;           /* likelihood+gradient evaluations (n_live + walker steps) */
     int64_t n_dead;          /* dead records written */
@@ -154,7 +164,7 @@ typedef struct {
     int64_t nosave;          /* walks that saved no point (fell back to the last in-slice point) */
     int64_t it_outs, it_steps;    /* counters of the last walk (out_frac) */
     int32_t state;           /* GGNS_RUN_* */
-    int32_t reserved;
+    int32_t n_clusters;      /* cluster mode: cluster indices in use (removed ones included); else 0 */
 } ggns_run_stats;
 
 /* Values a caller may load into a run (tests, checkpoint/resume). */

@@ -31,14 +31,16 @@ class ggns_run_desc(C.Structure):
                 ("delta_p", C.c_double), ("out_hi", C.c_double), ("out_lo", C.c_double),
                 ("dt_down", C.c_double), ("dt_up", C.c_double),
                 ("term_kind", C.c_int32), ("max_iter", C.c_int32), ("term_tol", C.c_double),
-                ("seed", C.c_uint64), ("tile_c", C.c_int32), ("noise_mode", C.c_int32)]
+                ("seed", C.c_uint64), ("tile_c", C.c_int32), ("noise_mode", C.c_int32),
+                ("cluster_mode", C.c_int32), ("cluster_kmax", C.c_int32)]
 
 
 class ggns_layout(C.Structure):
     _fields_ = [("live_x", C.c_int64), ("live_logl", C.c_int64), ("killed", C.c_int64),
                 ("survivors", C.c_int64), ("start", C.c_int64), ("walk_x", C.c_int64),
                 ("walk_logl", C.c_int64), ("dead_logl", C.c_int64), ("dead_logw", C.c_int64),
-                ("dead_cap", C.c_int64), ("elem_bytes", C.c_int32), ("reserved", C.c_int32)]
+                ("dead_cap", C.c_int64), ("elem_bytes", C.c_int32), ("reserved", C.c_int32),
+                ("label", C.c_int64), ("cluster_table", C.c_int64)]
 
 
 class ggns_run_stats(C.Structure):
@@ -48,7 +50,7 @@ class ggns_run_stats(C.Structure):
                 ("iter", C.c_int64), ("evals", C.c_int64), ("n_dead", C.c_int64),
                 ("steps_out", C.c_int64), ("steps_in", C.c_int64), ("prunes", C.c_int64),
                 ("nosave", C.c_int64), ("it_outs", C.c_int64), ("it_steps", C.c_int64),
-                ("state", C.c_int32), ("reserved", C.c_int32)]
+                ("state", C.c_int32), ("n_clusters", C.c_int32)]
 
 
 class ggns_run_vars(C.Structure):

@@ -39,6 +39,8 @@ bool valid_desc(const ggns_run_desc &r) {
     if (r.param_offset < 0) return false;
     if (r.tile_c < 0 || r.tile_c > 16) return false;
     if (r.noise_mode != 0 && r.noise_mode != 1) return false;
+    if (r.cluster_mode != 0 && r.cluster_mode != 1) return false;
+    if (r.cluster_mode && (r.cluster_kmax < 2 || r.cluster_kmax > kKnnMax)) return false;
     return true;
 }
 
@@ -95,6 +97,8 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.out_hi = D.out_hi; R.out_lo = D.out_lo; R.dt_down = D.dt_down; R.dt_up = D.dt_up;
         R.term_tol = D.term_tol; R.seed = D.seed; R.param_offset = D.param_offset;
         R.noise_mode = D.noise_mode;
+        R.cluster_mode = D.cluster_mode;
+        R.cluster_kmax = D.cluster_mode ? D.cluster_kmax : 0;
         const bool mma = D.precision == GGNS_FP32_BF16MMA;
         if (!mma && D.tile_c != 0 && D.tile_c != 1 && D.tile_c != 2 && D.tile_c != 4 && D.tile_c != 8)
             return GGNS_EUNSUPPORTED;
@@ -130,6 +134,15 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.off_walk_logl = off; off = align_up(off + (int64_t)D.n_kill * 8);
         R.off_dead_logl = off; off = align_up(off + R.dead_cap * 8);
         R.off_dead_logw = off; off = align_up(off + R.dead_cap * 8);
+        if (D.cluster_mode) {
+            R.off_label = off; off = align_up(off + (int64_t)D.n_live * 4);
+            R.off_cltab = off; off = align_up(off + (int64_t)sizeof(ClusterTab));
+            R.off_members = off; off = align_up(off + (int64_t)D.n_live * 4);
+            R.off_knn = off; off = align_up(off + (int64_t)D.n_live * kKnnMax * 4);
+            R.off_start_cl = off; off = align_up(off + (int64_t)D.n_kill * 4);
+        } else {
+            R.off_label = R.off_cltab = R.off_members = R.off_knn = R.off_start_cl = -1;
+        }
     }
     P.total = off;
     return GGNS_OK;
@@ -157,6 +170,8 @@ struct ggns_ctx {
     std::vector<Class> walk_classes, init_classes;
     std::vector<Acc> acc_host;
     int max_kd = 1;
+    bool any_cluster = false, any_fp64 = false, any_fp32 = false;
+    int max_live = 0;
     // walk classes after the first run on side streams forked from and joined
     // back into the caller's stream (default priority; capturable)
     std::vector<hipStream_t> side;
@@ -265,6 +280,13 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
     c->params = params_dev;
     c->n_params = n_params;
     build_classes(c);
+    for (const RunDev &R : c->plan.runs) {
+        if (R.cluster_mode) {
+            c->any_cluster = true;
+            c->max_live = std::max(c->max_live, R.n_live);
+            if (R.prec == GGNS_FP64) c->any_fp64 = true; else c->any_fp32 = true;
+        }
+    }
     for (size_t i = 1; i < c->walk_classes.size(); ++i) {
         hipStream_t ss;
         hipEvent_t e;
@@ -324,6 +346,12 @@ int ggns_attach(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const
 
 int ggns_evidence_update(ggns_ctx *ctx, int32_t final_sweep, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
+    if (ctx->any_cluster) {
+        const int rc = launch_clusters(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(),
+                                       ctx->max_live, final_sweep ? 1 : 0, ctx->any_fp64,
+                                       ctx->any_fp32, reinterpret_cast<hipStream_t>(stream));
+        if (rc != GGNS_OK) return rc;
+    }
     launch_evidence(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), final_sweep ? 1 : 0,
                     reinterpret_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
@@ -430,6 +458,8 @@ int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out) {
     out->dead_cap = R.dead_cap;
     out->elem_bytes = (R.prec == GGNS_FP64) ? 8 : 4;
     out->reserved = 0;
+    out->label = R.off_label;
+    out->cluster_table = R.off_cltab;
     return GGNS_OK;
 }
 
@@ -452,7 +482,7 @@ int ggns_read_stats(ggns_ctx *ctx, ggns_run_stats *out, void *stream) {
         o.iter = a.iter; o.evals = a.evals; o.n_dead = a.n_dead; o.steps_out = a.steps_out;
         o.steps_in = a.steps_in; o.prunes = a.prunes; o.nosave = a.nosave;
         o.it_outs = (int64_t)a.it_outs; o.it_steps = (int64_t)a.it_steps;
-        o.state = a.state; o.reserved = 0;
+        o.state = a.state; o.n_clusters = a.n_clusters;
     }
     return GGNS_OK;
 }

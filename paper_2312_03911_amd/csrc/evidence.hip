@@ -196,9 +196,9 @@ __device__ void run_summary(const RunDev &R, Acc *acc, const double *dl, const d
     if (t == 0) {
         acc->h = h;
         acc->sigma_kl = sqrt(h > 0.0 ? h / n : 0.0);
-        acc->log_z2 = lz2;
+        acc->log_z2 = R.cluster_mode ? -INFINITY : lz2;
         const double v = lz2 - 2.0 * lzr;
-        acc->sigma_mom = sqrt(v > 0.0 ? v : 0.0);
+        acc->sigma_mom = R.cluster_mode ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
     }
 }
 
@@ -234,25 +234,23 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
             slot[i] = 0x7FFFFFFF;
         }
     }
-    lmax = block_max(lmax, scratch);   // contains the barriers
+    lmax = block_max_d(lmax, scratch);   // contains the barriers
     if (flags[0]) {
         if (t == 0) acc->state = GGNS_RUN_NONFINITE;
         return;
     }
     // termination test (reading: remaining-evidence or X*L peak)
     if (t == 0) {
-        int stop = final_sweep ? GGNS_RUN_DONE : 0;
-        const double ltol = log(R.term_tol);
-        if (R.term_kind == GGNS_TERM_REMAINING_Z) {
-            if (acc->log_x + lmax < ltol + acc->log_z) stop = GGNS_RUN_DONE;
-        } else {
-            const double r = acc->log_x + lmax;
-            if (r > acc->log_xl_max) acc->log_xl_max = r;
-            if (acc->iter > 0 && r - acc->log_xl_max < ltol) stop = GGNS_RUN_DONE;
-        }
-        if (!stop && acc->iter >= R.max_iter) stop = GGNS_RUN_MAXITER;
-        flags[1] = stop;
+        double xl = acc->log_xl_max;
+        flags[1] = termination_decision(R, acc, lmax, final_sweep, &xl);
+        acc->log_xl_max = xl;
     }
+    // cluster mode: per-cluster counts of this batch's kills
+    const bool clm = R.cluster_mode != 0;
+    ClusterTab *tab = clm ? at<ClusterTab>(arena, R.off_cltab) : nullptr;
+    int32_t *label = clm ? at<int32_t>(arena, R.off_label) : nullptr;
+    __shared__ int kcount[kClMax];
+    for (int p = t; p < kClMax; p += T) kcount[p] = 0;
     // bitonic sort of (log L, slot) ascending.  A compare-exchange stage of
     // stride j only touches blocks of 2j consecutive keys, so every stage with
     // 2j <= CH runs inside one wavefront's chunk of CH keys with wavefront-level
@@ -306,15 +304,24 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     const double lw = acc->log_x - log((double)n + 1.0);
     const int nkill = stop ? n : k;
 
-    // dead records and the log-sum-exp of the killed log L
+    // dead records and the log-sum-exp of the killed log L.  With clusters a
+    // killed point of cluster p weighs Xbar_p / (n_p + 1) with n_p its live
+    // count before the batch: the per-point updates Xbar_p <- n Xbar_p/(n+1)
+    // within the batch telescope to that (Eqs. update0, update2)
     double m_loc = -INFINITY, s_loc = 0.0;
     for (int j = t; j < nkill; j += T) {
         const double v = key_value(key[j]);
+        double wj = lw;
+        if (clm) {
+            const int p = label[slot[j]];
+            wj = tab->clx[p] - log((double)tab->cn[p] + 1.0);
+            atomicAdd(&kcount[p], 1);
+        }
         if (nd + j < R.dead_cap) {
             dead_l[nd + j] = v;
-            dead_w[nd + j] = lw;
+            dead_w[nd + j] = wj;
         }
-        lse_push(v, m_loc, s_loc);
+        lse_push(clm ? v + wj : v, m_loc, s_loc);
     }
     // positions of the dead points in the same order (posterior samples)
     if (R.dead_x != nullptr) {
@@ -335,12 +342,29 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     }
     const double lse = block_lse(m_loc, s_loc, scratch);
     if (t == 0) {
-        acc->log_z = lae(acc->log_z, lse + lw);
+        acc->log_z = lae(acc->log_z, clm ? lse : lse + lw);
         acc->n_dead = nd + nkill;
+        if (clm) {
+            // volumes after the batch: Xbar_p (n_p - k_p + 1) / (n_p + 1); a
+            // cluster left without points is removed; Xbar = sum over clusters
+            double lsum = -INFINITY;
+            for (int p = 0; p < tab->n_clusters; ++p) {
+                const int kp = kcount[p], np = tab->cn[p];
+                if (kp > 0) {
+                    tab->clx[p] = (np - kp > 0)
+                        ? tab->clx[p] + (log((double)(np - kp + 1)) - log((double)np + 1.0))
+                        : -INFINITY;
+                    tab->cn[p] = np - kp;
+                }
+                if (tab->cn[p] > 0) lsum = lae(lsum, tab->clx[p]);
+            }
+            acc->log_x = lsum;
+            acc->n_clusters = tab->n_clusters;
+        }
         if (stop) {
-            acc->log_x = lw;
+            if (!clm) acc->log_x = lw;
         } else {
-            acc->log_x += log((double)(n + 1 - k)) - log((double)n + 1.0);
+            if (!clm) acc->log_x += log((double)(n + 1 - k)) - log((double)n + 1.0);
             acc->lstar = key_value(key[k - 1]);
             acc->it_outs = 0ull;
             acc->it_steps = 0ull;
@@ -367,15 +391,56 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     __syncthreads();
     for (int j = t; j < k; j += T) dead_flag[killed[j]] = 1;
     __syncthreads();
-    // each thread owns a contiguous range of slots
-    const int per = (n + T - 1) / T;
-    const int s0 = t * per, s1 = (s0 + per < n) ? s0 + per : n;
-    int cnt = 0;
-    for (int i = s0; i < s1; ++i) cnt += dead_flag[i] ? 0 : 1;
-    __shared__ int ibuf[kEvThreads];
-    int pos = block_exscan_int(cnt, ibuf);
-    for (int i = s0; i < s1; ++i)
-        if (!dead_flag[i]) surv[pos++] = i;
+    if (!clm) {
+        // each thread owns a contiguous range of slots
+        const int per = (n + T - 1) / T;
+        const int s0 = t * per, s1 = (s0 + per < n) ? s0 + per : n;
+        int cnt = 0;
+        for (int i = s0; i < s1; ++i) cnt += dead_flag[i] ? 0 : 1;
+        __shared__ int ibuf[kEvThreads];
+        int pos = block_exscan_int(cnt, ibuf);
+        for (int i = s0; i < s1; ++i)
+            if (!dead_flag[i]) surv[pos++] = i;
+        return;
+    }
+    // cluster mode: survivors grouped by cluster (ascending slot within each),
+    // by a sort of (label, slot) keys; the spawning CDF over the clusters
+    for (int i = t; i < NP; i += T)
+        key[i] = (i < n && !dead_flag[i]) ? (((unsigned long long)label[i] << 12) | (unsigned long long)i)
+                                         : ~0ull;
+    for (int size = 2; size <= NP; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = t; i < (NP >> 1); i += T) {
+                const int lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const unsigned long long a = key[lo], b = key[hi];
+                if ((a > b) == asc) { key[lo] = b; key[hi] = a; }
+            }
+        }
+    }
+    __syncthreads();
+    const int nsurv = n - k;
+    for (int i = t; i < nsurv; i += T) surv[i] = (int32_t)(key[i] & 0xFFFull);
+    const int ncl = tab->n_clusters;
+    for (int p = t; p <= ncl; p += T) {
+        int lo = 0, hi = nsurv;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((int)(key[mid] >> 12) < p) lo = mid + 1; else hi = mid;
+        }
+        tab->soff[p] = lo;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double cmax = -INFINITY, cum = 0.0;
+        for (int p = 0; p < ncl; ++p)
+            if (tab->soff[p + 1] > tab->soff[p] && tab->clx[p] > cmax) cmax = tab->clx[p];
+        for (int p = 0; p < ncl; ++p) {
+            if (tab->soff[p + 1] > tab->soff[p]) cum += exp(tab->clx[p] - cmax);
+            tab->cum[p] = cum;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kEvThreads)

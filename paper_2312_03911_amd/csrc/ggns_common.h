@@ -42,6 +42,23 @@ struct RunDev {
     // positions of the dead points (posterior samples), caller-owned; null when off
     void *dead_x;
     int64_t dead_x_cap;        // rows of dead_x
+    // clusters (cluster_mode 1): labels per live slot, the cluster table, the
+    // live slots grouped by cluster, k-nearest-neighbour lists, walker clusters
+    int32_t cluster_mode, cluster_kmax;
+    int64_t off_label, off_cltab, off_members, off_knn, off_start_cl;
+};
+
+constexpr int kClMax = 64;      // clusters per run
+constexpr int kKnnMax = 16;     // neighbours kept per point
+
+// Per-run cluster table (arena).
+struct ClusterTab {
+    double clx[kClMax];         // log Xbar_p (-inf: removed)
+    double cum[kClMax];         // spawning CDF over clusters with survivors (scaled)
+    int32_t cn[kClMax];         // live points per cluster
+    int32_t soff[kClMax + 1];   // survivors grouped by cluster: offsets into the survivor list
+    int32_t moff[kClMax + 1];   // live slots grouped by cluster: offsets into members
+    int32_t n_clusters, n_splits, stopping, pad;
 };
 
 // Mutable per-run state on the device.
@@ -50,6 +67,7 @@ struct Acc {
     long long iter, evals, n_dead, steps_out, steps_in, prunes, nosave;
     unsigned long long it_outs, it_steps;
     int32_t state, summary_pending;
+    int32_t n_clusters, pad_acc;   // cluster indices in use (cluster mode)
 };
 
 // A walk work item: walkers [m_begin, m_end) of one run.
@@ -84,6 +102,8 @@ int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev
 int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_blocks, int steps,
                          float *normals, uint32_t *words, float *checksum, hipStream_t s);
 int launch_gather_acc(void *arena, const RunDev *runs_dev, int n_runs, Acc *mirror, hipStream_t s);
+int launch_clusters(void *arena, const RunDev *runs_dev, int n_runs, int max_live, int final_sweep,
+                    bool any_fp64, bool any_fp32, hipStream_t s);
 void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,
                      long long iter, hipStream_t s);
 

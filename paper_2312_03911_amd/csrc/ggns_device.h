@@ -500,6 +500,73 @@ __host__ __device__ inline int64_t converted_size(int var, int d, int dp) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Run-level helpers shared by the evidence and cluster kernels.
+// ---------------------------------------------------------------------------
+
+// Maximum over a workgroup of up to 1024 threads (barriers inside).
+__device__ inline double block_max_d(double v, double *scratch) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    double r = scratch[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = scratch[i] > r ? scratch[i] : r;
+    __syncthreads();
+    return r;
+}
+
+// Termination test at the head of an iteration (remaining evidence, or the
+// X L peak), or max_iter: 0 to go on, else the run's final state.  The new
+// running maximum of X L goes to *xl_max when it is not null.
+__device__ inline int termination_decision(const RunDev &R, const Acc *acc, double lmax,
+                                           int final_sweep, double *xl_max) {
+    int stop = final_sweep ? GGNS_RUN_DONE : 0;
+    const double ltol = log(R.term_tol);
+    if (R.term_kind == GGNS_TERM_REMAINING_Z) {
+        if (acc->log_x + lmax < ltol + acc->log_z) stop = GGNS_RUN_DONE;
+    } else {
+        const double r = acc->log_x + lmax;
+        const double xl = r > acc->log_xl_max ? r : acc->log_xl_max;
+        if (xl_max) *xl_max = xl;
+        if (acc->iter > 0 && r - xl < ltol) stop = GGNS_RUN_DONE;
+    }
+    if (!stop && acc->iter >= R.max_iter) stop = GGNS_RUN_MAXITER;
+    return stop;
+}
+
+// A walker's start: without clusters a survivor picked by word 0; with
+// clusters first the cluster, in proportion to its prior volume over the
+// clusters with survivors (word 1 against the spawning CDF), then one of its
+// survivors (word 0).  Writes the cluster to *cl.
+__device__ inline int pick_start(const RunDev &R, void *arena, const uint32_t (&w)[4], int *cl) {
+    const int32_t *surv = at<int32_t>(arena, R.off_surv);
+    if (!R.cluster_mode) {
+        *cl = 0;
+        const int nsurv = R.n_live - R.n_kill;
+        return surv[(int)(((uint64_t)w[0] * (uint64_t)nsurv) >> 32)];
+    }
+    const ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
+    const int nc = tab->n_clusters;
+    double tot = 0.0;
+    for (int p = 0; p < nc; ++p)
+        if (tab->soff[p + 1] > tab->soff[p]) tot = tab->cum[p];
+    const double target = ((double)w[1] + 0.5) * 0x1p-32 * tot;
+    int pc = 0;
+    for (int p = 0; p < nc; ++p) {
+        if (tab->soff[p + 1] == tab->soff[p]) continue;
+        pc = p;
+        if (target < tab->cum[p]) break;
+    }
+    const int cnt = tab->soff[pc + 1] - tab->soff[pc];
+    *cl = pc;
+    return surv[tab->soff[pc] + (int)(((uint64_t)w[0] * (uint64_t)cnt) >> 32)];
+}
+
 // Instantiate a call for a run-time variant (KIND_ is the compile-time value).
 #define GGNS_DISPATCH_KIND(var, CALL)                                    \
     switch (var) {                                                       \

@@ -122,6 +122,23 @@ __global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, con
         acc->steps_out = acc->steps_in = acc->prunes = acc->nosave = 0;
         acc->it_outs = acc->it_steps = 0ull;
         acc->state = GGNS_RUN_ACTIVE;
+        acc->n_clusters = R.cluster_mode ? 1 : 0;
+        if (R.cluster_mode) {
+            ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
+            for (int p = 0; p < kClMax; ++p) {
+                tab->clx[p] = (p == 0) ? 0.0 : -INFINITY;
+                tab->cn[p] = (p == 0) ? R.n_live : 0;
+                tab->cum[p] = 0.0;
+            }
+            for (int p = 0; p <= kClMax; ++p) tab->soff[p] = tab->moff[p] = 0;
+            tab->n_clusters = 1;
+            tab->n_splits = 0;
+            tab->stopping = 0;
+        }
+    }
+    if (init_state && R.cluster_mode) {
+        int32_t *label = at<int32_t>(arena, R.off_label);
+        for (int i = threadIdx.x; i < R.n_live; i += blockDim.x) label[i] = 0;
     }
 }
 
@@ -199,6 +216,16 @@ __global__ void replace_kernel(void *arena, const RunDev *__restrict__ runs) {
     const double *wl = at<double>(arena, R.off_walk_logl);
     double *ll = at<double>(arena, R.off_live_logl);
     for (int64_t m = e0; m < R.n_kill; m += stride) ll[killed[m]] = wl[m];
+    if (R.cluster_mode) {
+        // the new point joins the cluster its walker was spawned in
+        int32_t *label = at<int32_t>(arena, R.off_label);
+        const int32_t *scl = at<int32_t>(arena, R.off_start_cl);
+        ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
+        for (int64_t m = e0; m < R.n_kill; m += stride) {
+            label[killed[m]] = scl[m];
+            atomicAdd(&tab->cn[scl[m]], 1);
+        }
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long st = acc->it_steps;
         if (st > 0) {

@@ -124,8 +124,12 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     auto start_walker = [&](int mm) {
         uint32_t w[4];
         draw4(seed, 0u, (uint32_t)mm, it, TAG_START, 0u, w);
-        s = surv[(int)(((uint64_t)w[0] * (uint64_t)nsurv) >> 32)];
-        if (lead) start_arr[mm] = s;
+        int cl;
+        s = pick_start(R, arena, w, &cl);
+        if (lead) {
+            start_arr[mm] = s;
+            if (R.cluster_mode) at<int32_t>(arena, R.off_start_cl)[mm] = cl;
+        }
         const float *xs = live_x + (int64_t)s * d;
         float *wo = walk_x + (int64_t)mm * d;
 #pragma unroll

@@ -147,8 +147,10 @@ __global__ void plain_start_kernel(void *arena, const RunDev *__restrict__ runs,
     const uint32_t it = (uint32_t)acc->iter;
     uint32_t w[4];
     draw4(R.seed, 0u, (uint32_t)m, it, TAG_START, 0u, w);
-    const int s = at<int32_t>(arena, R.off_surv)[(int)(((uint64_t)w[0] * (uint64_t)nsurv) >> 32)];
+    int cl;
+    const int s = pick_start(R, arena, w, &cl);
     at<int32_t>(arena, R.off_start)[m] = s;
+    if (R.cluster_mode) at<int32_t>(arena, R.off_start_cl)[m] = cl;
     const double *xs = at<double>(arena, R.off_live_x) + (int64_t)s * d;
     double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
     for (int a = 0; a < d; ++a) S.x[a * k + m] = wo[a] = xs[a];

@@ -41,6 +41,7 @@ def make_descs(configs: Sequence[RunConfig], tile_c=None):
         D.seed = int(c.seed) & (2 ** 64 - 1)
         D.tile_c = int(tile_c[i]) if tile_c is not None else 0
         D.noise_mode = c.noise_id
+        D.cluster_mode, D.cluster_kmax = int(c.cluster), int(c.cluster_kmax)
         blocks.append(np.asarray(c.params, np.float64))
         off += len(c.params)
     return descs, blocks
@@ -245,6 +246,25 @@ class Engine:
         n_dead = min(n_dead, lay.dead_cap)
         return (self._view(lay.dead_logl, n_dead * 8, self.torch.float64, (n_dead,)),
                 self._view(lay.dead_logw, n_dead * 8, self.torch.float64, (n_dead,)))
+
+    def labels(self, r):
+        """Cluster of each live slot (cluster mode)."""
+        c, lay = self.cfgs[r], self.layouts[r]
+        if lay.label < 0:
+            raise ValueError("run is not in cluster mode")
+        return self._view(lay.label, c.n_live * 4, self.torch.int32, (c.n_live,))
+
+    def clusters(self, r) -> dict:
+        """The run's cluster table, copied to the host (cluster mode)."""
+        lay = self.layouts[r]
+        if lay.cluster_table < 0:
+            raise ValueError("run is not in cluster mode")
+        raw = self.arena[lay.cluster_table:lay.cluster_table + 1816].cpu().numpy()
+        f64, i32 = raw[:1024].view(np.float64), raw[1024:1816].view(np.int32)
+        nc = int(i32[194])
+        return {"log_xbar": f64[:64].copy(), "cdf": f64[64:128].copy(), "n_live": i32[:64].copy(),
+                "surv_off": i32[64:129].copy(), "member_off": i32[129:194].copy(),
+                "n_clusters": nc, "n_splits": int(i32[195]), "stopping": int(i32[196])}
 
     def set_trace(self, r: int, steps: int):
         """Record the first `steps` steps of every walker of run r."""

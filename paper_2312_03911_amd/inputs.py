@@ -60,7 +60,7 @@ class RunConfig:
     name: str = ""
     noise: str = "component"      # eps of p *= 1 + delta_p eps: "component" or "walker"
     cluster: int = 0              # 1: cluster recognition and volume-proportional spawning
-    cluster_kmax: int = 32        # largest neighbour count the cluster finding tries
+    cluster_kmax: int = 8         # largest neighbour count the cluster finding tries
 
     def __post_init__(self):
         self.params = np.ascontiguousarray(self.params, dtype=np.float64)

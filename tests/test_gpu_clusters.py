@@ -1,0 +1,129 @@
+"""Cluster mode on the GPU against the oracle on identical inputs: cluster
+finding, per-cluster kill weights and volumes, grouped survivors, spawning,
+and whole FP64 runs."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2312_03911_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _engine(cfgs):
+    from paper_2312_03911_amd.engine import Engine
+    return Engine(cfgs)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _blob_cfg(d, n, precision, seed):
+    return inputs.RunConfig(kind="gauss_diag", d=d, n_live=n, lo=-20.0, hi=20.0, precision=precision,
+                            params=inputs.gauss_diag_params(np.zeros(d), np.full(d, 3.0)),
+                            seed=seed, cluster=1, max_ref=0, n_steps_max=10)
+
+
+def _blobs(centres, per, d, scale, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([c + scale * rng.standard_normal((per, d)) for c in centres])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cluster_step_matches_oracle(torch, orc, precision):
+    d, per = 5, 100
+    centres = [np.full(d, -8.0), np.zeros(d), np.full(d, 8.0), np.array([8.0, -8.0, 8.0, -8.0, 8.0])]
+    X = _blobs(centres, per, d, 0.6, seed=3)
+    cfg = _blob_cfg(d, 4 * per, precision, seed=31)
+    eng = _engine([cfg])
+    xd = torch.from_numpy(X).to(eng.device, eng._fdtype(0))
+    eng.live_x(0).copy_(xd)
+    l, _ = eng.loglike(0, eng.live_x(0).clone(), grad=False)
+    eng.live_logl(0).copy_(l)
+    o = orc.Oracle(cfg).init()
+    o.set_state(live_x=_np(xd).astype(np.float64), live_logl=_np(l))
+    eng.evidence_update()
+    o.evidence_update()
+    torch.cuda.synchronize()
+    tab = eng.clusters(0)
+    assert tab["n_clusters"] == o.st.n_clusters == 4 and tab["n_splits"] == o.st.n_splits == 1
+    np.testing.assert_array_equal(_np(eng.labels(0)), o.label)
+    nc = o.st.n_clusters
+    np.testing.assert_array_equal(tab["n_live"][:nc], o.cn[:nc])
+    np.testing.assert_allclose(tab["log_xbar"][:nc], o.clx[:nc], rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
+    np.testing.assert_array_equal(_np(eng.survivors(0)), o.surv[:cfg.n_live - cfg.n_kill])
+    np.testing.assert_array_equal(tab["surv_off"][:nc + 1], o.surv_off[:nc + 1])
+    dl, dw = eng.dead(0)
+    np.testing.assert_array_equal(_np(dl), o.dead_logl[:o.n_dead])
+    np.testing.assert_allclose(_np(dw), o.dead_logw[:o.n_dead], rtol=0, atol=1e-12)
+    st = eng.stats()[0]
+    assert abs(st["log_z"] - o.st.lz) < 1e-12 and abs(st["log_x"] - o.st.lx) < 1e-12
+    assert st["n_clusters"] == 4
+    # spawning: the same clusters and starts for every walker
+    eng.hss_walk()
+    o.hss_walk()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.start(0)), o.start)
+    eng.replace_dead()
+    o.replace_dead()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.labels(0)), o.label)
+    np.testing.assert_array_equal(eng.clusters(0)["n_live"][:nc], o.cn[:nc])
+
+
+def test_one_blob_stays_one_cluster(torch):
+    d, n = 6, 300
+    cfg = _blob_cfg(d, n, "fp64", seed=32)
+    eng = _engine([cfg])
+    X = inputs.ball_points(n, d, np.zeros(d), 3.0, seed=4)
+    eng.live_x(0).copy_(torch.from_numpy(X).to(eng.device))
+    l, _ = eng.loglike(0, eng.live_x(0).clone(), grad=False)
+    eng.live_logl(0).copy_(l)
+    eng.evidence_update()
+    torch.cuda.synchronize()
+    assert eng.clusters(0)["n_clusters"] == 1
+
+
+@pytest.mark.parametrize("seed", [900, 901])
+def test_cluster_mode_fp64_full_run_matches_oracle(torch, orc, seed):
+    d = 4
+    prm = inputs.gmm_params(np.array([np.full(d, -4.0), np.full(d, 4.0)]), np.full((2, d), 0.5))
+    cfg = inputs.RunConfig(kind="gmm_diag", d=d, n_live=200, n_comp=2, params=prm, lo=-8.0, hi=8.0,
+                           seed=seed, precision="fp64", cluster=1, noise="walker", max_ref=0,
+                           n_steps_max=40)
+    eng = _engine([cfg])
+    st = eng.run(poll_every=4)[0]
+    o = orc.Oracle(cfg).run()
+    assert st["state"] == o.st.state == 1
+    assert st["iter"] == o.st.iter and st["n_clusters"] == o.st.n_clusters >= 2
+    assert abs(st["log_z"] - o.st.lz) < 1e-9
+    assert abs(st["sigma_kl"] - o.st.sigma_kl) < 1e-9
+
+
+def test_cluster_mode_runs_batched_with_plain_runs(torch):
+    """A cluster-mode run and ordinary runs in one batch: each equals itself
+    run alone."""
+    d = 4
+    prm = inputs.gmm_params(np.array([np.full(d, -4.0), np.full(d, 4.0)]), np.full((2, d), 0.5))
+    ccfg = inputs.RunConfig(kind="gmm_diag", d=d, n_live=200, n_comp=2, params=prm, lo=-8.0,
+                            hi=8.0, seed=950, precision="fp32", cluster=1)
+    cfgs = [inputs.config_shells(d=8, n_live=200, seed=951), ccfg]
+    both = _engine(cfgs)
+    both.iterate(12)
+    alone = _engine([ccfg])
+    alone.iterate(12)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(both.live_x(1)), _np(alone.live_x(0)))
+    np.testing.assert_array_equal(_np(both.labels(1)), _np(alone.labels(0)))
+    assert both.stats()[1] == alone.stats()[0]
