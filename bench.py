@@ -60,6 +60,11 @@ def workload(name: str):
         return inputs.replicate(inputs.config_gauss2d(), 10, base_seed=2100)
     if name == "gmm64":
         return [inputs.config_gmm()]
+    if name == "gmm64_clusters":
+        # the same mixture with cluster recognition and volume-proportional spawning
+        return [inputs.config_gmm(cluster=1)]
+    if name == "gmm64_clusters_x10":
+        return inputs.replicate(inputs.config_gmm(cluster=1), 10, base_seed=2400)
     if name == "corr256":
         return [inputs.config_corr_gauss()]
     if name == "batch64":

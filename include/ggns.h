@@ -121,7 +121,7 @@ typedef struct {
                                 prior volumes (Section 3, mode collapse mitigation; Algorithm GGNS
                                 with its cluster-finding algorithm; Eqs. update0, update2, new0);
                                 0: one cluster.  sigma_mom is not computed in cluster mode. */
-    int32_t cluster_kmax;    /* largest neighbour count the cluster finding tries, 2..16 */
+    int32_t cluster_kmax;    /* largest neighbour count the cluster finding tries, 2..8 */
 } ggns_run_desc;
 
 /* Byte offsets (from the arena base) of one run's arrays. */

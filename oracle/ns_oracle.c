@@ -319,7 +319,8 @@ typedef struct {
     uint64_t seed;
     int32_t noise_mode;         /* R7: 0 per component, 1 one normal per walker */
     int32_t cluster_mode;       /* C1-C10: 0 one cluster, 1 cluster recognition and spawning */
-    int32_t cluster_kmax, pad_; /* C2: largest neighbour count tried */
+    int32_t cluster_kmax;       /* C2: largest neighbour count tried */
+    int32_t knn_fp32;           /* C2: neighbour distances in FP32 (the engine's precision) */
 } orc_desc;
 
 enum { ST_ACTIVE = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3 };
@@ -478,7 +479,9 @@ static void final_sweep(const orc_desc *D, orc_state *S)
  *       once for each existing cluster (clusters created in this iteration
  *       are not re-examined in it);
  *   C2  for k = 2, 3, ...: link every point of the cluster to its k nearest
- *       other points of the cluster (squared Euclidean distance, ties by slot),
+ *       other points of the cluster (squared Euclidean distance summed over
+ *       coordinates in order with fused multiply-adds, in the engine's
+ *       precision: FP64 for FP64 runs, FP32 otherwise; ties by slot),
  *       take the connected components of the undirected graph and their
  *       sizes; stop at the first k whose sorted sizes equal those of k - 1 and
  *       use that k's components.  k runs up to min(cluster_kmax, m - 1) for m
@@ -500,12 +503,26 @@ static void final_sweep(const orc_desc *D, orc_state *S)
  * ------------------------------------------------------------------------ */
 #define ORC_CL_MAX 64
 
+/* Squared distance summed over coordinates in order with fused multiply-adds
+ * (s <- fma(t, t, s), correctly rounded), in the precision the engine ranks
+ * neighbours in (the ranks are integer decisions): FP64 for FP64 runs, FP32
+ * otherwise. */
+static int g_knn_fp32 = 0;
+
 static double dist2(const double *a, const double *b, int d)
 {
+    if (g_knn_fp32) {
+        float s = 0.0f;
+        for (int i = 0; i < d; ++i) {
+            float t = (float)a[i] - (float)b[i];
+            s = fmaf(t, t, s);
+        }
+        return (double)s;
+    }
     double s = 0.0;
     for (int i = 0; i < d; ++i) {
         double t = a[i] - b[i];
-        s = s + t * t;
+        s = fma(t, t, s);
     }
     return s;
 }
@@ -591,6 +608,7 @@ static void find_clusters(const orc_desc *D, orc_state *S)
         int K = D->cluster_kmax < m - 1 ? D->cluster_kmax : m - 1;
         if (K < 2) continue;
         int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * K);
+        g_knn_fp32 = D->knn_fp32;
         knn_lists(S->live_x, d, idx, m, K, nb);
         int nprev = -1, found = 0, nc = 0;
         for (int k = 2; k <= K; ++k) {

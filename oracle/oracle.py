@@ -44,7 +44,7 @@ class _Desc(C.Structure):
                 ("term_kind", C.c_int32), ("max_iter", C.c_int32),
                 ("term_tol", C.c_double), ("seed", C.c_uint64),
                 ("noise_mode", C.c_int32), ("cluster_mode", C.c_int32),
-                ("cluster_kmax", C.c_int32), ("pad", C.c_int32)]
+                ("cluster_kmax", C.c_int32), ("knn_fp32", C.c_int32)]
 
 
 _PD = C.POINTER(C.c_double)
@@ -189,7 +189,8 @@ class Oracle:
                           max_iter=cfg.max_iter, term_tol=cfg.term_tol,
                           seed=C.c_uint64(int(cfg.seed) & (2**64 - 1)),
                           noise_mode=cfg.noise_id, cluster_mode=int(cfg.cluster),
-                          cluster_kmax=int(cfg.cluster_kmax))
+                          cluster_kmax=int(cfg.cluster_kmax),
+                          knn_fp32=int(cfg.precision != "fp64"))
         self.params = np.ascontiguousarray(cfg.params, dtype=np.float64)
         cap = k * cfg.max_iter + n
         self.live_x = np.zeros((n, d))

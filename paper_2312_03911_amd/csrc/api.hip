@@ -140,8 +140,11 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
             R.off_members = off; off = align_up(off + (int64_t)D.n_live * 4);
             R.off_knn = off; off = align_up(off + (int64_t)D.n_live * kKnnMax * 4);
             R.off_start_cl = off; off = align_up(off + (int64_t)D.n_kill * 4);
+            R.off_knn_part = off; off = align_up(off + (int64_t)D.n_live * kKnnSplit * kKnnMax * 8);
+            R.off_knn_part_s = off; off = align_up(off + (int64_t)D.n_live * kKnnSplit * kKnnMax * 4);
         } else {
             R.off_label = R.off_cltab = R.off_members = R.off_knn = R.off_start_cl = -1;
+            R.off_knn_part = R.off_knn_part_s = -1;
         }
     }
     P.total = off;

@@ -25,7 +25,8 @@ namespace {
 
 constexpr int kClThreads = 1024;
 
-__device__ __forceinline__ bool lex_less(double a, int sa, double b, int sb) {
+template <typename T>
+__device__ __forceinline__ bool lex_less(T a, int sa, T b, int sb) {
     return a < b || (a == b && sa < sb);
 }
 
@@ -87,78 +88,168 @@ cluster_pre_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep
     }
 }
 
-// One wavefront per live point: its kKnnMax nearest other points of its cluster.
-template <typename T>
-__global__ void __launch_bounds__(256)
-knn_kernel(void *arena, const RunDev *__restrict__ runs) {
+// Nearest neighbours within clusters, in two launches.  knn_part: a
+// workgroup of 4 wavefronts takes 64 consecutive entries of the cluster-grouped
+// member list as queries (one per lane) and one of kKnnSplit shares of the
+// candidate range of their clusters, split again between its wavefronts; a
+// candidate is the same for every lane of a wavefront, so its coordinates
+// arrive through scalar loads; each lane keeps the KN best of its share
+// (squared distance accumulated with fused multiply-adds in coordinate order,
+// in the run's precision; ties by slot); the wavefronts' lists merge in LDS
+// and go to a partial-list buffer.  knn_merge: one thread per query merges its
+// kKnnSplit partial lists into its neighbour list.
+constexpr int kKnnWaves = 4;
+
+template <typename T, int KN>
+__global__ void __launch_bounds__(64 * kKnnWaves)
+knn_part_kernel(void *arena, const RunDev *__restrict__ runs) {
     const RunDev &R = runs[blockIdx.y];
     if (!R.cluster_mode || (R.prec == GGNS_FP64) != (sizeof(T) == 8)) return;
     const Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
     const ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
     if (tab->stopping) return;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (i >= R.n_live) return;
+    const int n = R.n_live;
+    const int qb = blockIdx.x / kKnnSplit, split = blockIdx.x % kKnnSplit;
+    const int q0 = qb * 64;
+    if (q0 >= n) return;
+    __shared__ T lst_d[kKnnWaves][KN][64];
+    __shared__ int lst_s[kKnnWaves][KN][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t *label = at<int32_t>(arena, R.off_label);
-    const int c = label[i];
-    const int m0 = tab->moff[c], m = tab->moff[c + 1] - m0;
-    if (m < 3) return;
-    const int keff = (R.cluster_kmax < m - 1) ? R.cluster_kmax : m - 1;
-    const int d = R.d;
-    const T *X = at<T>(arena, R.off_live_x);
-    const T *xi = X + (int64_t)i * d;
     const int32_t *members = at<int32_t>(arena, R.off_members);
-    double bd[kKnnMax];
-    int bs[kKnnMax];
+    const int qn = (n - q0 < 64) ? n - q0 : 64;
+    const bool qvalid = lane < qn;
+    const int qi = members[q0 + (qvalid ? lane : 0)];
+    const int qc = label[qi];
+    // candidate range: the clusters of the first and the last query; this
+    // block's share of it, and this wavefront's share of that
+    const int c_lo = label[members[q0]], c_hi = label[members[q0 + qn - 1]];
+    const int lo = tab->moff[c_lo], hi = tab->moff[c_hi + 1];
+    const int parts = kKnnSplit * kKnnWaves, part = split * kKnnWaves + wave;
+    const int per = (hi - lo + parts - 1) / parts;
+    const int u0 = lo + part * per, u1 = (u0 + per < hi) ? u0 + per : hi;
+    const int d = R.d;
+    const T *__restrict__ X = at<T>(arena, R.off_live_x);
+    const T *xq = X + (int64_t)qi * d;
+    T bd[KN];
+    int bs[KN];
 #pragma unroll
-    for (int q = 0; q < kKnnMax; ++q) { bd[q] = INFINITY; bs[q] = 0x7FFFFFFF; }
-    for (int u = lane; u < m; u += 64) {
-        const int j = members[m0 + u];
-        if (j == i) continue;
-        const T *xj = X + (int64_t)j * d;
-        double s = 0.0;
-        {
-#pragma clang fp contract(off)
-            for (int a = 0; a < d; ++a) {
-                const double e = (double)xi[a] - (double)xj[a];
-                s = s + e * e;
+    for (int q = 0; q < KN; ++q) { bd[q] = (T)INFINITY; bs[q] = 0x7FFFFFFF; }
+    constexpr int TILE = 8, CHUNK = (sizeof(T) == 8) ? 16 : 32;
+    for (int ub = u0; ub < u1; ub += TILE) {
+        int cj[TILE];
+        T acc2[TILE];
+#pragma unroll
+        for (int t = 0; t < TILE; ++t) {
+            // the same candidate for every lane: make that explicit so that its
+            // coordinates come through scalar loads
+            cj[t] = __builtin_amdgcn_readfirstlane((ub + t < u1) ? members[ub + t] : -1);
+            acc2[t] = (T)0;
+        }
+        for (int c0 = 0; c0 < d; c0 += CHUNK) {
+            const int cn = (d - c0 < CHUNK) ? d - c0 : CHUNK;
+            T qv[CHUNK];
+#pragma unroll
+            for (int a = 0; a < CHUNK; ++a) qv[a] = (a < cn) ? xq[c0 + a] : (T)0;
+#pragma unroll
+            for (int t = 0; t < TILE; ++t) {
+                if (cj[t] < 0) continue;
+                const T *xc = X + (int64_t)cj[t] * d + c0;
+#pragma unroll
+                for (int a = 0; a < CHUNK; ++a) {
+                    if (a < cn) {
+                        const T e = qv[a] - xc[a];
+                        acc2[t] = fma(e, e, acc2[t]);
+                    }
+                }
             }
         }
-        if (lex_less(s, j, bd[kKnnMax - 1], bs[kKnnMax - 1])) {
-            bd[kKnnMax - 1] = s;
-            bs[kKnnMax - 1] = j;
 #pragma unroll
-            for (int q = kKnnMax - 1; q > 0; --q) {
-                const bool sw = lex_less(bd[q], bs[q], bd[q - 1], bs[q - 1]);
-                const double td = bd[q];
-                const int ts = bs[q];
-                bd[q] = sw ? bd[q - 1] : bd[q];
-                bs[q] = sw ? bs[q - 1] : bs[q];
-                bd[q - 1] = sw ? td : bd[q - 1];
-                bs[q - 1] = sw ? ts : bs[q - 1];
+        for (int t = 0; t < TILE; ++t) {
+            const int j = cj[t];
+            if (j < 0) continue;
+            const bool ok = qvalid && label[j] == qc && j != qi &&
+                            lex_less(acc2[t], j, bd[KN - 1], bs[KN - 1]);
+            if (ok) {
+                bd[KN - 1] = acc2[t];
+                bs[KN - 1] = j;
+#pragma unroll
+                for (int q = KN - 1; q > 0; --q) {
+                    const bool sw = lex_less(bd[q], bs[q], bd[q - 1], bs[q - 1]);
+                    const T td = bd[q];
+                    const int ts = bs[q];
+                    bd[q] = sw ? bd[q - 1] : bd[q];
+                    bs[q] = sw ? bs[q - 1] : bs[q];
+                    bd[q - 1] = sw ? td : bd[q - 1];
+                    bs[q - 1] = sw ? ts : bs[q - 1];
+                }
             }
         }
     }
-    // merge the 64 lane lists: keff rounds of a wavefront arg-min of the heads
-    int32_t *knn = at<int32_t>(arena, R.off_knn) + (int64_t)i * kKnnMax;
+#pragma unroll
+    for (int q = 0; q < KN; ++q) {
+        lst_d[wave][q][lane] = bd[q];
+        lst_s[wave][q][lane] = bs[q];
+    }
+    __syncthreads();
+    if (wave == 0 && qvalid) {
+        int head[kKnnWaves];
+#pragma unroll
+        for (int w = 0; w < kKnnWaves; ++w) head[w] = 0;
+        double *pd = at<double>(arena, R.off_knn_part) + ((int64_t)(q0 + lane) * kKnnSplit + split) * KN;
+        int32_t *ps = at<int32_t>(arena, R.off_knn_part_s) + ((int64_t)(q0 + lane) * kKnnSplit + split) * KN;
+        for (int r = 0; r < KN; ++r) {
+            int bw = 0;
+            T dmin = (T)INFINITY;
+            int smin = 0x7FFFFFFF;
+#pragma unroll
+            for (int w = 0; w < kKnnWaves; ++w) {
+                if (head[w] >= KN) continue;
+                const T dv = lst_d[w][head[w]][lane];
+                const int sv = lst_s[w][head[w]][lane];
+                if (lex_less(dv, sv, dmin, smin)) { dmin = dv; smin = sv; bw = w; }
+            }
+            pd[r] = (double)dmin;
+            ps[r] = smin;
+            head[bw] += 1;
+        }
+    }
+}
+
+__global__ void knn_merge_kernel(void *arena, const RunDev *__restrict__ runs) {
+    const RunDev &R = runs[blockIdx.y];
+    if (!R.cluster_mode) return;
+    const Acc *acc = at<Acc>(arena, R.off_acc);
+    if (acc->state != GGNS_RUN_ACTIVE) return;
+    const ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
+    if (tab->stopping) return;
+    const int qpos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qpos >= R.n_live) return;
+    const int qi = at<int32_t>(arena, R.off_members)[qpos];
+    const int qc = at<int32_t>(arena, R.off_label)[qi];
+    const int m = tab->moff[qc + 1] - tab->moff[qc];
+    if (m < 3) return;
+    const int keff = (R.cluster_kmax < m - 1) ? R.cluster_kmax : m - 1;
+    const double *pd = at<double>(arena, R.off_knn_part) + (int64_t)qpos * kKnnSplit * kKnnMax;
+    const int32_t *ps = at<int32_t>(arena, R.off_knn_part_s) + (int64_t)qpos * kKnnSplit * kKnnMax;
+    int head[kKnnSplit];
+#pragma unroll
+    for (int w = 0; w < kKnnSplit; ++w) head[w] = 0;
+    int32_t *knn = at<int32_t>(arena, R.off_knn) + (int64_t)qi * kKnnMax;
     for (int r = 0; r < keff; ++r) {
-        double hd = bd[0];
-        int hs = bs[0];
+        int bw = 0;
+        double dmin = INFINITY;
+        int smin = 0x7FFFFFFF;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double od = __shfl_xor(hd, o, 64);
-            const int os = __shfl_xor(hs, o, 64);
-            const bool take = lex_less(od, os, hd, hs);
-            hd = take ? od : hd;
-            hs = take ? os : hs;
+        for (int w = 0; w < kKnnSplit; ++w) {
+            if (head[w] >= kKnnMax) continue;
+            const double dv = pd[w * kKnnMax + head[w]];
+            const int sv = ps[w * kKnnMax + head[w]];
+            if (lex_less(dv, sv, dmin, smin)) { dmin = dv; smin = sv; bw = w; }
         }
-        if (lane == 0) knn[r] = hs;
-        if (bs[0] == hs) {
-#pragma unroll
-            for (int q = 0; q < kKnnMax - 1; ++q) { bd[q] = bd[q + 1]; bs[q] = bs[q + 1]; }
-            bd[kKnnMax - 1] = INFINITY;
-            bs[kKnnMax - 1] = 0x7FFFFFFF;
-        }
+        knn[r] = smin;
+        head[bw] += 1;
     }
 }
 
@@ -187,8 +278,12 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
     __shared__ int nroot[kClMax], roots[kClMax][kClMax], newid_base[kClMax];
     __shared__ int ccount[kClMax];
     __shared__ int changed;
+    __shared__ int label[kMaxLive];
+    __shared__ uint32_t rkey[kMaxLive];
+    __shared__ int fpos[kClMax];
     const int n = R.n_live, t = threadIdx.x, T = blockDim.x;
-    int32_t *label = at<int32_t>(arena, R.off_label);
+    int32_t *label_g = at<int32_t>(arena, R.off_label);
+    for (int i = t; i < n; i += T) label[i] = label_g[i];
     const int32_t *knn = at<int32_t>(arena, R.off_knn);
     const int nc0 = tab->n_clusters;
     for (int p = t; p < kClMax; p += T) {
@@ -229,22 +324,57 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
             if (keff[p] && !stopped[p] && k <= keff[p] && par[i] == i) atomicAdd(&cnt_cur[p], 1);
         }
         __syncthreads();
+        if (t == 0) changed = 0;
+        __syncthreads();
         for (int p = t; p < kClMax; p += T) {
             if (!keff[p] || stopped[p] || k > keff[p]) continue;
             if (k >= 3 && cnt_cur[p] == cnt_prev[p]) stopped[p] = k;
             cnt_prev[p] = cnt_cur[p];
+            if (!stopped[p] && k < keff[p]) changed = 1;   // some cluster still grows its graph
         }
         __syncthreads();
+        if (!changed) break;
     }
-    // roots of the stopped clusters in ascending slot order
-    if (t == 0) {
-        for (int i = 0; i < n; ++i) {
-            const int p = label[i];
-            if (stopped[p] && par[i] == i) {
-                if (nroot[p] < kClMax) roots[p][nroot[p]] = i;
-                nroot[p] += 1;
+    // roots of the stopped clusters in ascending slot order: a sort of
+    // (cluster << 12 | slot) keys of the roots, then per-cluster runs
+    {
+        int NP = 1;
+        while (NP < n) NP <<= 1;
+        for (int i = t; i < NP; i += T)
+            rkey[i] = (i < n && stopped[label[i]] && par[i] == i)
+                          ? ((uint32_t)label[i] << 12) | (uint32_t)i : 0xFFFFFFFFu;
+        for (int size = 2; size <= NP; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                __syncthreads();
+                for (int i = t; i < (NP >> 1); i += T) {
+                    const int lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                    const bool asc = (lo & size) == 0;
+                    const uint32_t a = rkey[lo], b = rkey[hi];
+                    if ((a > b) == asc) { rkey[lo] = b; rkey[hi] = a; }
+                }
             }
         }
+        __syncthreads();
+        for (int j = t; j < n; j += T) {
+            const uint32_t kj = rkey[j];
+            if (kj == 0xFFFFFFFFu) continue;
+            const int p = (int)(kj >> 12);
+            if (j == 0 || (int)(rkey[j - 1] >> 12) != p) fpos[p] = j;
+            if (j + 1 == NP || (int)(rkey[j + 1] >> 12) != p) nroot[p] = j + 1;   // end, for now
+        }
+        __syncthreads();
+        for (int j = t; j < n; j += T) {
+            const uint32_t kj = rkey[j];
+            if (kj == 0xFFFFFFFFu) continue;
+            const int p = (int)(kj >> 12), r = j - fpos[p];
+            if (r < kClMax) roots[p][r] = (int)(kj & 0xFFFu);
+        }
+        __syncthreads();
+        for (int p = t; p < kClMax; p += T)
+            if (nroot[p] > 0) nroot[p] -= fpos[p];
+        __syncthreads();
+    }
+    if (t == 0) {
         int ncl = nc0, splits = tab->n_splits;
         for (int p = 0; p < nc0; ++p) {
             newid_base[p] = -1;
@@ -267,7 +397,7 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
         int rank = 0;
         while (rank < kClMax - 1 && roots[p][rank] != r) ++rank;
         const int q = (rank == 0) ? p : newid_base[p] + rank - 1;
-        label[i] = q;
+        label_g[i] = q;
         atomicAdd(&ccount[q], 1);
     }
     __syncthreads();
@@ -289,11 +419,15 @@ int launch_clusters(void *arena, const RunDev *runs_dev, int n_runs, int max_liv
                     bool any_fp64, bool any_fp32, hipStream_t s) {
     hipLaunchKernelGGL(cluster_pre_kernel, dim3(n_runs), dim3(kClThreads), 0, s, arena, runs_dev,
                        final_sweep);
-    const dim3 grid((max_live + 3) / 4, n_runs);
+    const dim3 grid((max_live + 63) / 64 * kKnnSplit, n_runs);
     if (any_fp64)
-        hipLaunchKernelGGL(knn_kernel<double>, grid, dim3(256), 0, s, arena, runs_dev);
+        hipLaunchKernelGGL((knn_part_kernel<double, kKnnMax>), grid, dim3(64 * kKnnWaves), 0, s,
+                           arena, runs_dev);
     if (any_fp32)
-        hipLaunchKernelGGL(knn_kernel<float>, grid, dim3(256), 0, s, arena, runs_dev);
+        hipLaunchKernelGGL((knn_part_kernel<float, kKnnMax>), grid, dim3(64 * kKnnWaves), 0, s,
+                           arena, runs_dev);
+    hipLaunchKernelGGL(knn_merge_kernel, dim3((max_live + 255) / 256, n_runs), dim3(256), 0, s,
+                       arena, runs_dev);
     hipLaunchKernelGGL(cluster_cc_kernel, dim3(n_runs), dim3(kClThreads), 0, s, arena, runs_dev);
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }

@@ -46,10 +46,12 @@ struct RunDev {
     // live slots grouped by cluster, k-nearest-neighbour lists, walker clusters
     int32_t cluster_mode, cluster_kmax;
     int64_t off_label, off_cltab, off_members, off_knn, off_start_cl;
+    int64_t off_knn_part, off_knn_part_s;   // per query and share: partial neighbour lists
 };
 
 constexpr int kClMax = 64;      // clusters per run
-constexpr int kKnnMax = 16;     // neighbours kept per point
+constexpr int kKnnMax = 8;      // neighbours kept per point (largest cluster_kmax)
+constexpr int kKnnSplit = 16;   // shares of the candidate range searched in parallel
 
 // Per-run cluster table (arena).
 struct ClusterTab {
