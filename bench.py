@@ -69,6 +69,22 @@ def workload(name: str):
         return [inputs.config_corr_gauss()]
     if name == "batch64":
         return inputs.config_batch()
+    if name in ("gauss_sweep", "gauss_sweep_dead", "gauss_sweep_classic"):
+        # the dimension sweep of the paper's comparison (diagonal Gaussian,
+        # n_live = 200 at every d, 10 runs each): the d=2 Gaussian's family,
+        # mean 0.5 and width 0.05 per axis in the unit box, FP32 walks with the
+        # paper's default walk settings; termination at tol 0.01 by the X L peak
+        # with L the largest live likelihood, or with L the dead point's, or by
+        # the remaining evidence
+        term = {"gauss_sweep": 1, "gauss_sweep_dead": 2, "gauss_sweep_classic": 0}[name]
+        out = []
+        for d in (2, 4, 8, 16, 32, 64, 128):
+            base = inputs.RunConfig(kind="gauss_diag", d=d, n_live=200, lo=0.0, hi=1.0,
+                                    params=inputs.gauss_diag_params(np.full(d, 0.5), np.full(d, 0.05)),
+                                    precision="fp32", term_kind=term, term_tol=0.01,
+                                    n_steps_max=max(64, 5 * d), name=f"gauss_d{d}")
+            out += inputs.replicate(base, 10, base_seed=8000 + 100 * d)
+        return out
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -181,6 +197,22 @@ def plain_baseline(cfgs, fused_value: float, fused_ms_per_run: float, fused_stat
             "logz_minus_closed_form_mean": float(np.mean(dz)),
             "logz_minus_fused_mean": float(np.mean(dfz)),
             "logz_minus_fused_sd": float(np.std(dfz))}
+
+
+def sweep_report(cfgs, stats, truth) -> dict:
+    """Mean evaluations, log Z error and sigma_KL of the runs of each dimension,
+    and the log-log slope of evaluations against d."""
+    by_d = {}
+    for c, st_, t in zip(cfgs, stats, truth):
+        by_d.setdefault(c.d, []).append((st_["evals"], st_["log_z"] - t, st_["sigma_kl"]))
+    ds = sorted(by_d)
+    col = lambda j, f: [float(f([v[j] for v in by_d[d]])) for d in ds]  # noqa: E731
+    ev = col(0, np.mean)
+    return {"d": ds, "evals_mean": ev,
+            "logz_minus_closed_form_mean": col(1, np.mean),
+            "logz_minus_closed_form_sd": col(1, np.std),
+            "sigma_kl_mean": col(2, np.mean),
+            "loglog_slope_evals_vs_d": float(np.polyfit(np.log(ds), np.log(ev), 1)[0])}
 
 
 def main():
@@ -347,6 +379,9 @@ def main():
                      "sigma_kl_mean": float(np.mean([s["sigma_kl"] for s in stats])),
                      "sigma_mom_mean": float(np.mean([s["sigma_mom"] for s in stats]))},
     }
+    # evaluations and log Z error against dimension (the sweep workloads)
+    if args.workload.startswith("gauss_sweep"):
+        res["dimension_sweep"] = sweep_report(cfgs, stats, truth)
     # mode recovery of the mixture runs (one untimed pass with the dead points'
     # positions kept)
     if not args.no_alt and any(c.kind == "gmm_diag" for c in cfgs):
@@ -378,6 +413,8 @@ def main():
         st_alt = alt.run(poll_every=args.poll)
         alt.close()
         dza = [s_["log_z"] - t for s_, t in zip(st_alt, truth)]
+        if args.workload.startswith("gauss_sweep"):
+            res["dimension_sweep_walker_noise"] = sweep_report(cfgs, st_alt, truth)
         res["accuracy_walker_noise"] = {
             "noise": "one normal per walker and step",
             "logz_minus_closed_form_mean": float(np.mean(dza)),

@@ -81,8 +81,20 @@ enum {
 };
 
 /* Termination (paper: Appendix A loop test and the X*L peak criterion of
- * Section 3 / Appendix I). */
-enum { GGNS_TERM_REMAINING_Z = 0, GGNS_TERM_XL_PEAK = 1 };
+ * Section 3 / Appendix I).  All three are tested at the head of an iteration,
+ * with Xbar the expected prior volume left; the peak tests are skipped at the
+ * first iteration.
+ *   REMAINING_Z:   Xbar * max live L < tol * Zbar.
+ *   XL_PEAK:       Xbar * max live L below tol times its running maximum
+ *                  (L as in the loop end of Algorithm GGNS).
+ *   XL_PEAK_DEAD:  the same test with L the likelihood of the highest point
+ *                  killed in the previous iteration, i.e. L_i X_i of the
+ *                  current dead point (the tol entry of the Appendix C table).
+ *                  A lucky live point far above the rest can hold the largest
+ *                  live L high for several iterations, long enough for
+ *                  XL_PEAK to fire before the bulk of the evidence; the dead
+ *                  point's L is a quantile of the live set and does not jump. */
+enum { GGNS_TERM_REMAINING_Z = 0, GGNS_TERM_XL_PEAK = 1, GGNS_TERM_XL_PEAK_DEAD = 2 };
 
 /* One run.  Defaults from the paper: min_ref 1, max_ref 3, delta_p 0.05
  * (Appendix C table), dt_init 0.1 (Appendix G), out_frac band 0.05 / 0.15 with

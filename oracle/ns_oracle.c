@@ -59,7 +59,11 @@
  *   R16 batch kill with n_p = n, n-1, ..., n-k+1 (the Xbar convention).
  *   R17 final sweep with n_p = n, ..., 1.
  *   R18 termination: remaining-evidence test Xbar * max L < tol * Zbar, or the
- *       X*L peak test of the paper (skipped at the first iteration).
+ *       X*L peak test of the paper (skipped at the first iteration) in one of
+ *       its two forms: L the largest live likelihood (Algorithm GGNS, loop
+ *       end), or L the likelihood of the current dead point, read as the
+ *       highest point killed in the previous iteration, with the volume left
+ *       after that kill (the tol entry of the Appendix C table).
  *   R19 sigma_mom^2 = log Z2bar - 2 log Zbar from the moment recursion, every
  *       right-hand side using pre-update values and X2bar initialised to 1.
  *   R22 random streams: Philox4x32-10 (counter based) for prior draws, start
@@ -685,7 +689,7 @@ int orc_evidence_update(const orc_desc *D, orc_state *S, int force_final)
     if (D->term_kind == 0) {
         if (S->lx + lmax < log(D->term_tol) + S->lz) stop = 1;
     } else {
-        double r = S->lx + lmax;
+        double r = S->lx + (D->term_kind == 1 ? lmax : S->lstar);
         if (r > S->lxl_max) S->lxl_max = r;
         if (S->iter > 0 && r - S->lxl_max < log(D->term_tol)) stop = 1;
     }

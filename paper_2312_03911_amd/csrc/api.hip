@@ -35,6 +35,7 @@ bool valid_desc(const ggns_run_desc &r) {
     if (!(r.prior_hi > r.prior_lo)) return false;
     if (!(r.dt_init > 0.0)) return false;
     if (r.n_steps_max < 1 || r.min_ref < 0 || r.max_ref < 0 || r.prune_streak < 0) return false;
+    if (r.term_kind < GGNS_TERM_REMAINING_Z || r.term_kind > GGNS_TERM_XL_PEAK_DEAD) return false;
     if (!(r.term_tol > 0.0) || r.max_iter < 0) return false;
     if (r.param_offset < 0) return false;
     if (r.tile_c < 0 || r.tile_c > 16) return false;

@@ -530,7 +530,7 @@ __device__ inline int termination_decision(const RunDev &R, const Acc *acc, doub
     if (R.term_kind == GGNS_TERM_REMAINING_Z) {
         if (acc->log_x + lmax < ltol + acc->log_z) stop = GGNS_RUN_DONE;
     } else {
-        const double r = acc->log_x + lmax;
+        const double r = acc->log_x + (R.term_kind == GGNS_TERM_XL_PEAK ? lmax : acc->lstar);
         const double xl = r > acc->log_xl_max ? r : acc->log_xl_max;
         if (xl_max) *xl_max = xl;
         if (acc->iter > 0 && r - xl < ltol) stop = GGNS_RUN_DONE;

@@ -53,7 +53,7 @@ class RunConfig:
     out_lo: float = 0.05
     dt_down: float = 0.9
     dt_up: float = 1.1
-    term_kind: int = 0            # 0: remaining evidence fraction, 1: X*L peak
+    term_kind: int = 0            # 0: remaining evidence fraction, 1: X*L_max peak, 2: X*L_dead peak
     term_tol: float = 1e-3
     max_iter: int = 0             # 0 -> a generous bound from d, width and n_live
     seed: int = 0

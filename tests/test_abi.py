@@ -52,7 +52,8 @@ def test_arena_size_and_validation():
     assert nb >= need and nb % 256 == 0
     bad = [dict(d=0), dict(d=257), dict(n_live=1), dict(n_kill=0), dict(n_kill=100),
            dict(lik_kind=7), dict(prior_hi=-1.0), dict(n_steps_max=0), dict(tile_c=17),
-           dict(tile_c=-1), dict(precision=2)]  # BF16 only for the correlated Gaussian
+           dict(tile_c=-1), dict(term_kind=3), dict(term_kind=-1),
+           dict(precision=2)]  # BF16 only for the correlated Gaussian
     for kw in bad:
         one = (_lib.ggns_run_desc * 1)(_desc(cfgs[0], **kw))
         assert L.ggns_arena_bytes(one, 1) == _lib.GGNS_EINVAL, kw

@@ -211,10 +211,14 @@ def test_loglike_and_adjoint_match_oracle(torch, orc, name, make, tol, tau):
     assert l0.numel() == 0
 
 
-def test_gauss2d_fp64_full_run_matches_oracle(torch, orc):
-    """The whole FP64 run (init, iterations, final sweep) reproduces the oracle."""
-    for seed in (2100, 2101, 2102):
-        cfg = inputs.config_gauss2d(seed=seed)
+@pytest.mark.parametrize("term_kind", [0, 1, 2])
+def test_gauss2d_fp64_full_run_matches_oracle(torch, orc, term_kind):
+    """The whole FP64 run (init, iterations, final sweep) reproduces the oracle,
+    under each termination test (remaining evidence at 1e-3, the two X*L peak
+    forms at 0.01)."""
+    tol = 1e-3 if term_kind == 0 else 0.01
+    for seed in ((2100, 2101, 2102) if term_kind == 0 else (2103, 2104)):
+        cfg = inputs.config_gauss2d(seed=seed, term_kind=term_kind, term_tol=tol)
         eng = _engine([cfg])
         st = eng.run(poll_every=4)[0]
         o = orc.Oracle(cfg).run()

@@ -183,6 +183,54 @@ def test_xl_peak_termination(orc):
     assert (o.st.lx + math.log(cfg.n_live + 1)) + lmax - o.st.lxl_max < math.log(0.01)
 
 
+def _exact_slice_run(orc, cfg, sig, seed):
+    """A run whose walk is replaced by exact uniform draws from the slice."""
+    c0 = -0.5 * cfg.d * math.log(2 * math.pi * sig ** 2)
+    o = orc.Oracle(cfg).init()
+    rng = np.random.default_rng(seed)
+    while True:
+        o.evidence_update()
+        if not o.active:
+            return o
+        rad = sig * math.sqrt(2 * (c0 - o.st.lstar))
+        X = _ball_box_draws(cfg.n_kill, cfg.d, rad, cfg.lo, cfg.hi, rng)
+        o.out_x[...] = X
+        o.out_logl[...] = c0 - 0.5 * (X ** 2).sum(1) / sig ** 2
+        o.st.it_steps = 0
+        o.replace_dead()
+
+
+def test_xl_peak_dead_point_stop_matches_closed_form(orc):
+    """X*L over the dead points follows the curve X L(X) of the isotropic
+    Gaussian, X(r) = V_d r^d / V_prior with log L = c0 - r^2 / 2 sigma^2; it
+    peaks at r^2 = d sigma^2 and has fallen to tol times the peak where
+    u = r^2 / d sigma^2 < 1 solves log u - u + 1 = 2 log(tol) / d.  With exact
+    slice draws the run stops at the first iteration past that volume: its
+    log Xbar lies within one iteration's shrink, log((n-k+1)/(n+1)), beyond it.
+    The X * max-live-L form of the test fires much earlier, because the top
+    live point sits about log n below Xbar in log X."""
+    from scipy import optimize
+    d, n, sig, lo, hi, tol = 8, 200, 0.5, -6.0, 6.0, 0.01
+    u = optimize.brentq(lambda u: math.log(u) - u + 1 - 2 * math.log(tol) / d, 1e-12, 1.0)
+    log_vd = 0.5 * d * math.log(math.pi) - special.gammaln(0.5 * d + 1)
+    lx_stop = log_vd + 0.5 * d * math.log(u * d * sig ** 2) - d * math.log(hi - lo)
+    shrink = math.log((n // 2 + 1) / (n + 1))
+    base = inputs.RunConfig(kind="gauss_diag", d=d, n_live=n, lo=lo, hi=hi, precision="fp64",
+                            params=inputs.gauss_diag_params(np.zeros(d), np.full(d, sig)),
+                            term_tol=tol)
+    stops = {}
+    for kind in (2, 1):
+        lx = []
+        for r in range(12):
+            o = _exact_slice_run(orc, base.replace(term_kind=kind, seed=900 + r), sig, 77 + r)
+            assert o.st.state == 1
+            lx.append(o.st.iter * shrink)
+        stops[kind] = np.array(lx)
+    se = stops[2].std() / math.sqrt(len(stops[2])) + 0.02
+    assert shrink - 4 * se < stops[2].mean() - lx_stop < 4 * se
+    assert stops[1].mean() > stops[2].mean() + 3.0
+
+
 def test_max_iter_and_nonfinite_states(orc):
     cfg = inputs.config_gauss2d(seed=5, max_iter=3)
     o = orc.Oracle(cfg).run()
