@@ -71,6 +71,10 @@ def load() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2312_03911_amd.build` (no CPU fallback exists)")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so both see the same devices, streams and allocations (a
+        # second runtime loaded beside torch's finds no device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         PD = C.POINTER(ggns_run_desc)

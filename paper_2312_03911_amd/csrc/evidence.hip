@@ -115,6 +115,162 @@ __device__ int block_exscan_int(int v, int *buf) {
     return block_exscan<int>(v, 0, [](int a, int b) { return a + b; }, buf);
 }
 
+// Bitonic sort of 1024 E (key, slot) pairs, E per thread (element i = E t + e
+// of thread t), ascending by key and then slot.  Compare-exchange stages of
+// stride below E stay inside the thread; strides E .. 32 E pair lanes
+// stride / E apart in the same wavefront (DPP for 1 and 2 lanes, ds_swizzle
+// up to 16, a lane permute for 32); strides of 64 E and more cross wavefronts
+// through LDS between two barriers.  The order is total (slots are distinct;
+// the padding entries are all equal), so the sorted sequence is unique.
+template <int X>
+__device__ __forceinline__ int xor_lanes(int v) {
+    if constexpr (X == 1) return __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false);
+    else if constexpr (X == 2) return __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false);
+    else if constexpr (X <= 16) return __builtin_amdgcn_ds_swizzle(v, (X << 10) | 0x1F);
+    else return __shfl_xor(v, X, 64);
+}
+
+__device__ __forceinline__ bool kv_greater(unsigned long long ka, int sa, unsigned long long kb,
+                                           int sb) {
+    return (ka > kb) | ((ka == kb) & (sa > sb));
+}
+
+// This lane's pair against the lane X away: keep the smaller when keep_min.
+template <int X>
+__device__ __forceinline__ void lane_cas(unsigned long long &k, int &s, bool keep_min) {
+    const int lo = xor_lanes<X>((int)(unsigned)k);
+    const int hi = xor_lanes<X>((int)(unsigned)(k >> 32));
+    const int so = xor_lanes<X>(s);
+    const unsigned long long ko = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    const bool gt = kv_greater(k, s, ko, so);
+    const bool take = keep_min ? gt : !gt;
+    k = take ? ko : k;
+    s = take ? so : s;
+}
+
+template <int E>
+__device__ void sort_pairs(unsigned long long (&k)[E], int (&s)[E], unsigned long long *lk, int *ls) {
+    constexpr int N = 1024 * E;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= 64 * E) {
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    lk[E * t + e] = k[e];
+                    ls[E * t + e] = s[e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = E * t + e, j = i ^ stride;
+                    const unsigned long long kb = lk[j];
+                    const int sb = ls[j];
+                    const bool keep_min = ((i & size) == 0) == ((i & stride) == 0);
+                    const bool gt = kv_greater(k[e], s[e], kb, sb);
+                    const bool take = keep_min ? gt : !gt;
+                    k[e] = take ? kb : k[e];
+                    s[e] = take ? sb : s[e];
+                }
+            } else if (stride >= E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = E * t + e;
+                    const bool keep_min = ((i & size) == 0) == ((i & stride) == 0);
+                    switch (stride / E) {
+                        case 1: lane_cas<1>(k[e], s[e], keep_min); break;
+                        case 2: lane_cas<2>(k[e], s[e], keep_min); break;
+                        case 4: lane_cas<4>(k[e], s[e], keep_min); break;
+                        case 8: lane_cas<8>(k[e], s[e], keep_min); break;
+                        case 16: lane_cas<16>(k[e], s[e], keep_min); break;
+                        default: lane_cas<32>(k[e], s[e], keep_min); break;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (e & stride) continue;
+                    const int f = e | stride;
+                    const bool asc = ((E * t + e) & size) == 0;
+                    const bool sw = kv_greater(k[e], s[e], k[f], s[f]) == asc;
+                    const unsigned long long ka = k[e];
+                    const int sa = s[e];
+                    k[e] = sw ? k[f] : k[e];
+                    s[e] = sw ? s[f] : s[e];
+                    k[f] = sw ? ka : k[f];
+                    s[f] = sw ? sa : s[f];
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        lk[E * t + e] = k[e];
+        ls[E * t + e] = s[e];
+    }
+    __syncthreads();
+}
+
+// The kill order of one run: its n log L (padded to 1024 E with entries above
+// every key) sorted with their slots into key[] / slot[] in LDS, after the
+// largest log L and the NaN check (*nan set, nothing sorted) and the
+// termination decision (flags[1], by thread 0).
+template <int E>
+__device__ void kill_order(const RunDev &R, Acc *acc, const double *ll, int final_sweep,
+                           unsigned long long *key, int *slot, double *scratch, int *flags,
+                           bool *nan) {
+    const int n = R.n_live, t = threadIdx.x;
+    unsigned long long k[E];
+    int s[E];
+    double lmax = -INFINITY;
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = E * t + e;
+        if (i < n) {
+            const double v = ll[i];
+            bad = bad | isnan(v);
+            lmax = v > lmax ? v : lmax;
+            k[e] = order_key(v);
+            s[e] = i;
+        } else {
+            k[e] = ~0ull;
+            s[e] = 0x7FFFFFFF;
+        }
+    }
+    if (bad) flags[0] = 1;
+    lmax = block_max_d(lmax, scratch);   // contains the barriers
+    *nan = flags[0] != 0;
+    if (*nan) return;
+    if (t == 0) {
+        double xl = acc->log_xl_max;
+        flags[1] = termination_decision(R, acc, lmax, final_sweep, &xl);
+        acc->log_xl_max = xl;
+    }
+    sort_pairs<E>(k, s, key, slot);
+}
+
+// Survivors' (label << 12 | slot) keys, the others above every key, sorted
+// into key[] (cluster mode).
+template <int E>
+__device__ void sort_survivor_keys(int n, const int32_t *label, const int *dead_flag,
+                                   unsigned long long *key, int *slot) {
+    unsigned long long k[E];
+    int s[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = E * threadIdx.x + e;
+        k[e] = (i < n && !dead_flag[i]) ? (((unsigned long long)label[i] << 12) | (unsigned long long)i)
+                                        : ~0ull;
+        s[e] = 0;
+    }
+    sort_pairs<E>(k, s, key, slot);
+}
+
 // Run summary over the whole dead sequence: information H, and the second
 // moment of Z from the single-cluster recursion (update0, update2, update3,
 // update5, update8).  Written as scans: with X_i = prod n_p/(n_p+1) and
@@ -218,32 +374,18 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     while (NP < n) NP <<= 1;
     const double *ll = at<double>(arena, R.off_live_logl);
     const int t = threadIdx.x, T = blockDim.x;
+    const int E = (n <= 1024) ? 1 : (n <= 2048 ? 2 : 4);
 
     if (t == 0) flags[0] = 0;
     __syncthreads();
-    double lmax = -INFINITY;
-    for (int i = t; i < NP; i += T) {
-        if (i < n) {
-            const double v = ll[i];
-            if (isnan(v)) flags[0] = 1;
-            lmax = v > lmax ? v : lmax;
-            key[i] = order_key(v);
-            slot[i] = i;
-        } else {
-            key[i] = ~0ull;
-            slot[i] = 0x7FFFFFFF;
-        }
-    }
-    lmax = block_max_d(lmax, scratch);   // contains the barriers
-    if (flags[0]) {
+    // the kill order (and the termination test, by thread 0)
+    bool nan = false;
+    if (E == 1) kill_order<1>(R, acc, ll, final_sweep, key, slot, scratch, flags, &nan);
+    else if (E == 2) kill_order<2>(R, acc, ll, final_sweep, key, slot, scratch, flags, &nan);
+    else kill_order<4>(R, acc, ll, final_sweep, key, slot, scratch, flags, &nan);
+    if (nan) {
         if (t == 0) acc->state = GGNS_RUN_NONFINITE;
         return;
-    }
-    // termination test (reading: remaining-evidence or X*L peak)
-    if (t == 0) {
-        double xl = acc->log_xl_max;
-        flags[1] = termination_decision(R, acc, lmax, final_sweep, &xl);
-        acc->log_xl_max = xl;
     }
     // cluster mode: per-cluster counts of this batch's kills
     const bool clm = R.cluster_mode != 0;
@@ -251,51 +393,6 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     int32_t *label = clm ? at<int32_t>(arena, R.off_label) : nullptr;
     __shared__ int kcount[kClMax];
     for (int p = t; p < kClMax; p += T) kcount[p] = 0;
-    // bitonic sort of (log L, slot) ascending.  A compare-exchange stage of
-    // stride j only touches blocks of 2j consecutive keys, so every stage with
-    // 2j <= CH runs inside one wavefront's chunk of CH keys with wavefront-level
-    // ordering only; workgroup barriers remain for the few wide stages.
-    {
-        const int wave = t >> 6, lane = t & 63;
-        const int CH = (NP / (T >> 6) > 128) ? NP / (T >> 6) : (NP < 128 ? NP : 128);
-        auto cas = [&](int i, int stride, int size) {
-            const int lo = 2 * stride * (i / stride) + (i % stride);
-            const int hi = lo + stride;
-            const bool asc = (lo & size) == 0;
-            const unsigned long long ka = key[lo], kb = key[hi];
-            const int sa = slot[lo], sb = slot[hi];
-            const bool greater = (ka > kb) || (ka == kb && sa > sb);
-            if (greater == asc) {
-                key[lo] = kb; key[hi] = ka;
-                slot[lo] = sb; slot[hi] = sa;
-            }
-        };
-        auto wave_sync = [] {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        };
-        // stages of stride <= CH/2 inside the wavefront's chunk [wave CH, wave CH + CH)
-        auto local_stages = [&](int size, int stride) {
-            if (wave * CH < NP) {
-                for (; stride > 0; stride >>= 1) {
-                    for (int q = lane; q < CH / 2; q += 64) cas(wave * (CH / 2) + q, stride, size);
-                    wave_sync();
-                }
-            }
-        };
-        __syncthreads();
-        for (int size = 2; size <= CH; size <<= 1) local_stages(size, size >> 1);
-        for (int size = 2 * CH; size <= NP; size <<= 1) {
-            int stride = size >> 1;
-            for (; 2 * stride > CH; stride >>= 1) {
-                __syncthreads();
-                for (int i = t; i < (NP >> 1); i += T) cas(i, stride, size);
-            }
-            __syncthreads();
-            local_stages(size, stride);
-        }
-    }
     __syncthreads();
     const int stop = flags[1];
     double *dead_l = at<double>(arena, R.off_dead_logl);
@@ -405,21 +502,9 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     }
     // cluster mode: survivors grouped by cluster (ascending slot within each),
     // by a sort of (label, slot) keys; the spawning CDF over the clusters
-    for (int i = t; i < NP; i += T)
-        key[i] = (i < n && !dead_flag[i]) ? (((unsigned long long)label[i] << 12) | (unsigned long long)i)
-                                         : ~0ull;
-    for (int size = 2; size <= NP; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int i = t; i < (NP >> 1); i += T) {
-                const int lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const unsigned long long a = key[lo], b = key[hi];
-                if ((a > b) == asc) { key[lo] = b; key[hi] = a; }
-            }
-        }
-    }
-    __syncthreads();
+    if (E == 1) sort_survivor_keys<1>(n, label, dead_flag, key, slot);
+    else if (E == 2) sort_survivor_keys<2>(n, label, dead_flag, key, slot);
+    else sort_survivor_keys<4>(n, label, dead_flag, key, slot);
     const int nsurv = n - k;
     for (int i = t; i < nsurv; i += T) surv[i] = (int32_t)(key[i] & 0xFFFull);
     const int ncl = tab->n_clusters;

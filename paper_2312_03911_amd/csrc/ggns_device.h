@@ -117,38 +117,43 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
 constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
 
-// Sum N values over the group at once (independent chains interleave).  The
-// four in-row levels are always issued and kept or dropped by a select on the
-// uniform group size, so the step has no branch for them; the two cross-row
-// levels sit behind a uniform branch that only groups of 32 or 64 lanes take.
+// Sum N values over the group at once (independent chains interleave).  Groups
+// of 8 or more lanes take the three in-row levels every group needs without
+// selects, the fourth in-row level and the two cross-row levels behind uniform
+// branches; groups of 1, 2 or 4 lanes issue the two quad levels and keep or
+// drop each by a select on the uniform group size.  The additions, and their
+// order, are the same for every path.
 template <typename T, int N>
 __device__ __forceinline__ void group_sum_n(T (&v)[N], int G) {
+    if (G >= 8) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const T a1 = v[i] + dpp_mov<kDppXor1>(v[i]);
-        v[i] = (G > 1) ? a1 : v[i];
-    }
+        for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_mov<kDppXor1>(v[i]);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const T a2 = v[i] + dpp_mov<kDppXor2>(v[i]);
-        v[i] = (G > 2) ? a2 : v[i];
-    }
+        for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_mov<kDppXor2>(v[i]);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const T a4 = v[i] + dpp_mov<kDppHalfMirror>(v[i]);
-        v[i] = (G > 4) ? a4 : v[i];
-    }
+        for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_mov<kDppHalfMirror>(v[i]);
+        if (G > 8) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const T a8 = v[i] + dpp_mov<kDppMirror>(v[i]);
-        v[i] = (G > 8) ? a8 : v[i];
-    }
-    if (G > 16) {
+            for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_mov<kDppMirror>(v[i]);
+            if (G > 16) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 16, 64);
-        if (G > 32) {
+                for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 16, 64);
+                if (G > 32) {
 #pragma unroll
-            for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 32, 64);
+                    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 32, 64);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const T a1 = v[i] + dpp_mov<kDppXor1>(v[i]);
+            v[i] = (G > 1) ? a1 : v[i];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const T a2 = v[i] + dpp_mov<kDppXor2>(v[i]);
+            v[i] = (G > 2) ? a2 : v[i];
         }
     }
 }

@@ -17,10 +17,11 @@
 // registers for the whole walk.  The run's converted parameters (zero-padded
 // to G*C coordinates) are staged in LDS once per block.  A step is branch-free
 // apart from the rare events (a reservoir write, a prune, the end of a walker):
-// one fused xor-butterfly reduction round in DPP, selects for the reflection,
-// and the noise generated first so that it overlaps the reduction latency.
-// The only HBM traffic of a walk is the gather of its start point and its
-// reservoir writes.
+// one fused xor-butterfly reduction round in DPP, selects for the reflection
+// and the reservoir, and the noise generated first so that it overlaps the
+// reduction latency.  The reservoir point lives in registers and is written
+// once, when the walker ends: the only HBM traffic of a walk is the gather of
+// its start point and that one row.
 #include "ggns_device.h"
 
 #ifndef GGNS_WALK_WAVES
@@ -136,7 +137,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     T *trace_x = reinterpret_cast<T *>(R.trace_x);
     const int k = R.n_kill;
 
-    T x[C], p[C], g[C];
+    T x[C], p[C], g[C], xo[C];
     Xoshiro eps[NB];
     Xoshiro res;
     int m = tile.m_begin + grp;
@@ -155,11 +156,10 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             if (R.cluster_mode) at<int32_t>(arena, R.off_start_cl)[mm] = cl;
         }
         const T *xs = live_x + (int64_t)s * d;
-        T *wo = walk_x + (int64_t)mm * d;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             x[c] = valid[c] ? xs[a0 + c] : T(0);
-            if (valid[c]) wo[a0 + c] = x[c];
+            xo[c] = x[c];
         }
         out_l = live_logl[s];
         momentum_draw<T, C>(seed, (uint32_t)mm, it, 0u, a0, d, p);
@@ -174,6 +174,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     };
 
     if (active) start_walker(m);
+    const bool walker_noise = R.noise_mode != 0;
 
     while (__any(active)) {
         // this step's noise and reservoir draw do not depend on the step, so
@@ -204,7 +205,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 }
             }
         }
-        if (R.noise_mode) {
+        if (walker_noise) {
             // one normal per walker and step: the first of its stream (coordinate 0,
             // held by the group's first lane)
             const T e0 = __shfl(eps_c[0], gbase, 64);
@@ -228,7 +229,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
         const bool viol = group_any(vany, G);
         const bool out = viol || ((double)lk.l <= lstar);
-        if (trace_x != nullptr) {
+        if (__builtin_expect(trace_x != nullptr, 0)) {
             if (active && steps < R.trace_steps) {
                 const int64_t row = (int64_t)steps * k + m;
 #pragma unroll
@@ -259,15 +260,13 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         // trajectory preservation: size-one reservoir over the kept points
         const bool keep = !out && nref >= min_ref;
         nsave += keep ? 1 : 0;
-        const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32))
-                                        : (nsave == 0));
-        if (take && active) {
-            T *wo = walk_x + (int64_t)m * d;
+        // the reservoir's test u * nsave < 2^32 is a zero high word of the product;
+        // bitwise on purpose: the decision costs no branch
+        const bool hit = __umulhi(ures, (uint32_t)nsave) == 0u;
+        const bool take = !out & (keep ? hit : (nsave == 0));
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (valid[c]) wo[a0 + c] = x[c];
-            out_l = (double)lk.l;
-        }
+        for (int c = 0; c < C; ++c) xo[c] = take ? x[c] : xo[c];
+        out_l = take ? (double)lk.l : out_l;
         // pruning: back to the start with fresh momentum
         if (prune_streak > 0 && streak >= prune_streak) {
             if (active) {
@@ -282,6 +281,12 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
         const bool done = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
         const bool need = active && done;
+        if (need) {
+            T *wo = walk_x + (int64_t)m * d;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (valid[c]) wo[a0 + c] = xo[c];
+        }
         if (need && gl == 0) {
             walk_logl[m] = out_l;
             c_outs += outs;
