@@ -264,7 +264,10 @@ def main():
     walk_ms = []
 
     def full_run(record: bool):
-        # re-initialise every run on the same arena, then iterate to the end
+        # re-initialise every run on the same arena, then iterate to the end:
+        # blocks of `poll` iterations, the runs' states copied back after each
+        # block and read one block later, so the stream never drains between
+        # blocks (the block enqueued after the last run stopped is no-ops)
         from paper_2312_03911_amd import _lib
         import ctypes as C
         eng.close()
@@ -272,27 +275,31 @@ def main():
         _lib.check(eng.L.ggns_init(C.byref(eng.ctx), eng.descs, len(cfgs), eng.params.data_ptr(),
                                    eng.params.numel(), eng.arena.data_ptr(), eng.arena_bytes,
                                    eng._stream()), "ggns_init")
+        evs = []
+        pending, b = None, 0
         while True:
-            evs = []
             for _ in range(args.poll):
                 eng.evidence_update()
                 if record:
                     a = torch.cuda.Event(enable_timing=True)
-                    b = torch.cuda.Event(enable_timing=True)
+                    e = torch.cuda.Event(enable_timing=True)
                     a.record(stream)
                     eng.hss_walk()
-                    b.record(stream)
-                    evs.append((a, b))
+                    e.record(stream)
+                    evs.append((a, e))
                 else:
                     eng.hss_walk()
                 eng.replace_dead()
-            st = eng.stats()
-            if record:
-                for a, b in evs:
-                    walk_ms.append(a.elapsed_time(b))
-            if all(s["state"] != 0 for s in st):
-                eng.finalize()
-                return eng.stats()
+            nxt = eng.states_async(b & 1)
+            b += 1
+            if pending is not None and (pending() != _lib.RUN_ACTIVE).all():
+                break
+            pending = nxt
+        eng.finalize()
+        st = eng.stats()
+        for a, e in evs:
+            walk_ms.append(a.elapsed_time(e))
+        return st
 
     for _ in range(args.warmup):
         full_run(False)
@@ -300,9 +307,15 @@ def main():
     t0 = time.perf_counter()
     stats = None
     for _ in range(args.steps):
-        stats = full_run(True)
+        stats = full_run(False)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # the same passes again with HIP events around every walk launch, for the
+    # walk kernel's launch durations (kept out of the throughput figure: each
+    # event adds a few microseconds between launches)
+    for _ in range(args.steps):
+        full_run(True)
+    torch.cuda.synchronize()
 
     evals = sum(s["evals"] for s in stats)
     ms_per_step = 1e3 * elapsed / args.steps

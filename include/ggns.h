@@ -259,6 +259,18 @@ int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out);
 /* Copy every run's stats to host memory `out` (n_runs entries); synchronises `stream`. */
 int ggns_read_stats(ggns_ctx *ctx, ggns_run_stats *out, void *stream);
 
+/* The same copy, enqueued on `stream` without waiting: a small gather kernel
+ * packs the records inside the arena, then one device-to-host copy fills
+ * `out` (n_runs entries, caller owned).  `out` should be pinned host memory
+ * (hipHostMalloc, or a pinned torch tensor) for the copy to run
+ * asynchronously; it is valid once the stream (or an event recorded on it
+ * after this call) has completed, and must not be read or reused before.  A
+ * driver loop can so poll the runs' states one block of iterations behind
+ * without draining the stream between blocks (a stopped run's launches are
+ * no-ops, so the extra block enqueued meanwhile changes nothing).  Not for
+ * graph capture. */
+int ggns_read_stats_async(ggns_ctx *ctx, ggns_run_stats *out, void *stream);
+
 /* Load log Zbar, log Xbar, dt and the iteration counter of one run. */
 int ggns_write_vars(ggns_ctx *ctx, int32_t run, const ggns_run_vars *vars, void *stream);
 

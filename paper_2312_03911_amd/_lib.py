@@ -16,8 +16,8 @@ RUN_ACTIVE, RUN_DONE, RUN_MAXITER, RUN_NONFINITE = 0, 1, 2, 3
 # every symbol the header declares
 SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update", "ggns_finalize",
            "ggns_hss_walk", "ggns_replace_dead", "ggns_loglike_grad", "ggns_loglike_vjp",
-           "ggns_run_layout", "ggns_read_stats", "ggns_write_vars", "ggns_set_trace",
-           "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
+           "ggns_run_layout", "ggns_read_stats", "ggns_read_stats_async", "ggns_write_vars",
+           "ggns_set_trace", "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
            "ggns_noise_normals", "ggns_set_dead_x", "ggns_free", "ggns_status_string")
 
 
@@ -91,6 +91,7 @@ def load() -> C.CDLL:
         L.ggns_loglike_vjp.argtypes = [vp, i32, vp, i64, vp, vp, vp]
         L.ggns_run_layout.argtypes = [vp, i32, C.POINTER(ggns_layout)]
         L.ggns_read_stats.argtypes = [vp, C.POINTER(ggns_run_stats), vp]
+        L.ggns_read_stats_async.argtypes = [vp, vp, vp]
         L.ggns_write_vars.argtypes = [vp, i32, C.POINTER(ggns_run_vars), vp]
         L.ggns_set_trace.argtypes = [vp, i32, vp, vp, vp, i32]
         L.ggns_tile_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
@@ -107,8 +108,8 @@ def load() -> C.CDLL:
         L.ggns_status_string.restype = C.c_char_p
         for name in ("ggns_evidence_update", "ggns_finalize", "ggns_hss_walk", "ggns_replace_dead",
                      "ggns_loglike_grad", "ggns_loglike_vjp", "ggns_run_layout",
-                     "ggns_read_stats", "ggns_write_vars", "ggns_set_trace", "ggns_tile_shape",
-                     "ggns_hss_walk_plain"):
+                     "ggns_read_stats", "ggns_read_stats_async", "ggns_write_vars",
+                     "ggns_set_trace", "ggns_tile_shape", "ggns_hss_walk_plain"):
             getattr(L, name).restype = C.c_int
         _lib = L
         return L

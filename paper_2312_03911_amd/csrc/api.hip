@@ -82,6 +82,8 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
     P.n_tile_slots = ntiles;
     off = align_up(off + (int64_t)sizeof(Tile) * ntiles);
     // contiguous copy of every run's accumulators, gathered for one read-back
+    // the stats records the gather packs for one copy to the host
+    static_assert(sizeof(ggns_run_stats) <= sizeof(Acc), "stats mirror sized by Acc");
     P.off_mirror = off;
     off = align_up(off + (int64_t)sizeof(Acc) * n_runs);
     for (int r = 0; r < n_runs; ++r) {
@@ -172,7 +174,6 @@ struct ggns_ctx {
     int64_t n_params = 0;
     std::vector<Tile> tiles_host;
     std::vector<Class> walk_classes, init_classes;
-    std::vector<Acc> acc_host;
     int max_kd = 1;
     bool any_cluster = false, any_fp64 = false, any_fp32 = false;
     int max_live = 0;
@@ -307,7 +308,6 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
     // MMA runs convert P to FP32 too: their prior draws and the stand-alone
     // likelihood use the FP32 vector path
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    c->acc_host.resize(n_runs);
     if (hipMemcpyAsync(c->runs_dev(), c->plan.runs.data(), sizeof(RunDev) * n_runs,
                        hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(c->tiles_dev(), c->tiles_host.data(), sizeof(Tile) * c->tiles_host.size(),
@@ -467,28 +467,24 @@ int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out) {
     return GGNS_OK;
 }
 
-int ggns_read_stats(ggns_ctx *ctx, ggns_run_stats *out, void *stream) {
+int ggns_read_stats_async(ggns_ctx *ctx, ggns_run_stats *out, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
     if (out == nullptr) return GGNS_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int n = (int)ctx->plan.runs.size();
-    Acc *mirror = at<Acc>(ctx->arena, ctx->plan.off_mirror);
+    ggns_run_stats *mirror = at<ggns_run_stats>(ctx->arena, ctx->plan.off_mirror);
     if (launch_gather_acc(ctx->arena, ctx->runs_dev(), n, mirror, s) != GGNS_OK ||
-        hipMemcpyAsync(ctx->acc_host.data(), mirror, sizeof(Acc) * n, hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
+        hipMemcpyAsync(out, mirror, sizeof(ggns_run_stats) * n, hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
         return GGNS_EHIP;
-    for (int r = 0; r < n; ++r) {
-        const Acc &a = ctx->acc_host[r];
-        ggns_run_stats &o = out[r];
-        o.log_z = a.log_z; o.log_x = a.log_x; o.log_z2 = a.log_z2; o.dt = a.dt; o.lstar = a.lstar;
-        o.log_xl_max = a.log_xl_max; o.h = a.h; o.sigma_kl = a.sigma_kl; o.sigma_mom = a.sigma_mom;
-        o.iter = a.iter; o.evals = a.evals; o.n_dead = a.n_dead; o.steps_out = a.steps_out;
-        o.steps_in = a.steps_in; o.prunes = a.prunes; o.nosave = a.nosave;
-        o.it_outs = (int64_t)a.it_outs; o.it_steps = (int64_t)a.it_steps;
-        o.state = a.state; o.n_clusters = a.n_clusters;
-    }
     return GGNS_OK;
+}
+
+int ggns_read_stats(ggns_ctx *ctx, ggns_run_stats *out, void *stream) {
+    const int rc = ggns_read_stats_async(ctx, out, stream);
+    if (rc != GGNS_OK) return rc;
+    return hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? GGNS_OK
+                                                                                     : GGNS_EHIP;
 }
 
 int ggns_write_vars(ggns_ctx *ctx, int32_t run, const ggns_run_vars *v, void *stream) {

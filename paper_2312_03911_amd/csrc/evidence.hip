@@ -215,62 +215,6 @@ __device__ void sort_pairs(unsigned long long (&k)[E], int (&s)[E], unsigned lon
     __syncthreads();
 }
 
-// The kill order of one run: its n log L (padded to 1024 E with entries above
-// every key) sorted with their slots into key[] / slot[] in LDS, after the
-// largest log L and the NaN check (*nan set, nothing sorted) and the
-// termination decision (flags[1], by thread 0).
-template <int E>
-__device__ void kill_order(const RunDev &R, Acc *acc, const double *ll, int final_sweep,
-                           unsigned long long *key, int *slot, double *scratch, int *flags,
-                           bool *nan) {
-    const int n = R.n_live, t = threadIdx.x;
-    unsigned long long k[E];
-    int s[E];
-    double lmax = -INFINITY;
-    bool bad = false;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = E * t + e;
-        if (i < n) {
-            const double v = ll[i];
-            bad = bad | isnan(v);
-            lmax = v > lmax ? v : lmax;
-            k[e] = order_key(v);
-            s[e] = i;
-        } else {
-            k[e] = ~0ull;
-            s[e] = 0x7FFFFFFF;
-        }
-    }
-    if (bad) flags[0] = 1;
-    lmax = block_max_d(lmax, scratch);   // contains the barriers
-    *nan = flags[0] != 0;
-    if (*nan) return;
-    if (t == 0) {
-        double xl = acc->log_xl_max;
-        flags[1] = termination_decision(R, acc, lmax, final_sweep, &xl);
-        acc->log_xl_max = xl;
-    }
-    sort_pairs<E>(k, s, key, slot);
-}
-
-// Survivors' (label << 12 | slot) keys, the others above every key, sorted
-// into key[] (cluster mode).
-template <int E>
-__device__ void sort_survivor_keys(int n, const int32_t *label, const int *dead_flag,
-                                   unsigned long long *key, int *slot) {
-    unsigned long long k[E];
-    int s[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = E * threadIdx.x + e;
-        k[e] = (i < n && !dead_flag[i]) ? (((unsigned long long)label[i] << 12) | (unsigned long long)i)
-                                        : ~0ull;
-        s[e] = 0;
-    }
-    sort_pairs<E>(k, s, key, slot);
-}
-
 // Run summary over the whole dead sequence: information H, and the second
 // moment of Z from the single-cluster recursion (update0, update2, update3,
 // update5, update8).  Written as scans: with X_i = prod n_p/(n_p+1) and
@@ -358,47 +302,116 @@ __device__ void run_summary(const RunDev &R, Acc *acc, const double *dl, const d
     }
 }
 
-__global__ void __launch_bounds__(kEvThreads)
-evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
-    const RunDev &R = runs[blockIdx.x];
-    Acc *acc = at<Acc>(arena, R.off_acc);
-    if (acc->state != GGNS_RUN_ACTIVE) return;
-
-    __shared__ unsigned long long key[kMaxLive];
-    __shared__ int slot[kMaxLive];
-    __shared__ double scratch[32];
-    __shared__ int flags[2];
-
-    const int n = R.n_live, k = R.n_kill;
-    int NP = 1;
-    while (NP < n) NP <<= 1;
-    const double *ll = at<double>(arena, R.off_live_logl);
-    const int t = threadIdx.x, T = blockDim.x;
-    const int E = (n <= 1024) ? 1 : (n <= 2048 ? 2 : 4);
-
-    if (t == 0) flags[0] = 0;
+// Block-wide maximum and sum with one barrier each: DPP and lane permutes
+// inside the wavefront, the 16 wavefront results through LDS.  Every call
+// takes its own 16 slots of scratch, so none needs a trailing barrier.
+__device__ __forceinline__ double wave_max_d(double v) {
+    v = fmax(v, dpp_mov<kDppXor1>(v));
+    v = fmax(v, dpp_mov<kDppXor2>(v));
+    v = fmax(v, dpp_mov<kDppHalfMirror>(v));
+    v = fmax(v, dpp_mov<kDppMirror>(v));
+    v = fmax(v, __shfl_xor(v, 16, 64));
+    return fmax(v, __shfl_xor(v, 32, 64));
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+    v += dpp_mov<kDppXor1>(v);
+    v += dpp_mov<kDppXor2>(v);
+    v += dpp_mov<kDppHalfMirror>(v);
+    v += dpp_mov<kDppMirror>(v);
+    v += __shfl_xor(v, 16, 64);
+    return v + __shfl_xor(v, 32, 64);
+}
+__device__ double block_max_once(double v, double *sc) {
+    v = wave_max_d(v);
+    if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = v;
     __syncthreads();
-    // the kill order (and the termination test, by thread 0)
-    bool nan = false;
-    if (E == 1) kill_order<1>(R, acc, ll, final_sweep, key, slot, scratch, flags, &nan);
-    else if (E == 2) kill_order<2>(R, acc, ll, final_sweep, key, slot, scratch, flags, &nan);
-    else kill_order<4>(R, acc, ll, final_sweep, key, slot, scratch, flags, &nan);
-    if (nan) {
+    double r = sc[0];
+    for (int i = 1; i < kEvThreads / 64; ++i) r = fmax(r, sc[i]);
+    return r;
+}
+__device__ double block_sum_once(double v, double *sc) {
+    v = wave_sum_d(v);
+    if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < kEvThreads / 64; ++i) r += sc[i];
+    return r;
+}
+
+// One iteration of one run (Algorithm GGNS, the kill loop, and Eqs. update0 to
+// update9 in batch form), with its n log L held E per thread: termination
+// test, kill order, dead records and evidence, volumes, survivors.  The run's
+// accumulators are read once, at the start, next to the log L loads.
+template <int E>
+__device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_sweep,
+                              unsigned long long *key, int *slot, unsigned char *dead_flag,
+                              int *kcount, int *ibuf, double *scratch, int *flags) {
+    const int n = R.n_live, k = R.n_kill;
+    const int t = threadIdx.x, T = blockDim.x;
+    const double *ll = at<double>(arena, R.off_live_logl);
+    unsigned long long kk[E];
+    int ss[E];
+    double vmax = -INFINITY;
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = E * t + e;
+        if (i < n) {
+            const double v = ll[i];
+            bad = bad | isnan(v);
+            vmax = v > vmax ? v : vmax;
+            kk[e] = order_key(v);
+            ss[e] = i;
+        } else {
+            kk[e] = ~0ull;
+            ss[e] = 0x7FFFFFFF;
+        }
+    }
+    // the accumulator fields this launch reads (the termination test's and the
+    // kill's), loaded once
+    Acc a;
+    a.state = acc->state;
+    a.log_x = acc->log_x;
+    a.log_z = acc->log_z;
+    a.lstar = acc->lstar;
+    a.log_xl_max = acc->log_xl_max;
+    a.iter = acc->iter;
+    a.n_dead = acc->n_dead;
+    if (a.state != GGNS_RUN_ACTIVE) return;
+    for (int i = t; i < E * 1024; i += T) dead_flag[i] = 0;
+    for (int p = t; p < kClMax; p += T) kcount[p] = 0;
+    // the largest log L and, through the same barrier, whether any is NaN
+    {
+        const double wm = wave_max_d(vmax);
+        const bool wbad = __ballot(bad) != 0ull;
+        if ((t & 63) == 0) {
+            scratch[t >> 6] = wm;
+            flags[t >> 6] = wbad ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    double lmax = scratch[0];
+    int anybad = flags[0];
+    for (int i = 1; i < kEvThreads / 64; ++i) {
+        lmax = fmax(lmax, scratch[i]);
+        anybad |= flags[i];
+    }
+    if (anybad) {
         if (t == 0) acc->state = GGNS_RUN_NONFINITE;
         return;
     }
-    // cluster mode: per-cluster counts of this batch's kills
+    double xl = a.log_xl_max;
+    const int stop = termination_decision(R, &a, lmax, final_sweep, &xl);
+    if (t == 0) acc->log_xl_max = xl;
+    sort_pairs<E>(kk, ss, key, slot);   // ends with a barrier
+
     const bool clm = R.cluster_mode != 0;
     ClusterTab *tab = clm ? at<ClusterTab>(arena, R.off_cltab) : nullptr;
     int32_t *label = clm ? at<int32_t>(arena, R.off_label) : nullptr;
-    __shared__ int kcount[kClMax];
-    for (int p = t; p < kClMax; p += T) kcount[p] = 0;
-    __syncthreads();
-    const int stop = flags[1];
     double *dead_l = at<double>(arena, R.off_dead_logl);
     double *dead_w = at<double>(arena, R.off_dead_logw);
-    const long long nd = acc->n_dead;
-    const double lw = acc->log_x - log((double)n + 1.0);
+    const long long nd = a.n_dead;
+    const double lw = a.log_x - log((double)n + 1.0);
     const int nkill = stop ? n : k;
 
     // dead records and the log-sum-exp of the killed log L.  With clusters a
@@ -429,19 +442,27 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
         const long long rows = (nd + nkill <= R.dead_x_cap) ? nkill
                                : (nd < R.dead_x_cap ? R.dead_x_cap - nd : 0);
         for (long long e = t; e < rows * d; e += T) {
-            const long long j = e / d, a = e % d;
-            const long long src = ((long long)slot[j] * d + a) * es, dst = ((nd + j) * d + a) * es;
+            const long long j = e / d, c = e % d;
+            const long long src = ((long long)slot[j] * d + c) * es, dst = ((nd + j) * d + c) * es;
             if (es == 8)
                 *reinterpret_cast<double *>(dx + dst) = *reinterpret_cast<const double *>(lx + src);
             else
                 *reinterpret_cast<float *>(dx + dst) = *reinterpret_cast<const float *>(lx + src);
         }
     }
-    const double lse = block_lse(m_loc, s_loc, scratch);
+    const double gmax = block_max_once(m_loc, scratch + 16);
+    double lse = -INFINITY;
+    if (gmax != -INFINITY) {
+        const double part = (m_loc == -INFINITY) ? 0.0 : s_loc * exp(m_loc - gmax);
+        lse = gmax + log(block_sum_once(part, scratch + 32));
+    }
     if (t == 0) {
-        acc->log_z = lae(acc->log_z, clm ? lse : lse + lw);
+        acc->log_z = lae(a.log_z, clm ? lse : lse + lw);
         acc->n_dead = nd + nkill;
-        if (clm) {
+    }
+    if (clm) {
+        __syncthreads();   // kcount complete
+        if (t == 0) {
             // volumes after the batch: Xbar_p (n_p - k_p + 1) / (n_p + 1); a
             // cluster left without points is removed; Xbar = sum over clusters
             double lsum = -INFINITY;
@@ -458,10 +479,12 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
             acc->log_x = lsum;
             acc->n_clusters = tab->n_clusters;
         }
+    }
+    if (t == 0) {
         if (stop) {
             if (!clm) acc->log_x = lw;
         } else {
-            if (!clm) acc->log_x += log((double)(n + 1 - k)) - log((double)n + 1.0);
+            if (!clm) acc->log_x = a.log_x + (log((double)(n + 1 - k)) - log((double)n + 1.0));
             acc->lstar = key_value(key[k - 1]);
             acc->it_outs = 0ull;
             acc->it_steps = 0ull;
@@ -479,14 +502,10 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     // killed slots in kill order; survivors in ascending slot order
     int32_t *killed = at<int32_t>(arena, R.off_killed);
     int32_t *surv = at<int32_t>(arena, R.off_surv);
-    for (int j = t; j < k; j += T) killed[j] = slot[j];
-    __syncthreads();
-    // reuse slot[] as a dead flag per live slot (sorted order is no longer needed
-    // past this point except key[], which stays intact)
-    int *dead_flag = slot;
-    for (int i = t; i < NP; i += T) dead_flag[i] = 0;
-    __syncthreads();
-    for (int j = t; j < k; j += T) dead_flag[killed[j]] = 1;
+    for (int j = t; j < k; j += T) {
+        killed[j] = slot[j];
+        dead_flag[slot[j]] = 1;
+    }
     __syncthreads();
     if (!clm) {
         // each thread owns a contiguous range of slots
@@ -494,7 +513,6 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
         const int s0 = t * per, s1 = (s0 + per < n) ? s0 + per : n;
         int cnt = 0;
         for (int i = s0; i < s1; ++i) cnt += dead_flag[i] ? 0 : 1;
-        __shared__ int ibuf[kEvThreads];
         int pos = block_exscan_int(cnt, ibuf);
         for (int i = s0; i < s1; ++i)
             if (!dead_flag[i]) surv[pos++] = i;
@@ -502,9 +520,18 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     }
     // cluster mode: survivors grouped by cluster (ascending slot within each),
     // by a sort of (label, slot) keys; the spawning CDF over the clusters
-    if (E == 1) sort_survivor_keys<1>(n, label, dead_flag, key, slot);
-    else if (E == 2) sort_survivor_keys<2>(n, label, dead_flag, key, slot);
-    else sort_survivor_keys<4>(n, label, dead_flag, key, slot);
+    {
+        unsigned long long ck[E];
+        int cs[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = E * t + e;
+            ck[e] = (i < n && !dead_flag[i])
+                        ? (((unsigned long long)label[i] << 12) | (unsigned long long)i) : ~0ull;
+            cs[e] = 0;
+        }
+        sort_pairs<E>(ck, cs, key, slot);
+    }
     const int nsurv = n - k;
     for (int i = t; i < nsurv; i += T) surv[i] = (int32_t)(key[i] & 0xFFFull);
     const int ncl = tab->n_clusters;
@@ -526,6 +553,26 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
             tab->cum[p] = cum;
         }
     }
+}
+
+__global__ void __launch_bounds__(kEvThreads)
+evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
+    const RunDev &R = runs[blockIdx.x];
+    Acc *acc = at<Acc>(arena, R.off_acc);
+    __shared__ unsigned long long key[kMaxLive];
+    __shared__ int slot[kMaxLive];
+    __shared__ unsigned char dead_flag[kMaxLive];
+    __shared__ int kcount[kClMax];
+    __shared__ int ibuf[kEvThreads / 64];
+    __shared__ double scratch[48];
+    __shared__ int flags[kEvThreads / 64];
+    const int n = R.n_live;
+    if (n <= 1024)
+        evidence_body<1>(arena, R, acc, final_sweep, key, slot, dead_flag, kcount, ibuf, scratch, flags);
+    else if (n <= 2048)
+        evidence_body<2>(arena, R, acc, final_sweep, key, slot, dead_flag, kcount, ibuf, scratch, flags);
+    else
+        evidence_body<4>(arena, R, acc, final_sweep, key, slot, dead_flag, kcount, ibuf, scratch, flags);
 }
 
 __global__ void __launch_bounds__(kEvThreads)

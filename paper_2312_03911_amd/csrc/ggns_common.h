@@ -103,7 +103,8 @@ int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev
                       int poll_every, hipStream_t s);
 int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_blocks, int steps,
                          float *normals, uint32_t *words, float *checksum, hipStream_t s);
-int launch_gather_acc(void *arena, const RunDev *runs_dev, int n_runs, Acc *mirror, hipStream_t s);
+int launch_gather_acc(void *arena, const RunDev *runs_dev, int n_runs, ggns_run_stats *mirror,
+                      hipStream_t s);
 int launch_clusters(void *arena, const RunDev *runs_dev, int n_runs, int max_live, int final_sweep,
                     bool any_fp64, bool any_fp32, hipStream_t s);
 void launch_set_vars(void *arena, const RunDev *run_dev, double log_z, double log_x, double dt,

@@ -403,13 +403,24 @@ int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_bloc
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }
 
+// Every run's accumulators as the public stats record, packed for one copy.
 __global__ void gather_acc_kernel(void *arena, const RunDev *__restrict__ runs, int n_runs,
-                                  Acc *mirror) {
+                                  ggns_run_stats *mirror) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n_runs) mirror[r] = *at<Acc>(arena, runs[r].off_acc);
+    if (r >= n_runs) return;
+    const Acc &a = *at<Acc>(arena, runs[r].off_acc);
+    ggns_run_stats o;
+    o.log_z = a.log_z; o.log_x = a.log_x; o.log_z2 = a.log_z2; o.dt = a.dt; o.lstar = a.lstar;
+    o.log_xl_max = a.log_xl_max; o.h = a.h; o.sigma_kl = a.sigma_kl; o.sigma_mom = a.sigma_mom;
+    o.iter = a.iter; o.evals = a.evals; o.n_dead = a.n_dead; o.steps_out = a.steps_out;
+    o.steps_in = a.steps_in; o.prunes = a.prunes; o.nosave = a.nosave;
+    o.it_outs = (int64_t)a.it_outs; o.it_steps = (int64_t)a.it_steps;
+    o.state = a.state; o.n_clusters = a.n_clusters;
+    mirror[r] = o;
 }
 
-int launch_gather_acc(void *arena, const RunDev *runs_dev, int n_runs, Acc *mirror, hipStream_t s) {
+int launch_gather_acc(void *arena, const RunDev *runs_dev, int n_runs, ggns_run_stats *mirror,
+                      hipStream_t s) {
     if (n_runs <= 0) return GGNS_OK;
     hipLaunchKernelGGL(gather_acc_kernel, dim3((n_runs + 63) / 64), dim3(64), 0, s, arena, runs_dev,
                        n_runs, mirror);

@@ -14,9 +14,6 @@ import numpy as np
 from . import _lib
 from .inputs import RunConfig
 
-_TERM = {0: 0, 1: 1}
-
-
 def _torch():
     import torch
     return torch
@@ -97,6 +94,7 @@ class Engine:
         self._graph_iters = 0
         self._trace = {}
         self._dead_x = {}
+        self._stat_bufs = None
 
     # ------------------------------------------------------------------ plumbing
     def _stream(self):
@@ -176,15 +174,53 @@ class Engine:
             self.iterate(iters)
 
     def run(self, poll_every: int = 8, use_graph: bool = False, max_blocks: int = 10 ** 6,
-            plain: bool = False):
-        """Iterate until every run stopped; returns the per-run stats."""
-        for _ in range(max_blocks):
-            self.step_block(poll_every, use_graph, plain)
-            st = self.stats()
-            if all(s["state"] != _lib.RUN_ACTIVE for s in st):
+            plain: bool = False, pipelined: bool = True):
+        """Iterate until every run stopped; returns the per-run stats.
+
+        Pipelined (the default): the runs' states are copied back after every
+        block of `poll_every` iterations without draining the stream, and read
+        one block later, while the next block runs; the block enqueued after
+        the last run stopped is all no-op launches.  Results are the same
+        either way."""
+        if plain or not pipelined:
+            for _ in range(max_blocks):
+                self.step_block(poll_every, use_graph, plain)
+                st = self.stats()
+                if all(s["state"] != _lib.RUN_ACTIVE for s in st):
+                    self.finalize()
+                    return self.stats()
+            raise RuntimeError("runs did not terminate")
+        pending = None
+        for b in range(max_blocks):
+            self.step_block(poll_every, use_graph)
+            nxt = self.states_async(b & 1)
+            if pending is not None and not (pending() == _lib.RUN_ACTIVE).any():
                 self.finalize()
                 return self.stats()
+            pending = nxt
         raise RuntimeError("runs did not terminate")
+
+    def states_async(self, slot: int = 0):
+        """Enqueue the copy of every run's stats into pinned host buffer `slot`
+        (0 or 1) on the engine's stream; returns a function that waits for it
+        and gives the runs' states (numpy int32)."""
+        torch = self.torch
+        n = len(self.cfgs)
+        rec = C.sizeof(_lib.ggns_run_stats)
+        if self._stat_bufs is None:
+            self._stat_bufs = [torch.empty(n * rec, dtype=torch.uint8, pin_memory=True)
+                               for _ in range(2)]
+        buf = self._stat_bufs[slot]
+        _lib.check(self.L.ggns_read_stats_async(self.ctx, buf.data_ptr(), self._stream()),
+                   "ggns_read_stats_async")
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(self.device))
+        off = _lib.ggns_run_stats.state.offset
+
+        def wait():
+            ev.synchronize()
+            return buf.numpy().view(np.int32)[off // 4::rec // 4][:n].copy()
+        return wait
 
     # ------------------------------------------------------------------ state
     def stats(self) -> List[dict]:

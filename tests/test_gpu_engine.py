@@ -79,6 +79,22 @@ def test_graph_replays_match_eager_iterations(torch):
             assert s_e[r] == s_g[r], (block, r)
 
 
+def test_pipelined_run_matches_synchronous_run(torch):
+    """Reading the states one block behind (no drain between blocks) gives the
+    same runs as reading them after every block; the asynchronous stats copy
+    carries the same states as the synchronous read."""
+    cfgs = _small_mix()
+    a = _engine(cfgs)
+    sa = a.run(poll_every=3, pipelined=False)
+    b = _engine(cfgs)
+    sb = b.run(poll_every=3, pipelined=True)
+    for x, y in zip(sa, sb):
+        assert x == y
+    assert list(b.states_async(1)()) == [s["state"] for s in sb]
+    a.close()
+    b.close()
+
+
 def test_checkpoint_and_resume_is_exact(torch):
     cfgs = _small_mix()
     a = _engine(cfgs)
