@@ -69,20 +69,35 @@ def workload(name: str):
         return [inputs.config_corr_gauss()]
     if name == "batch64":
         return inputs.config_batch()
-    if name in ("gauss_sweep", "gauss_sweep_dead", "gauss_sweep_classic"):
+    if name.startswith("gauss_sweep"):
         # the dimension sweep of the paper's comparison (diagonal Gaussian,
         # n_live = 200 at every d, 10 runs each): the d=2 Gaussian's family,
         # mean 0.5 and width 0.05 per axis in the unit box, FP32 walks with the
-        # paper's default walk settings; termination at tol 0.01 by the X L peak
-        # with L the largest live likelihood, or with L the dead point's, or by
-        # the remaining evidence
-        term = {"gauss_sweep": 1, "gauss_sweep_dead": 2, "gauss_sweep_classic": 0}[name]
+        # paper's default walk settings.  Termination at tol 0.01 by the X L
+        # peak with L the largest live likelihood (gauss_sweep), with L the dead
+        # point's (gauss_sweep_dead), or by the remaining evidence
+        # (gauss_sweep_classic); ablations of the last: a fixed step of 0.1 or
+        # 0.5 prior widths (_dt01, _dt05), no momentum noise (_dp0)
+        parts = name.split("_")[2:]
+        term = 1
+        kw = {}
+        for p_ in parts:
+            if p_ == "dead":
+                term = 2
+            elif p_ == "classic":
+                term = 0
+            elif p_ in ("dt01", "dt05"):
+                kw.update(dt_init=0.1 if p_ == "dt01" else 0.5, dt_up=1.0, dt_down=1.0)
+            elif p_ == "dp0":
+                kw.update(delta_p=0.0)
+            else:
+                raise SystemExit(f"unknown workload {name}")
         out = []
         for d in (2, 4, 8, 16, 32, 64, 128):
             base = inputs.RunConfig(kind="gauss_diag", d=d, n_live=200, lo=0.0, hi=1.0,
                                     params=inputs.gauss_diag_params(np.full(d, 0.5), np.full(d, 0.05)),
                                     precision="fp32", term_kind=term, term_tol=0.01,
-                                    n_steps_max=max(64, 5 * d), name=f"gauss_d{d}")
+                                    n_steps_max=max(64, 5 * d), name=f"gauss_d{d}", **kw)
             out += inputs.replicate(base, 10, base_seed=8000 + 100 * d)
         return out
     raise SystemExit(f"unknown workload {name}")
