@@ -69,6 +69,13 @@ def workload(name: str):
         return [inputs.config_corr_gauss()]
     if name == "batch64":
         return inputs.config_batch()
+    if name == "torus_sweep":
+        # the torus reward (Eq. torus) at d = 2 ... 128, c = d + 1, alpha = 2,
+        # beta = 3, n_live 500, 10 runs per d, all in one batch
+        out = []
+        for d in (2, 4, 8, 16, 32, 64, 128):
+            out += inputs.replicate(inputs.config_torus(d=d, n_live=500), 10, base_seed=9000 + 100 * d)
+        return out
     if name.startswith("gauss_sweep"):
         # the dimension sweep of the paper's comparison (diagonal Gaussian,
         # n_live = 200 at every d, 10 runs each): the d=2 Gaussian's family,
@@ -116,6 +123,10 @@ def valu_flops_per_eval(cfg, out_frac: float) -> float:
         lik = 5 * K * d + 10 * K
     elif cfg.kind == "gmm_diag":
         lik = 7 * K * d + 10 * K
+    elif cfg.kind == "torus":
+        # per coordinate: argument (FMA), sine and cosine (one each), f cos, the
+        # sum, p.(f cos) and |f cos|^2 (FMAs), the score; log and quotient
+        lik = 11 * d + 10
     elif cfg.precision == "bf16mma":
         lik = 3 * d + 2
     else:
@@ -408,7 +419,7 @@ def main():
                      "sigma_mom_mean": float(np.mean([s["sigma_mom"] for s in stats]))},
     }
     # evaluations and log Z error against dimension (the sweep workloads)
-    if args.workload.startswith("gauss_sweep"):
+    if args.workload.startswith("gauss_sweep") or args.workload == "torus_sweep":
         res["dimension_sweep"] = sweep_report(cfgs, stats, truth)
     # mode recovery of the mixture runs (one untimed pass with the dead points'
     # positions kept)
@@ -441,7 +452,7 @@ def main():
         st_alt = alt.run(poll_every=args.poll)
         alt.close()
         dza = [s_["log_z"] - t for s_, t in zip(st_alt, truth)]
-        if args.workload.startswith("gauss_sweep"):
+        if args.workload.startswith("gauss_sweep") or args.workload == "torus_sweep":
             res["dimension_sweep_walker_noise"] = sweep_report(cfgs, st_alt, truth)
         res["accuracy_walker_noise"] = {
             "noise": "one normal per walker and step",

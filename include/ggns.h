@@ -69,8 +69,15 @@ enum {
  *   GAUSS_DIAG: mu[d], sigma[d]                        N(mu, diag sigma^2)
  *   GAUSS_FULL: mu[d], P[d*d] (row-major), log det P   N(mu, P^-1)
  *   SHELLS:     n_comp x { c[d], r, w }   sum_k (2 pi w^2)^-1/2 exp(-(|x-c_k|-r)^2 / 2w^2)
- *   GMM_DIAG:   n_comp x { mu[d], sigma[d] }           equal-weight diagonal mixture */
-enum { GGNS_LIK_GAUSS_DIAG = 0, GGNS_LIK_GAUSS_FULL = 1, GGNS_LIK_SHELLS = 2, GGNS_LIK_GMM_DIAG = 3 };
+ *   GMM_DIAG:   n_comp x { mu[d], sigma[d] }           equal-weight diagonal mixture
+ *   TORUS:      { alpha, beta, c }   the reward of Eq. (torus), L = (S + c)^3 with
+ *               S = sum over coordinates a = 0 .. d-1 of cos(beta x_a) for even a
+ *               (the paper's odd 1-based indices) and sin(alpha x_a) for odd a; meant
+ *               for the prior box [0, 2 pi)^d; c > d is required (L > 0): a run
+ *               with c <= d starts stopped, in state GGNS_RUN_NONFINITE.  With alpha, beta nonzero integers the normalisation
+ *               over the box is (2 pi)^d (c^3 + 3 d c / 2) (Appendix F). */
+enum { GGNS_LIK_GAUSS_DIAG = 0, GGNS_LIK_GAUSS_FULL = 1, GGNS_LIK_SHELLS = 2, GGNS_LIK_GMM_DIAG = 3,
+       GGNS_LIK_TORUS = 4 };
 
 /* Arithmetic of the walk.  The threshold compare, the evidence, the weights and
  * the log prior volume are FP64 in every mode. */

@@ -180,7 +180,7 @@ static void normals_philox(uint64_t seed, uint32_t walker, uint32_t iter, uint32
 /* under the uniform box prior has a closed form.                        */
 /* ------------------------------------------------------------------ */
 
-enum { LIK_GAUSS_DIAG = 0, LIK_GAUSS_FULL = 1, LIK_SHELLS = 2, LIK_GMM_DIAG = 3 };
+enum { LIK_GAUSS_DIAG = 0, LIK_GAUSS_FULL = 1, LIK_SHELLS = 2, LIK_GMM_DIAG = 3, LIK_TORUS = 4 };
 
 static double logaddexp(double a, double b)
 {
@@ -209,6 +209,9 @@ static double round_bf16(double v)
  *   GAUSS_FULL: mu[d], P[d*d] (precision, row-major), log det P
  *   SHELLS:     K times { c[d], r, w }
  *   GMM_DIAG:   K times { mu[d], sigma[d] }, equal weights 1/K
+ *   TORUS:      alpha, beta, c: the reward of Eq. (torus),
+ *               L = (sum_{i even} sin(alpha x_i) + sum_{j odd} cos(beta x_j) + c)^3
+ *               with the paper's 1-based indices i, j = 1 .. d (x[i-1] in C)
  * Writes log L to *logl and grad log L to g[d] (when g is not NULL). */
 int orc_loglike(int kind, int n_comp, const double *prm, int d, const double *x,
                 double *logl, double *g, int bf16)
@@ -278,6 +281,18 @@ int orc_loglike(int kind, int n_comp, const double *prm, int d, const double *x,
                 for (int a = 0; a < d; ++a) g[a] += coef * (x[a] - c[a]);
             }
         }
+        return 0;
+    }
+    if (kind == LIK_TORUS) {
+        const double alpha = prm[0], beta = prm[1], c = prm[2];
+        double s = c;
+        for (int i = 1; i <= d; ++i)
+            s += (i % 2 == 0) ? sin(alpha * x[i - 1]) : cos(beta * x[i - 1]);
+        *logl = 3.0 * log(s);
+        if (g)
+            for (int i = 1; i <= d; ++i)
+                g[i - 1] = 3.0 * ((i % 2 == 0) ? alpha * cos(alpha * x[i - 1])
+                                                : -beta * sin(beta * x[i - 1])) / s;
         return 0;
     }
     if (kind == LIK_GMM_DIAG) {
@@ -384,6 +399,8 @@ int orc_init(const orc_desc *D, const double *prm, orc_state *S)
     S->steps_out = S->steps_in = S->prunes = S->nosave = 0;
     S->it_outs = S->it_steps = 0;
     S->state = ST_ACTIVE;
+    /* the torus reward is positive everywhere only for c > d */
+    if (D->kind == LIK_TORUS && !(prm[2] > (double)d)) S->state = ST_NONFINITE;
     S->h = S->sigma_kl = S->sigma_mom = 0.0;
     if (D->cluster_mode) {
         for (int i = 0; i < n; ++i) S->label[i] = 0;

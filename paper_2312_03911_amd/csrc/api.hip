@@ -27,7 +27,7 @@ bool valid_desc(const ggns_run_desc &r) {
     if (r.d < 1 || r.d > kMaxD) return false;
     if (r.n_live < 2 || r.n_live > kMaxLive) return false;
     if (r.n_kill < 1 || r.n_kill >= r.n_live) return false;
-    if (r.lik_kind < 0 || r.lik_kind > 3) return false;
+    if (r.lik_kind < 0 || r.lik_kind > GGNS_LIK_TORUS) return false;
     if (r.precision < 0 || r.precision > 2) return false;
     if ((r.lik_kind == GGNS_LIK_SHELLS || r.lik_kind == GGNS_LIK_GMM_DIAG) &&
         (r.n_comp < 1 || r.n_comp > kMaxComp))
@@ -51,6 +51,7 @@ int64_t raw_params(const ggns_run_desc &r) {
         case GGNS_LIK_GAUSS_DIAG: return 2 * d;
         case GGNS_LIK_GAUSS_FULL: return d + d * d + 1;
         case GGNS_LIK_SHELLS: return K * (d + 2);
+        case GGNS_LIK_TORUS: return 3;
         default: return K * 2 * d;
     }
 }

@@ -197,6 +197,8 @@ __device__ __forceinline__ double m_div(double a, double b) { return a / b; }
 //   GAUSS_FULL: mu[d], cst = -d log(2 pi)/2 + log det P / 2, P[d*d]   (unpadded)
 //   SHELLS:     KM blocks {c[dp], r, iw2 = 1/w^2, lognorm = -log(2 pi w^2)/2}
 //   GMM_DIAG:   KM blocks {mu[dp], iv[dp], lognorm = -log K + sum(-log(2 pi)/2 - log sigma)}
+//   TORUS:      f[dp] (beta on even coordinates, alpha on odd ones), ph[dp] (pi/2 on even
+//               coordinates, 0 on odd ones: cos y = sin(y + pi/2)), c
 // Padding coordinates hold zeros (positions and momenta are zero there too) and
 // padding components have lognorm = -inf, so both contribute exactly nothing
 // and the arithmetic needs no per-coordinate or per-component branch.
@@ -261,6 +263,19 @@ struct GmmParams {
     }
 };
 
+template <typename T, int C>
+struct TorusParams {
+    T f[C], ph[C], c;
+    __device__ __forceinline__ void load(const T *prm, int dp, int a0) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            f[j] = prm[a0 + j];
+            ph[j] = prm[dp + a0 + j];
+        }
+        c = prm[2 * dp];
+    }
+};
+
 // The correlated Gaussian keeps P where it was staged (LDS or global) and
 // reads rows of it every step.
 template <typename T>
@@ -284,6 +299,41 @@ __device__ __forceinline__ LikOut<T> lik_gauss_diag(const DiagParams<T, C> &P, i
     }
     group_sum_n<T, 3>(acc, G);
     return {P.cst - T(0.5) * acc[0], acc[1], acc[2]};
+}
+
+// sin and cos of one argument: hardware v_sin / v_cos (they take revolutions)
+// in FP32, the library in FP64.
+__device__ __forceinline__ void m_sincos(float v, float &s, float &c) {
+    const float r = v * 0.159154943091895335769f;
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void m_sincos(double v, double &s, double &c) { sincos(v, &s, &c); }
+
+// Torus reward (Eq. torus): log L = 3 log(S + c), S = sum_a sin(f_a x_a + ph_a),
+// score g_a = 3 f_a cos(f_a x_a + ph_a) / (S + c).  Padding coordinates have
+// f = ph = 0 and add sin(0) = 0.  One reduction round: S, sum p_a f_a cos_a and
+// sum (f_a cos_a)^2.
+template <typename T, int C>
+__device__ __forceinline__ LikOut<T> lik_torus(const TorusParams<T, C> &P, int G,
+                                               const T (&x)[C], const T (&p)[C], T (&g)[C]) {
+    T acc[3] = {T(0), T(0), T(0)};   // S, p.(f cos), |f cos|^2
+    T fc[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        T sn, cs;
+        m_sincos(P.f[j] * x[j] + P.ph[j], sn, cs);
+        fc[j] = P.f[j] * cs;
+        acc[0] += sn;
+        acc[1] += p[j] * fc[j];
+        acc[2] += fc[j] * fc[j];
+    }
+    group_sum_n<T, 3>(acc, G);
+    const T q = acc[0] + P.c;
+    const T inv = m_div(T(3), q);
+#pragma unroll
+    for (int j = 0; j < C; ++j) g[j] = inv * fc[j];
+    return {T(3) * m_log(q), inv * acc[1], inv * inv * acc[2]};
 }
 
 // Shells: with u_k = x - c_k, the score is g = sum_k coef_k u_k, so
@@ -440,7 +490,7 @@ __device__ __forceinline__ LikOut<T> lik_gauss_full(const T *prm, int d, int a0,
     return {cst - T(0.5) * acc[0], acc[1], acc[2]};
 }
 
-// Kernel variants: the four families, with shells split by component count
+// Kernel variants: the five families, with shells split by component count
 // (two or fewer, else up to kMaxComp) so the fused reduction carries only the
 // dot products it needs.
 enum {
@@ -449,12 +499,14 @@ enum {
     VAR_SHELLS2 = 2,
     VAR_GMM = 3,
     VAR_SHELLS8 = 4,
-    VAR_GAUSS_FULL_BF16 = 5
+    VAR_GAUSS_FULL_BF16 = 5,
+    VAR_TORUS = 6
 };
 
 __host__ __device__ inline int lik_variant(int kind, int K, int prec) {
     if (kind == GGNS_LIK_SHELLS) return K <= 2 ? VAR_SHELLS2 : VAR_SHELLS8;
     if (kind == GGNS_LIK_GAUSS_FULL && prec == GGNS_FP32_BF16MMA) return VAR_GAUSS_FULL_BF16;
+    if (kind == GGNS_LIK_TORUS) return VAR_TORUS;
     return kind;
 }
 
@@ -474,6 +526,8 @@ template <typename T, int C>
 struct ParamsOf<T, C, VAR_SHELLS8> { using type = ShellParams<T, C, kMaxComp>; };
 template <typename T, int C>
 struct ParamsOf<T, C, VAR_GMM> { using type = GmmParams<T, C, kMaxComp>; };
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_TORUS> { using type = TorusParams<T, C>; };
 
 template <typename T, int C, int VAR>
 __device__ __forceinline__ LikOut<T> lik_step(const typename ParamsOf<T, C, VAR>::type &P, int d,
@@ -483,6 +537,7 @@ __device__ __forceinline__ LikOut<T> lik_step(const typename ParamsOf<T, C, VAR>
     else if constexpr (VAR == VAR_SHELLS2) return lik_shells<T, C, 2>(P, G, x, p, g);
     else if constexpr (VAR == VAR_SHELLS8) return lik_shells<T, C, kMaxComp>(P, G, x, p, g);
     else if constexpr (VAR == VAR_GMM) return lik_gmm<T, C, kMaxComp>(P, G, x, p, g);
+    else if constexpr (VAR == VAR_TORUS) return lik_torus<T, C>(P, G, x, p, g);
     else if constexpr (VAR == VAR_GAUSS_FULL_BF16)
         return lik_gauss_full<T, C, true>(P.prm, d, a0, G, x, p, g, xch);
     else return lik_gauss_full<T, C>(P.prm, d, a0, G, x, p, g, xch);
@@ -496,7 +551,8 @@ __host__ __device__ inline int variant_slots(int var) {
 // Elements of the converted parameter block (run precision) for a variant.
 __host__ __device__ inline int64_t converted_size(int var, int d, int dp) {
     switch (var) {
-        case VAR_GAUSS_DIAG: return 2 * (int64_t)dp + 1;
+        case VAR_GAUSS_DIAG:
+        case VAR_TORUS: return 2 * (int64_t)dp + 1;
         case VAR_GAUSS_FULL:
         case VAR_GAUSS_FULL_BF16: return (int64_t)d + 1 + (int64_t)d * d;
         case VAR_SHELLS2: return 2 * ((int64_t)dp + 3);
@@ -580,6 +636,7 @@ __device__ inline int pick_start(const RunDev &R, void *arena, const uint32_t (&
         case VAR_SHELLS2: { constexpr int KIND_ = VAR_SHELLS2; CALL; break; }       \
         case VAR_SHELLS8: { constexpr int KIND_ = VAR_SHELLS8; CALL; break; }       \
         case VAR_GAUSS_FULL_BF16: { constexpr int KIND_ = VAR_GAUSS_FULL_BF16; CALL; break; } \
+        case VAR_TORUS: { constexpr int KIND_ = VAR_TORUS; CALL; break; }           \
         default: { constexpr int KIND_ = VAR_GMM; CALL; break; }                    \
     }
 

@@ -34,6 +34,16 @@ __device__ void convert_params(const RunDev &R, const double *raw, T *out) {
         for (int64_t e = t; e < (int64_t)d * d; e += nt)
             out[d + 1 + e] = bf ? (T)round_bf16((float)raw[d + e]) : (T)raw[d + e];
         if (t == 0) out[d] = (T)(-0.5 * d * kLog2Pi + 0.5 * raw[d + (int64_t)d * d]);
+    } else if (R.kind == GGNS_LIK_TORUS) {
+        // the even coordinates (the paper's odd 1-based indices) carry cos(beta x),
+        // written sin(beta x + pi/2); the odd ones sin(alpha x)
+        const double half_pi = 1.57079632679489661923;
+        for (int a = t; a < dp; a += nt) {
+            const bool on = a < d;
+            out[a] = on ? (T)((a & 1) ? raw[0] : raw[1]) : T(0);
+            out[dp + a] = (on && !(a & 1)) ? (T)half_pi : T(0);
+        }
+        if (t == 0) out[2 * dp] = (T)raw[2];
     } else if (R.kind == GGNS_LIK_SHELLS) {
         for (int kk = 0; kk < slots; ++kk) {
             const double *blk = raw + kk * (d + 2);
@@ -122,6 +132,8 @@ __global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, con
         acc->steps_out = acc->steps_in = acc->prunes = acc->nosave = 0;
         acc->it_outs = acc->it_steps = 0ull;
         acc->state = GGNS_RUN_ACTIVE;
+        // the torus reward is a likelihood only where S + c > 0 for every x: c > d
+        if (R.kind == GGNS_LIK_TORUS && !(raw[2] > (double)R.d)) acc->state = GGNS_RUN_NONFINITE;
         acc->n_clusters = R.cluster_mode ? 1 : 0;
         if (R.cluster_mode) {
             ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);

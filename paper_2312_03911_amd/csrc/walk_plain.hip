@@ -82,6 +82,12 @@ __device__ double plain_loglike(const RunDev &R, const double *prm, const double
         }
         return prm[2 * dp] - 0.5 * q;
     }
+    if (R.kind == GGNS_LIK_TORUS) {
+        double q = prm[2 * dp];
+        for (int a = 0; a < d; ++a) q += sin(prm[a] * x(a) + prm[dp + a]);
+        for (int a = 0; a < d; ++a) gset(a, 3.0 * prm[a] * cos(prm[a] * x(a) + prm[dp + a]) / q);
+        return 3.0 * log(q);
+    }
     if (R.kind == GGNS_LIK_GAUSS_FULL) {
         const double *P = prm + d + 1;
         double q = 0.0;

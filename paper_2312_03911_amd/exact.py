@@ -72,6 +72,19 @@ def log_z_gauss_full(d, logdet_p, lo, hi):
     return -d * math.log(hi - lo)
 
 
+def log_z_torus(d, alpha, beta, c, lo, hi):
+    """The torus reward over the uniform prior on [0, 2 pi)^d: the recursion of
+    Appendix F, Z_d = 2 pi Z_{d-1} + 3 pi c (2 pi)^(d-1), Z_1 = 2 pi c^3 + 3 pi c,
+    divided by the prior volume (2 pi)^d, is c^3 + 3 d c / 2.  It holds for
+    nonzero integer frequencies (then every sine and cosine and the odd
+    moments integrate to zero over whole periods)."""
+    if not (alpha == int(alpha) and beta == int(beta) and alpha != 0 and beta != 0):
+        raise ValueError("the torus normalisation needs nonzero integer alpha and beta")
+    if abs(lo) > 1e-12 or abs(hi - 2 * math.pi) > 1e-12:
+        raise ValueError("the torus normalisation is over [0, 2 pi)^d")
+    return math.log(c ** 3 + 1.5 * d * c)
+
+
 def log_z(cfg: RunConfig) -> float:
     d, p = cfg.d, cfg.params
     if cfg.kind == "gauss_diag":
@@ -82,4 +95,6 @@ def log_z(cfg: RunConfig) -> float:
         return log_z_shells(d, cfg.n_comp, float(p[d]), float(p[d + 1]), cfg.lo, cfg.hi)
     if cfg.kind == "gauss_full":
         return log_z_gauss_full(d, float(p[d + d * d]), cfg.lo, cfg.hi)
+    if cfg.kind == "torus":
+        return log_z_torus(d, float(p[0]), float(p[1]), float(p[2]), cfg.lo, cfg.hi)
     raise ValueError(cfg.kind)

@@ -25,7 +25,7 @@ from typing import List
 
 import numpy as np
 
-KINDS = {"gauss_diag": 0, "gauss_full": 1, "shells": 2, "gmm_diag": 3}
+KINDS = {"gauss_diag": 0, "gauss_full": 1, "shells": 2, "gmm_diag": 3, "torus": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16mma": 2}
 NOISE = {"component": 0, "walker": 1}
 
@@ -95,6 +95,7 @@ class RunConfig:
 #   gauss_full: mu[d], P[d*d] (precision matrix, row-major), log det P
 #   shells:     n_comp blocks of {centre[d], radius, width}
 #   gmm_diag:   n_comp blocks of {mu[d], sigma[d]}, equal weights
+#   torus:      {alpha, beta, c} of the torus reward (Eq. torus)
 # ---------------------------------------------------------------------------
 
 def gauss_diag_params(mu, sigma) -> np.ndarray:
@@ -108,6 +109,10 @@ def shells_params(centres, radius, width) -> np.ndarray:
 
 def gmm_params(mus, sigmas) -> np.ndarray:
     return np.concatenate([np.concatenate([m, s]) for m, s in zip(mus, sigmas)]).astype(np.float64)
+
+
+def torus_params(alpha, beta, c) -> np.ndarray:
+    return np.array([alpha, beta, c], np.float64)
 
 
 def haar_orthogonal(d: int, rng: np.random.Generator) -> np.ndarray:
@@ -184,6 +189,20 @@ def config_gmm(d: int = 64, n_live: int = 4000, n_comp: int = 8, seed: int = 240
     base = dict(kind="gmm_diag", d=d, n_live=n_live, params=prm, lo=-8.0, hi=8.0,
                 n_comp=n_comp, precision="fp32", n_steps_max=5 * d, min_ref=1,
                 max_ref=3, seed=seed, name=f"gmm{n_comp}_d{d}_nlive{n_live}_fp32")
+    base.update(kw)
+    return RunConfig(**base)
+
+
+def config_torus(d: int = 32, n_live: int = 500, alpha: int = 2, beta: int = 3, c=None,
+                 seed: int = 2600, **kw) -> RunConfig:
+    """Torus reward (Eq. torus) on the prior box [0, 2 pi)^d with integer
+    frequencies alpha = 2, beta = 3 and c = d + 1 (the smallest integer with a
+    positive reward everywhere; the paper states neither); FP32 walks with the
+    paper's walk defaults (min_ref 1, max_ref 3), cap max(64, 5d)."""
+    cc = float(d + 1) if c is None else float(c)
+    base = dict(kind="torus", d=d, n_live=n_live, params=torus_params(alpha, beta, cc), lo=0.0,
+                hi=2.0 * math.pi, precision="fp32", n_steps_max=max(64, 5 * d), min_ref=1,
+                max_ref=3, seed=seed, name=f"torus_d{d}_nlive{n_live}_a{alpha}b{beta}")
     base.update(kw)
     return RunConfig(**base)
 

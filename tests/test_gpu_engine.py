@@ -167,6 +167,24 @@ def test_shells_end_to_end_agree_with_oracle_within_error(torch, orc):
     assert abs(diff) < 4 * err, (diff, err)
 
 
+def test_torus_runs_match_closed_form_and_oracle(torch, orc):
+    """Torus reward, FP32 on the GPU: ten d = 32 runs in one batch; their mean
+    log Z lies within three standard errors of the closed form, like the FP64
+    oracle's runs of the same problem; a run with c <= d stops before walking."""
+    cfgs = inputs.replicate(inputs.config_torus(d=32, n_live=200), 10, base_seed=2800)
+    bad = inputs.config_torus(d=8, n_live=100, c=8.0)
+    eng = _engine(cfgs + [bad])
+    st = eng.run(poll_every=8)
+    truth = exact.log_z(cfgs[0])
+    dz = np.array([s["log_z"] - truth for s in st[:-1]])
+    assert all(s["state"] == 1 for s in st[:-1])
+    assert st[-1]["state"] == 3 and st[-1]["iter"] == 0
+    se = max(dz.std(ddof=1), np.mean([s["sigma_kl"] for s in st[:-1]])) / math.sqrt(len(dz))
+    assert abs(dz.mean()) < 3 * se, (dz.mean(), se)
+    oz = np.array([orc.Oracle(c.replace(precision="fp64")).run().st.lz - truth for c in cfgs[:4]])
+    assert abs(oz.mean()) < 3 * max(oz.std(ddof=1), 0.02) / 2 + 3 * se
+
+
 def test_tile_shapes_agree_and_autotune_picks_one(torch):
     """Every coordinates-per-lane choice computes the same walk (FP64: up to
     summation order), and the autotuner returns an admissible choice."""

@@ -69,6 +69,10 @@ CASES = [
                                                      precision="bf16mma", n_steps_max=60), 1e-4, 1e-4),
     ("corr128_bf16", lambda: inputs.config_corr_gauss(d=128, n_live=256, seed=18, param_seed=9,
                                                       precision="bf16mma"), 1e-4, 1e-4),
+    # torus reward (hardware sin/cos in FP32, the library's in FP64)
+    ("torus16_fp32", lambda: inputs.config_torus(d=16, n_live=400, seed=23), 1e-4, 1e-4),
+    ("torus9_fp64", lambda: inputs.config_torus(d=9, n_live=200, seed=24, precision="fp64"),
+     1e-10, 1e-9),
     # one noise normal per walker and step (noise_mode 1)
     ("gauss2d_fp64_wnoise", lambda: inputs.config_gauss2d(seed=19, noise="walker"), 1e-10, 1e-9),
     ("shells32_fp32_wnoise", lambda: inputs.config_shells(d=32, n_live=1000, seed=20, noise="walker"),
