@@ -138,6 +138,8 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.off_walk_logl = off; off = align_up(off + (int64_t)D.n_kill * 8);
         R.off_dead_logl = off; off = align_up(off + R.dead_cap * 8);
         R.off_dead_logw = off; off = align_up(off + R.dead_cap * 8);
+        R.fin_chunks = (int32_t)((R.dead_cap + kFinChunk - 1) / kFinChunk);
+        R.off_fin = off; off = align_up(off + (int64_t)R.fin_chunks * 5 * 8);
         if (D.cluster_mode) {
             R.off_label = off; off = align_up(off + (int64_t)D.n_live * 4);
             R.off_cltab = off; off = align_up(off + (int64_t)sizeof(ClusterTab));
@@ -358,13 +360,15 @@ int ggns_evidence_update(ggns_ctx *ctx, int32_t final_sweep, void *stream) {
         if (rc != GGNS_OK) return rc;
     }
     launch_evidence(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), final_sweep ? 1 : 0,
-                    reinterpret_cast<hipStream_t>(stream));
+                    ctx->any_cluster ? 1 : 0, reinterpret_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }
 
 int ggns_finalize(ggns_ctx *ctx, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
-    launch_finalize(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(),
+    int max_chunks = 1;
+    for (const RunDev &R : ctx->plan.runs) max_chunks = std::max(max_chunks, (int)R.fin_chunks);
+    launch_finalize(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), max_chunks,
                     reinterpret_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }

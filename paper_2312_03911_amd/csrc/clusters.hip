@@ -32,6 +32,20 @@ __device__ __forceinline__ bool lex_less(T a, int sa, T b, int sb) {
 
 }  // namespace
 
+// (label << 12 | slot) of the n live slots, E per thread, sorted into key[]
+template <int E>
+__device__ void group_members(int n, const int32_t *label, unsigned long long *key, int *slot) {
+    unsigned long long k[E];
+    int s[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = E * threadIdx.x + e;
+        k[e] = (i < n) ? (((unsigned long long)label[i] << 12) | (unsigned long long)i) : ~0ull;
+        s[e] = 0;
+    }
+    sort_pairs<E>(k, s, key, slot);
+}
+
 // Termination decision and members grouped by cluster.
 __global__ void __launch_bounds__(kClThreads)
 cluster_pre_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
@@ -40,7 +54,8 @@ cluster_pre_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep
     Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
     ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
-    __shared__ uint32_t key[kMaxLive];
+    __shared__ unsigned long long key[kMaxLive];
+    __shared__ int slot_s[kMaxLive];
     __shared__ double scratch[32];
     __shared__ int nanflag;
     const int n = R.n_live, t = threadIdx.x, T = blockDim.x;
@@ -58,22 +73,10 @@ cluster_pre_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep
     const int stop = nanflag ? 1 : termination_decision(R, acc, lmax, final_sweep, nullptr);
     if (t == 0) tab->stopping = stop;
     if (stop) return;
-    // live slots grouped by cluster: sort of (label << 12 | slot)
-    int NP = 1;
-    while (NP < n) NP <<= 1;
-    for (int i = t; i < NP; i += T) key[i] = (i < n) ? ((uint32_t)label[i] << 12) | (uint32_t)i : 0xFFFFFFFFu;
-    for (int size = 2; size <= NP; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int i = t; i < (NP >> 1); i += T) {
-                const int lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const uint32_t a = key[lo], b = key[hi];
-                if ((a > b) == asc) { key[lo] = b; key[hi] = a; }
-            }
-        }
-    }
-    __syncthreads();
+    // live slots grouped by cluster: sort of (label << 12 | slot) keys
+    if (n <= 1024) group_members<1>(n, label, key, slot_s);
+    else if (n <= 2048) group_members<2>(n, label, key, slot_s);
+    else group_members<4>(n, label, key, slot_s);
     int32_t *members = at<int32_t>(arena, R.off_members);
     for (int i = t; i < n; i += T) members[i] = (int32_t)(key[i] & 0xFFFu);
     const int nc = tab->n_clusters;

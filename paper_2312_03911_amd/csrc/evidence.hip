@@ -115,192 +115,6 @@ __device__ int block_exscan_int(int v, int *buf) {
     return block_exscan<int>(v, 0, [](int a, int b) { return a + b; }, buf);
 }
 
-// Bitonic sort of 1024 E (key, slot) pairs, E per thread (element i = E t + e
-// of thread t), ascending by key and then slot.  Compare-exchange stages of
-// stride below E stay inside the thread; strides E .. 32 E pair lanes
-// stride / E apart in the same wavefront (DPP for 1 and 2 lanes, ds_swizzle
-// up to 16, a lane permute for 32); strides of 64 E and more cross wavefronts
-// through LDS between two barriers.  The order is total (slots are distinct;
-// the padding entries are all equal), so the sorted sequence is unique.
-template <int X>
-__device__ __forceinline__ int xor_lanes(int v) {
-    if constexpr (X == 1) return __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false);
-    else if constexpr (X == 2) return __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false);
-    else if constexpr (X <= 16) return __builtin_amdgcn_ds_swizzle(v, (X << 10) | 0x1F);
-    else return __shfl_xor(v, X, 64);
-}
-
-__device__ __forceinline__ bool kv_greater(unsigned long long ka, int sa, unsigned long long kb,
-                                           int sb) {
-    return (ka > kb) | ((ka == kb) & (sa > sb));
-}
-
-// This lane's pair against the lane X away: keep the smaller when keep_min.
-template <int X>
-__device__ __forceinline__ void lane_cas(unsigned long long &k, int &s, bool keep_min) {
-    const int lo = xor_lanes<X>((int)(unsigned)k);
-    const int hi = xor_lanes<X>((int)(unsigned)(k >> 32));
-    const int so = xor_lanes<X>(s);
-    const unsigned long long ko = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
-    const bool gt = kv_greater(k, s, ko, so);
-    const bool take = keep_min ? gt : !gt;
-    k = take ? ko : k;
-    s = take ? so : s;
-}
-
-template <int E>
-__device__ void sort_pairs(unsigned long long (&k)[E], int (&s)[E], unsigned long long *lk, int *ls) {
-    constexpr int N = 1024 * E;
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            if (stride >= 64 * E) {
-                __syncthreads();
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    lk[E * t + e] = k[e];
-                    ls[E * t + e] = s[e];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int i = E * t + e, j = i ^ stride;
-                    const unsigned long long kb = lk[j];
-                    const int sb = ls[j];
-                    const bool keep_min = ((i & size) == 0) == ((i & stride) == 0);
-                    const bool gt = kv_greater(k[e], s[e], kb, sb);
-                    const bool take = keep_min ? gt : !gt;
-                    k[e] = take ? kb : k[e];
-                    s[e] = take ? sb : s[e];
-                }
-            } else if (stride >= E) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int i = E * t + e;
-                    const bool keep_min = ((i & size) == 0) == ((i & stride) == 0);
-                    switch (stride / E) {
-                        case 1: lane_cas<1>(k[e], s[e], keep_min); break;
-                        case 2: lane_cas<2>(k[e], s[e], keep_min); break;
-                        case 4: lane_cas<4>(k[e], s[e], keep_min); break;
-                        case 8: lane_cas<8>(k[e], s[e], keep_min); break;
-                        case 16: lane_cas<16>(k[e], s[e], keep_min); break;
-                        default: lane_cas<32>(k[e], s[e], keep_min); break;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    if (e & stride) continue;
-                    const int f = e | stride;
-                    const bool asc = ((E * t + e) & size) == 0;
-                    const bool sw = kv_greater(k[e], s[e], k[f], s[f]) == asc;
-                    const unsigned long long ka = k[e];
-                    const int sa = s[e];
-                    k[e] = sw ? k[f] : k[e];
-                    s[e] = sw ? s[f] : s[e];
-                    k[f] = sw ? ka : k[f];
-                    s[f] = sw ? sa : s[f];
-                }
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        lk[E * t + e] = k[e];
-        ls[E * t + e] = s[e];
-    }
-    __syncthreads();
-}
-
-// Run summary over the whole dead sequence: information H, and the second
-// moment of Z from the single-cluster recursion (update0, update2, update3,
-// update5, update8).  Written as scans: with X_i = prod n_p/(n_p+1) and
-// Y_i = prod n_p/(n_p+2) over the records before i, ZX_i = X_i sum_{j<i}
-// Y_j L_j / ((n_j+2) X_j), and Z2 = sum_i 2 ZX_i L_i/(n_i+1) + 2 Y_i L_i^2 /
-// ((n_i+1)(n_i+2)).  The live count n_p of record i follows from the kill
-// pattern (iterations kill k points with n_p = n, ..., n-k+1; the final sweep
-// n points with n_p = n, ..., 1), so log n_p, log(n_p+1), log(n_p+2) come from a
-// table of log v, v = 0 .. n+2, held in LDS.
-__device__ void run_summary(const RunDev &R, Acc *acc, const double *dl, const double *dw,
-                            long long N, long long n_batch, double *lg, double *buf,
-                            double *scratch) {
-    const int n = R.n_live, k = R.n_kill;
-    const int T = blockDim.x, t = threadIdx.x;
-    for (int v = t; v <= n + 2; v += T) lg[v] = (v > 0) ? log((double)v) : -INFINITY;
-    __syncthreads();
-    const long long chunk = (N + T - 1) / T;
-    const long long i0 = (long long)t * chunk;
-    const long long i1 = (i0 + chunk < N) ? i0 + chunk : N;
-    const double lz = acc->log_z;
-    // position of record i0 in its kill pattern
-    auto np_at = [&](long long i) -> int {
-        return (i < n_batch) ? n - (int)(i % k) : n - (int)(i - n_batch);
-    };
-
-    // H = sum p_i (log L_i - log Z), p_i = L_i w_i / Z; prefix sums of log X, log Y
-    double hpart = 0.0, sx = 0.0, sy = 0.0;
-    {
-        int np = (i0 < N) ? np_at(i0) : n;
-        for (long long i = i0; i < i1; ++i) {
-            const double lp = dl[i] + dw[i] - lz;
-            hpart += exp(lp) * (dl[i] - lz);
-            sx += lg[np] - lg[np + 1];
-            sy += lg[np] - lg[np + 2];
-            --np;
-            if (i + 1 == n_batch || (i + 1 < n_batch && np == n - k)) np = n;
-        }
-    }
-    const double h = block_sum(hpart, scratch);
-    const double lx0 = block_exscan_sum(sx, buf);
-    const double ly0 = block_exscan_sum(sy, buf);
-    // local log-sum of c_j = Y_j L_j / ((n_j+2) X_j)
-    double cm = -INFINITY, cs = 0.0;
-    {
-        double x = lx0, y = ly0;
-        int np = (i0 < N) ? np_at(i0) : n;
-        for (long long i = i0; i < i1; ++i) {
-            lse_push(y + dl[i] - lg[np + 2] - x, cm, cs);
-            x += lg[np] - lg[np + 1];
-            y += lg[np] - lg[np + 2];
-            --np;
-            if (i + 1 == n_batch || (i + 1 < n_batch && np == n - k)) np = n;
-        }
-    }
-    const double lc_local = (cm == -INFINITY) ? -INFINITY : cm + log(cs);
-    const double lsum = block_exscan_lae(lc_local, buf);
-    // terms of Z2 and of the recursion's own Z
-    double am = -INFINITY, as = 0.0, zm = -INFINITY, zs = 0.0;
-    {
-        double x = lx0, y = ly0;
-        double sm = lsum, ss = (lsum == -INFINITY) ? 0.0 : 1.0;   // running S_j as (sm, ss)
-        const double l2 = 0.69314718055994530942;
-        int np = (i0 < N) ? np_at(i0) : n;
-        for (long long i = i0; i < i1; ++i) {
-            const double ln1 = lg[np + 1], ln2 = lg[np + 2];
-            const double ls = (sm == -INFINITY) ? -INFINITY : sm + log(ss);
-            lse_push(l2 + x + ls + dl[i] - ln1, am, as);
-            lse_push(l2 + y + 2.0 * dl[i] - ln1 - ln2, am, as);
-            lse_push(x + dl[i] - ln1, zm, zs);
-            lse_push(y + dl[i] - ln2 - x, sm, ss);
-            x += lg[np] - ln1;
-            y += lg[np] - ln2;
-            --np;
-            if (i + 1 == n_batch || (i + 1 < n_batch && np == n - k)) np = n;
-        }
-    }
-    const double lz2 = block_lse(am, as, scratch);
-    const double lzr = block_lse(zm, zs, scratch);
-    if (t == 0) {
-        acc->h = h;
-        acc->sigma_kl = sqrt(h > 0.0 ? h / n : 0.0);
-        acc->log_z2 = R.cluster_mode ? -INFINITY : lz2;
-        const double v = lz2 - 2.0 * lzr;
-        acc->sigma_mom = R.cluster_mode ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
-    }
-}
 
 // Block-wide maximum and sum with one barrier each: DPP and lane permutes
 // inside the wavefront, the 16 wavefront results through LDS.  Every call
@@ -506,20 +320,35 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
         killed[j] = slot[j];
         dead_flag[slot[j]] = 1;
     }
+    if (clm) return;   // cluster mode: cluster_group_kernel groups the survivors
     __syncthreads();
-    if (!clm) {
-        // each thread owns a contiguous range of slots
-        const int per = (n + T - 1) / T;
-        const int s0 = t * per, s1 = (s0 + per < n) ? s0 + per : n;
-        int cnt = 0;
-        for (int i = s0; i < s1; ++i) cnt += dead_flag[i] ? 0 : 1;
-        int pos = block_exscan_int(cnt, ibuf);
-        for (int i = s0; i < s1; ++i)
-            if (!dead_flag[i]) surv[pos++] = i;
-        return;
-    }
-    // cluster mode: survivors grouped by cluster (ascending slot within each),
-    // by a sort of (label, slot) keys; the spawning CDF over the clusters
+    // each thread owns a contiguous range of slots
+    const int per = (n + T - 1) / T;
+    const int s0 = t * per, s1 = (s0 + per < n) ? s0 + per : n;
+    int cnt = 0;
+    for (int i = s0; i < s1; ++i) cnt += dead_flag[i] ? 0 : 1;
+    int pos = block_exscan_int(cnt, ibuf);
+    for (int i = s0; i < s1; ++i)
+        if (!dead_flag[i]) surv[pos++] = i;
+}
+
+// Cluster mode, after the kill: survivors grouped by cluster (ascending slot
+// within each) by a sort of (label, slot) keys, the survivor offsets of every
+// cluster and the spawning CDF over the clusters (Algorithm GGNS, the cluster
+// labels of the new points drawn in proportion to Xbar_p).  A launch of its
+// own, so that the evidence kernel's registers do not carry a second sort.
+template <int E>
+__device__ void cluster_group_body(void *arena, const RunDev &R, unsigned long long *key, int *slot,
+                                   unsigned char *dead_flag) {
+    const int n = R.n_live, k = R.n_kill, t = threadIdx.x, T = blockDim.x;
+    const int32_t *killed = at<int32_t>(arena, R.off_killed);
+    const int32_t *label = at<int32_t>(arena, R.off_label);
+    int32_t *surv = at<int32_t>(arena, R.off_surv);
+    ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
+    for (int i = t; i < E * 1024; i += T) dead_flag[i] = 0;
+    __syncthreads();
+    for (int j = t; j < k; j += T) dead_flag[killed[j]] = 1;
+    __syncthreads();
     {
         unsigned long long ck[E];
         int cs[E];
@@ -556,6 +385,20 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
 }
 
 __global__ void __launch_bounds__(kEvThreads)
+cluster_group_kernel(void *arena, const RunDev *__restrict__ runs) {
+    const RunDev &R = runs[blockIdx.x];
+    const Acc *acc = at<Acc>(arena, R.off_acc);
+    if (!R.cluster_mode || acc->state != GGNS_RUN_ACTIVE) return;
+    __shared__ unsigned long long key[kMaxLive];
+    __shared__ int slot[kMaxLive];
+    __shared__ unsigned char dead_flag[kMaxLive];
+    const int n = R.n_live;
+    if (n <= 1024) cluster_group_body<1>(arena, R, key, slot, dead_flag);
+    else if (n <= 2048) cluster_group_body<2>(arena, R, key, slot, dead_flag);
+    else cluster_group_body<4>(arena, R, key, slot, dead_flag);
+}
+
+__global__ void __launch_bounds__(kEvThreads)
 evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
     const RunDev &R = runs[blockIdx.x];
     Acc *acc = at<Acc>(arena, R.off_acc);
@@ -575,32 +418,226 @@ evidence_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep) {
         evidence_body<4>(arena, R, acc, final_sweep, key, slot, dead_flag, kcount, ibuf, scratch, flags);
 }
 
-__global__ void __launch_bounds__(kEvThreads)
-finalize_kernel(void *arena, const RunDev *__restrict__ runs) {
+// ---------------------------------------------------------------------------
+// Run summary after the final sweep: information H and the second moment of Z
+// from the single-cluster recursion (Eqs. update0, update2, update3, update5,
+// update8), over the dead sequence in chunks of kFinChunk records, one
+// workgroup per chunk and run.  Written as scans: with X_i = prod n_p/(n_p+1)
+// and Y_i = prod n_p/(n_p+2) over the records before i, and
+// S_i = sum_{j<i} c_j, c_j = Y_j L_j / ((n_j+2) X_j):
+//   Z2 = sum_i 2 X_i S_i L_i/(n_i+1) + 2 Y_i L_i^2 / ((n_i+1)(n_i+2)),
+//   Zr = sum_i X_i L_i/(n_i+1)  (the recursion's own Z).
+// The live count n_p of record i follows from the kill pattern (iterations
+// kill k points with n_p = n, ..., n-k+1; the final sweep n points with
+// n_p = n, ..., 1), so X_i and Y_i telescope to closed forms:
+//   r kills into a pattern give n+1-r over n+1 for X and
+//   (n+1-r)(n+2-r) over (n+1)(n+2) for Y; a whole iteration r = k.
+// Four launches: chunk totals of H and of the log-sum of c; a per-run scan of
+// the c totals; the chunk totals of Z2 and Zr from each chunk's start S; the
+// per-run sums.  Every partial lives in the run's `fin` section:
+//   [0][chunk] H part, [1][chunk] log-sum of c, [2][chunk] exclusive scan of [1],
+//   [3][chunk] log Z2 part, [4][chunk] log Zr part.
+// ---------------------------------------------------------------------------
+struct FinRun {
+    int n, k;
+    long long N, n_batch;
+    double lk_x, lk_y;   // log X and log Y factors of one whole iteration
+};
+
+__device__ __forceinline__ FinRun fin_run(const RunDev &R, const Acc *acc) {
+    FinRun f;
+    f.n = R.n_live;
+    f.k = R.n_kill;
+    const long long nd = acc->n_dead;
+    f.N = (nd < R.dead_cap) ? nd : R.dead_cap;
+    f.n_batch = nd - R.n_live;
+    const double n1 = f.n + 1.0, n2 = f.n + 2.0;
+    f.lk_x = log((f.n - f.k + 1.0) / n1);
+    f.lk_y = log((f.n - f.k + 1.0) * (f.n - f.k + 2.0) / (n1 * n2));
+    return f;
+}
+
+// live count, log X and log Y before record i (lg[v] = log v)
+__device__ __forceinline__ void fin_record(const FinRun &f, long long i, const double *lg, int &np,
+                                           double &lx, double &ly) {
+    long long q;
+    int r;
+    if (i < f.n_batch) {
+        q = i / f.k;
+        r = (int)(i % f.k);
+    } else {
+        q = f.n_batch / f.k;
+        r = (int)(i - f.n_batch);
+    }
+    np = f.n - r;
+    lx = (double)q * f.lk_x + (lg[f.n + 1 - r] - lg[f.n + 1]);
+    ly = (double)q * f.lk_y + (lg[f.n + 1 - r] + lg[f.n + 2 - r] - lg[f.n + 1] - lg[f.n + 2]);
+}
+
+__device__ __forceinline__ void fin_log_table(int n, double *lg) {
+    for (int v = threadIdx.x; v <= n + 2; v += blockDim.x) lg[v] = (v > 0) ? log((double)v) : -INFINITY;
+    __syncthreads();
+}
+
+// chunk totals of H and of the log-sum of c
+__global__ void __launch_bounds__(kFinThreads)
+fin_chunk_kernel(void *arena, const RunDev *__restrict__ runs) {
+    const RunDev &R = runs[blockIdx.y];
+    const Acc *acc = at<Acc>(arena, R.off_acc);
+    if (!acc->summary_pending) return;
+    const FinRun f = fin_run(R, acc);
+    const long long c0 = (long long)blockIdx.x * kFinChunk;
+    if (c0 >= f.N) return;
+    __shared__ double lg[kMaxLive + 3];
+    __shared__ double scratch[32];
+    fin_log_table(f.n, lg);
+    const double *dl = at<double>(arena, R.off_dead_logl);
+    const double *dw = at<double>(arena, R.off_dead_logw);
+    const double lz = acc->log_z;
+    const long long i0 = c0 + (long long)threadIdx.x * kFinPerThread;
+    double hpart = 0.0, cm = -INFINITY, cs = 0.0;
+    for (long long i = i0; i < i0 + kFinPerThread && i < f.N; ++i) {
+        const double lp = dl[i] + dw[i] - lz;
+        hpart += exp(lp) * (dl[i] - lz);
+        int np;
+        double lx, ly;
+        fin_record(f, i, lg, np, lx, ly);
+        lse_push(ly + dl[i] - lg[np + 2] - lx, cm, cs);
+    }
+    double *fin = at<double>(arena, R.off_fin);
+    const int nc = R.fin_chunks;
+    const double h = block_sum(hpart, scratch);
+    const double lc = block_lse(cm, cs, scratch);
+    if (threadIdx.x == 0) {
+        fin[blockIdx.x] = h;
+        fin[nc + blockIdx.x] = lc;
+    }
+}
+
+// per run: H, sigma_KL, and the exclusive log-sum-exp scan of the chunk totals
+__global__ void __launch_bounds__(kFinThreads)
+fin_scan_kernel(void *arena, const RunDev *__restrict__ runs) {
     const RunDev &R = runs[blockIdx.x];
     Acc *acc = at<Acc>(arena, R.off_acc);
     if (!acc->summary_pending) return;
-    __shared__ double lg[kMaxLive + 3];
-    __shared__ double buf[kEvThreads];
+    const FinRun f = fin_run(R, acc);
+    const int used = (int)((f.N + kFinChunk - 1) / kFinChunk);
+    const int nc = R.fin_chunks;
+    double *fin = at<double>(arena, R.off_fin);
     __shared__ double scratch[32];
-    const long long nd = acc->n_dead;
-    const long long N = (nd < R.dead_cap) ? nd : R.dead_cap;
-    const long long n_batch = nd - R.n_live;
-    run_summary(R, acc, at<double>(arena, R.off_dead_logl), at<double>(arena, R.off_dead_logw), N,
-                n_batch, lg, buf, scratch);
-    if (threadIdx.x == 0) acc->summary_pending = 0;
+    __shared__ double buf[kFinThreads];
+    const int per = (used + kFinThreads - 1) / kFinThreads;
+    const int b0 = threadIdx.x * per, b1 = (b0 + per < used) ? b0 + per : used;
+    double h = 0.0, lc = -INFINITY;
+    for (int b = b0; b < b1; ++b) {
+        h += fin[b];
+        lc = lae(lc, fin[nc + b]);
+    }
+    const double H = block_sum(h, scratch);
+    double run_lc = block_exscan_lae(lc, buf);
+    for (int b = b0; b < b1; ++b) {
+        fin[2 * nc + b] = run_lc;
+        run_lc = lae(run_lc, fin[nc + b]);
+    }
+    if (threadIdx.x == 0) {
+        acc->h = H;
+        acc->sigma_kl = sqrt(H > 0.0 ? H / f.n : 0.0);
+    }
+}
+
+// chunk totals of Z2 and Zr, each thread starting from its exclusive S
+__global__ void __launch_bounds__(kFinThreads)
+fin_moment_kernel(void *arena, const RunDev *__restrict__ runs) {
+    const RunDev &R = runs[blockIdx.y];
+    const Acc *acc = at<Acc>(arena, R.off_acc);
+    if (!acc->summary_pending) return;
+    const FinRun f = fin_run(R, acc);
+    const long long c0 = (long long)blockIdx.x * kFinChunk;
+    if (c0 >= f.N) return;
+    __shared__ double lg[kMaxLive + 3];
+    __shared__ double scratch[32];
+    __shared__ double buf[kFinThreads];
+    fin_log_table(f.n, lg);
+    const double *dl = at<double>(arena, R.off_dead_logl);
+    const long long i0 = c0 + (long long)threadIdx.x * kFinPerThread;
+    const long long i1 = (i0 + kFinPerThread < f.N) ? i0 + kFinPerThread : f.N;
+    // this thread's log-sum of c, then its exclusive prefix within the run
+    double cm = -INFINITY, cs = 0.0;
+    for (long long i = i0; i < i1; ++i) {
+        int np;
+        double lx, ly;
+        fin_record(f, i, lg, np, lx, ly);
+        lse_push(ly + dl[i] - lg[np + 2] - lx, cm, cs);
+    }
+    const double lc_local = (cm == -INFINITY) ? -INFINITY : cm + log(cs);
+    const double *fin_c = at<double>(arena, R.off_fin);
+    const int nc = R.fin_chunks;
+    const double lsum = lae(fin_c[2 * nc + blockIdx.x], block_exscan_lae(lc_local, buf));
+    double am = -INFINITY, as = 0.0, zm = -INFINITY, zs = 0.0;
+    double sm = lsum, ss = (lsum == -INFINITY) ? 0.0 : 1.0;   // running S as (sm, ss)
+    const double l2 = 0.69314718055994530942;
+    for (long long i = i0; i < i1; ++i) {
+        int np;
+        double x, y;
+        fin_record(f, i, lg, np, x, y);
+        const double ln1 = lg[np + 1], ln2 = lg[np + 2];
+        const double ls = (sm == -INFINITY) ? -INFINITY : sm + log(ss);
+        lse_push(l2 + x + ls + dl[i] - ln1, am, as);
+        lse_push(l2 + y + 2.0 * dl[i] - ln1 - ln2, am, as);
+        lse_push(x + dl[i] - ln1, zm, zs);
+        lse_push(y + dl[i] - ln2 - x, sm, ss);
+    }
+    const double lz2 = block_lse(am, as, scratch);
+    const double lzr = block_lse(zm, zs, scratch);
+    if (threadIdx.x == 0) {
+        double *fin = at<double>(arena, R.off_fin);
+        fin[3 * nc + blockIdx.x] = lz2;
+        fin[4 * nc + blockIdx.x] = lzr;
+    }
+}
+
+// per run: log Z2 and sigma_mom from the chunk totals; the summary is done
+__global__ void __launch_bounds__(kFinThreads)
+fin_total_kernel(void *arena, const RunDev *__restrict__ runs) {
+    const RunDev &R = runs[blockIdx.x];
+    Acc *acc = at<Acc>(arena, R.off_acc);
+    if (!acc->summary_pending) return;
+    const FinRun f = fin_run(R, acc);
+    const int used = (int)((f.N + kFinChunk - 1) / kFinChunk);
+    const int nc = R.fin_chunks;
+    const double *fin = at<double>(arena, R.off_fin);
+    __shared__ double scratch[32];
+    double m2 = -INFINITY, s2 = 0.0, mr = -INFINITY, sr = 0.0;
+    for (int b = threadIdx.x; b < used; b += blockDim.x) {
+        lse_push(fin[3 * nc + b], m2, s2);
+        lse_push(fin[4 * nc + b], mr, sr);
+    }
+    const double lz2 = block_lse(m2, s2, scratch);
+    const double lzr = block_lse(mr, sr, scratch);
+    if (threadIdx.x == 0) {
+        acc->log_z2 = R.cluster_mode ? -INFINITY : lz2;
+        const double v = lz2 - 2.0 * lzr;
+        acc->sigma_mom = R.cluster_mode ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
+        acc->summary_pending = 0;
+    }
 }
 
 }  // namespace
 
-void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(n_runs), dim3(kEvThreads), 0, s, arena, runs_dev);
+void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, int max_chunks, hipStream_t s) {
+    const dim3 chunks((unsigned)max_chunks, (unsigned)n_runs);
+    hipLaunchKernelGGL(fin_chunk_kernel, chunks, dim3(kFinThreads), 0, s, arena, runs_dev);
+    hipLaunchKernelGGL(fin_scan_kernel, dim3(n_runs), dim3(kFinThreads), 0, s, arena, runs_dev);
+    hipLaunchKernelGGL(fin_moment_kernel, chunks, dim3(kFinThreads), 0, s, arena, runs_dev);
+    hipLaunchKernelGGL(fin_total_kernel, dim3(n_runs), dim3(kFinThreads), 0, s, arena, runs_dev);
 }
 
 void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_sweep,
-                     hipStream_t s) {
+                     int any_cluster, hipStream_t s) {
     hipLaunchKernelGGL(evidence_kernel, dim3(n_runs), dim3(kEvThreads), 0, s, arena, runs_dev,
                        final_sweep);
+    if (any_cluster)
+        hipLaunchKernelGGL(cluster_group_kernel, dim3(n_runs), dim3(kEvThreads), 0, s, arena, runs_dev);
 }
 
 }  // namespace ggns

@@ -47,8 +47,13 @@ struct RunDev {
     int32_t cluster_mode, cluster_kmax;
     int64_t off_label, off_cltab, off_members, off_knn, off_start_cl;
     int64_t off_knn_part, off_knn_part_s;   // per query and share: partial neighbour lists
+    int64_t off_fin;           // run summary: five FP64 partials per chunk of dead records
+    int32_t fin_chunks, pad_fin;   // chunks of kFinChunk records covering dead_cap
 };
 
+constexpr int kFinThreads = 256;                      // run summary: threads per chunk
+constexpr int kFinPerThread = 16;                     // records per thread
+constexpr int kFinChunk = kFinThreads * kFinPerThread; // records per chunk (one workgroup)
 constexpr int kClMax = 64;      // clusters per run
 constexpr int kKnnMax = 8;      // neighbours kept per point (largest cluster_kmax)
 constexpr int kKnnSplit = 16;   // shares of the candidate range searched in parallel
@@ -88,8 +93,8 @@ void launch_prepare(void *arena, const RunDev *runs_dev, int n_runs, const doubl
 int launch_init_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int prec,
                       int C, int kind, hipStream_t s);
 void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_sweep,
-                     hipStream_t s);
-void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, hipStream_t s);
+                     int any_cluster, hipStream_t s);
+void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, int max_chunks, hipStream_t s);
 void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s);
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
                       int prec, int C, int kind, size_t lds_bytes, hipStream_t s);

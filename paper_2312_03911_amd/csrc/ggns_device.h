@@ -565,6 +565,106 @@ __host__ __device__ inline int64_t converted_size(int var, int d, int dp) {
 // Run-level helpers shared by the evidence and cluster kernels.
 // ---------------------------------------------------------------------------
 
+// Bitonic sort of 1024 E (key, slot) pairs by a workgroup of 1024 threads, E
+// per thread (element i = E t + e of thread t), ascending by key and then slot.  Compare-exchange stages of
+// stride below E stay inside the thread; strides E .. 32 E pair lanes
+// stride / E apart in the same wavefront (DPP for 1 and 2 lanes, ds_swizzle
+// up to 16, a lane permute for 32); strides of 64 E and more cross wavefronts
+// through LDS between two barriers.  The order is total (slots are distinct;
+// the padding entries are all equal), so the sorted sequence is unique.
+template <int X>
+__device__ __forceinline__ int xor_lanes(int v) {
+    if constexpr (X == 1) return __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false);
+    else if constexpr (X == 2) return __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false);
+    else if constexpr (X <= 16) return __builtin_amdgcn_ds_swizzle(v, (X << 10) | 0x1F);
+    else return __shfl_xor(v, X, 64);
+}
+
+__device__ __forceinline__ bool kv_greater(unsigned long long ka, int sa, unsigned long long kb,
+                                           int sb) {
+    return (ka > kb) | ((ka == kb) & (sa > sb));
+}
+
+// This lane's pair against the lane X away: keep the smaller when keep_min.
+template <int X>
+__device__ __forceinline__ void lane_cas(unsigned long long &k, int &s, bool keep_min) {
+    const int lo = xor_lanes<X>((int)(unsigned)k);
+    const int hi = xor_lanes<X>((int)(unsigned)(k >> 32));
+    const int so = xor_lanes<X>(s);
+    const unsigned long long ko = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    const bool gt = kv_greater(k, s, ko, so);
+    const bool take = keep_min ? gt : !gt;
+    k = take ? ko : k;
+    s = take ? so : s;
+}
+
+template <int E>
+__device__ inline void sort_pairs(unsigned long long (&k)[E], int (&s)[E], unsigned long long *lk, int *ls) {
+    constexpr int N = 1024 * E;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= 64 * E) {
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    lk[E * t + e] = k[e];
+                    ls[E * t + e] = s[e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = E * t + e, j = i ^ stride;
+                    const unsigned long long kb = lk[j];
+                    const int sb = ls[j];
+                    const bool keep_min = ((i & size) == 0) == ((i & stride) == 0);
+                    const bool gt = kv_greater(k[e], s[e], kb, sb);
+                    const bool take = keep_min ? gt : !gt;
+                    k[e] = take ? kb : k[e];
+                    s[e] = take ? sb : s[e];
+                }
+            } else if (stride >= E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = E * t + e;
+                    const bool keep_min = ((i & size) == 0) == ((i & stride) == 0);
+                    switch (stride / E) {
+                        case 1: lane_cas<1>(k[e], s[e], keep_min); break;
+                        case 2: lane_cas<2>(k[e], s[e], keep_min); break;
+                        case 4: lane_cas<4>(k[e], s[e], keep_min); break;
+                        case 8: lane_cas<8>(k[e], s[e], keep_min); break;
+                        case 16: lane_cas<16>(k[e], s[e], keep_min); break;
+                        default: lane_cas<32>(k[e], s[e], keep_min); break;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (e & stride) continue;
+                    const int f = e | stride;
+                    const bool asc = ((E * t + e) & size) == 0;
+                    const bool sw = kv_greater(k[e], s[e], k[f], s[f]) == asc;
+                    const unsigned long long ka = k[e];
+                    const int sa = s[e];
+                    k[e] = sw ? k[f] : k[e];
+                    s[e] = sw ? s[f] : s[e];
+                    k[f] = sw ? ka : k[f];
+                    s[f] = sw ? sa : s[f];
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        lk[E * t + e] = k[e];
+        ls[E * t + e] = s[e];
+    }
+    __syncthreads();
+}
+
 // Maximum over a workgroup of up to 1024 threads (barriers inside).
 __device__ inline double block_max_d(double v, double *scratch) {
     for (int o = 32; o > 0; o >>= 1) {

@@ -229,14 +229,22 @@ __global__ void replace_kernel(void *arena, const RunDev *__restrict__ runs) {
     double *ll = at<double>(arena, R.off_live_logl);
     for (int64_t m = e0; m < R.n_kill; m += stride) ll[killed[m]] = wl[m];
     if (R.cluster_mode) {
-        // the new point joins the cluster its walker was spawned in
+        // the new point joins the cluster its walker was spawned in; the
+        // workgroup counts its joins in LDS and adds them with one atomic per
+        // cluster
+        __shared__ int joins[kClMax];
         int32_t *label = at<int32_t>(arena, R.off_label);
         const int32_t *scl = at<int32_t>(arena, R.off_start_cl);
         ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
+        for (int p = threadIdx.x; p < kClMax; p += blockDim.x) joins[p] = 0;
+        __syncthreads();
         for (int64_t m = e0; m < R.n_kill; m += stride) {
             label[killed[m]] = scl[m];
-            atomicAdd(&tab->cn[scl[m]], 1);
+            atomicAdd(&joins[scl[m]], 1);
         }
+        __syncthreads();
+        for (int p = threadIdx.x; p < kClMax; p += blockDim.x)
+            if (joins[p] != 0) atomicAdd(&tab->cn[p], joins[p]);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long st = acc->it_steps;
