@@ -54,11 +54,17 @@ def _group_key(cfg: RunConfig) -> Tuple:
     return (cfg.kind, cfg.precision, cfg.d, cfg.n_comp, cfg.max_ref, cfg.n_steps_max)
 
 
-def _time_walk(cfgs: Sequence[RunConfig], c: int, warm: int, reps: int, device: str) -> float:
+def _time_walk(cfgs: Sequence[RunConfig], c, warm: int, reps: int, device: str,
+               allow_ended: bool = False):
+    """Mean walk launch time (ms) after `warm` iterations with tile shape `c`
+    (one for all runs, or a list), or None when a run ends before the timed
+    walks are over (nothing comparable to time) unless allow_ended."""
     import torch
 
+    from . import _lib
     from .engine import Engine
-    eng = Engine(cfgs, device=device, tile_c=[c] * len(cfgs))
+    tiles = list(c) if isinstance(c, (list, tuple)) else [c] * len(cfgs)
+    eng = Engine(cfgs, device=device, tile_c=tiles)
     eng.iterate(warm)
     stream = torch.cuda.current_stream(eng.device)
     t = 0.0
@@ -72,13 +78,20 @@ def _time_walk(cfgs: Sequence[RunConfig], c: int, warm: int, reps: int, device: 
         eng.replace_dead()
         b.synchronize()
         t += a.elapsed_time(b)
+    ended = any(s["state"] != _lib.RUN_ACTIVE for s in eng.stats())
     eng.close()
-    return t / reps
+    return None if (ended and not allow_ended) else t / reps
 
 
 def tune(configs: Sequence[RunConfig], device: str = "cuda", warm: int = 2, reps: int = 3,
-         verbose: bool = False) -> List[int]:
-    """Coordinates per lane for every run of the batch (0 = library default)."""
+         verbose: bool = False, warm_reflect: int = 30) -> List[int]:
+    """Coordinates per lane for every run of the batch (0 = library default).
+
+    Fixed-step groups are timed after `warm` iterations.  Reflection-mode groups
+    (max_ref > 0) are timed after `warm_reflect`: in their first iterations the
+    step is still far too large, every walker meets its reflections within a
+    few steps, and walks of that length favour other tile shapes than the
+    adapted walks that make up the run."""
     groups: Dict[Tuple, List[int]] = {}
     for i, c in enumerate(configs):
         groups.setdefault(_group_key(c), []).append(i)
@@ -91,11 +104,26 @@ def tune(configs: Sequence[RunConfig], device: str = "cuda", warm: int = 2, reps
             if len(cands) <= 1:
                 _CACHE[ckey] = cands[0] if cands else 0
             else:
-                times = {c: _time_walk(sub, c, warm, reps, device) for c in cands}
-                _CACHE[ckey] = min(times, key=times.get)
+                w = warm if sub[0].max_ref == 0 else max(warm, warm_reflect)
+                times = {c: _time_walk(sub, c, w, reps, device) for c in cands}
+                if any(t is None for t in times.values()):
+                    _CACHE[ckey] = 0    # runs too short to time: the library default
+                else:
+                    _CACHE[ckey] = min(times, key=times.get)
                 if verbose:
-                    print("autotune", key, {c: round(t, 4) for c, t in times.items()},
+                    print("autotune", key, {c: (None if t is None else round(t, 4)) for c, t in times.items()},
                           "->", _CACHE[ckey], flush=True)
         for i in idx:
             choice[i] = _CACHE[ckey]
+    if len(groups) > 1 and any(choice):
+        # the groups were timed alone; in the batch their walks share the chip,
+        # where fewer, fuller wavefronts can win.  Keep the per-group choices
+        # only if the whole batch walks faster with them than with the defaults
+        w = warm if all(c.max_ref == 0 for c in configs) else max(warm, warm_reflect)
+        t_tuned = _time_walk(configs, choice, w, reps, device, allow_ended=True)
+        t_default = _time_walk(configs, [0] * len(configs), w, reps, device, allow_ended=True)
+        if verbose:
+            print("autotune batch: tuned", t_tuned, "default", t_default, flush=True)
+        if t_default <= 1.02 * t_tuned:
+            return [0] * len(configs)
     return choice
