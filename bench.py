@@ -54,6 +54,11 @@ def workload(name: str):
         return inputs.replicate(inputs.config_shells(d=32, n_live=1000), 10, base_seed=2200)
     if name == "shells32":
         return [inputs.config_shells(d=32, n_live=1000)]
+    if name == "shells32x100":
+        # the same problem, 100 seeded runs in one batch: 50,000 walkers, enough
+        # wavefronts to fill every SIMD several times over (the batched form at
+        # full occupancy; the default keeps the paper's 10-run protocol)
+        return inputs.replicate(inputs.config_shells(d=32, n_live=1000), 100, base_seed=2200)
     if name == "gauss2d":
         return [inputs.config_gauss2d()]
     if name == "gauss2dx10":

@@ -18,8 +18,10 @@ namespace {
 
 constexpr int kEvThreads = 1024;
 
+// Order-preserving 64-bit key of a log L.  -0 and +0 compare equal (a tie,
+// broken by slot like any other), so -0 takes the key of +0.
 __device__ __forceinline__ unsigned long long order_key(double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v == 0.0 ? 0.0 : v);
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 __device__ __forceinline__ double key_value(unsigned long long k) {

@@ -238,3 +238,42 @@ def test_gauss2d_fp64_full_run_matches_oracle(torch, orc, term_kind):
         np.testing.assert_allclose(_np(dl), ol, rtol=1e-10, atol=1e-10)
         np.testing.assert_allclose(_np(dw), ow, rtol=1e-12, atol=1e-11)
         eng.close()
+
+
+KILL_SIZES = [(4096, 2048, 8), (4096, 1, 3), (4095, 4094, 2), (2049, 1024, 5), (2048, 1000, 1),
+              (1537, 1536, 3), (1025, 512, 2), (1024, 512, 4), (7, 3, 2), (2, 1, 1)]
+
+
+@pytest.mark.parametrize("n,k,d", KILL_SIZES, ids=[f"n{n}_k{k}_d{d}" for n, k, d in KILL_SIZES])
+def test_kill_order_at_edge_sizes(torch, orc, n, k, d):
+    """The kill step on identical live sets (positions and FP64 log L loaded on
+    both sides, with exact ties among them): killed slots in kill order,
+    survivors, threshold, evidence and volume match the oracle exactly at the
+    largest live set, at every register layout of the sort (1, 2 and 4 keys per
+    thread) and at ragged, tiny and extreme kill counts."""
+    cfg = inputs.RunConfig(kind="gauss_diag", d=d, n_live=n, n_kill=k, lo=-3.0, hi=3.0,
+                           precision="fp64", seed=40 + n + k,
+                           params=inputs.gauss_diag_params(np.zeros(d), np.ones(d)))
+    X = inputs.uniform_points(n, d, cfg.lo, cfg.hi, seed=n + 3 * k)
+    rng = np.random.default_rng(n * 7 + k)
+    L = np.round(rng.normal(-5.0, 2.0, size=n), 1)          # many exact ties
+    eng = _engine([cfg])
+    eng.live_x(0).copy_(torch.from_numpy(X).to(eng.device))
+    eng.live_logl(0).copy_(torch.from_numpy(L).to(eng.device))
+    eng.write_vars(0, -math.inf, 0.0, 0.1, 0)
+    o = orc.Oracle(cfg).init()
+    o.set_state(live_x=X, live_logl=L, log_z=-math.inf, log_x=0.0, dt=0.1, iteration=0)
+    eng.evidence_update()
+    o.evidence_update()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
+    np.testing.assert_array_equal(_np(eng.survivors(0)), o.surv[:n - k])
+    st = eng.stats()[0]
+    assert st["lstar"] == o.st.lstar
+    assert abs(st["log_z"] - o.st.lz) < 1e-12 * max(1.0, abs(o.st.lz))
+    assert abs(st["log_x"] - o.st.lx) < 1e-13
+    dl, dw = eng.dead(0)
+    ol, ow = o.dead()
+    np.testing.assert_array_equal(_np(dl), ol)
+    np.testing.assert_allclose(_np(dw), ow, rtol=1e-13, atol=1e-13)
+    eng.close()
