@@ -121,45 +121,50 @@ def test_mma_walk_shapes_match_oracle(torch, orc, d, waves):
     _trace_check(torch, orc, cfg, 1e-4, 1e-4, tile_c=[waves], steps=12)
 
 
-def _trace_check(torch, orc, cfg, tol, tau, tile_c=None, steps=20):
-    T = steps
-    eng = _engine([cfg], tile_c)
-    if tile_c is not None:
-        c, g = eng.tile_shape(0)
-        assert g == (4 * tile_c[0] if cfg.precision == "bf16mma" else g)
-    o = orc.Oracle(cfg, trace_steps=T).init()
+def _trace_state(cfg):
+    """Start state of a trace check: uniform points at the first iteration's
+    step; for the shells a mid-run state instead (points around both shells
+    and the step the run has adapted to by then: at the first iteration's step,
+    0.1 of the prior width times |p| ~ sqrt(d), the thin shell is a strongly
+    chaotic billiard where each bounce multiplies the FP32-vs-FP64 difference
+    several fold, which no short-walk tolerance can absorb)."""
     if cfg.kind == "shells":
-        # a mid-run state: points around both shells and the step the run has
-        # adapted to by then.  (At the first iteration's step, 0.1 of the prior
-        # width times |p| ~ sqrt(d), the thin shell is a strongly chaotic
-        # billiard: each bounce multiplies the FP32-vs-FP64 difference several
-        # fold, which no short-walk tolerance can absorb.)
         rng = np.random.default_rng(99)
         v = rng.standard_normal((cfg.n_live, cfg.d))
         v /= np.linalg.norm(v, axis=1, keepdims=True)
         X = v * rng.uniform(1.7, 2.3, size=(cfg.n_live, 1))
         X[:, 0] += np.where(np.arange(cfg.n_live) % 2 == 0, 3.5, -3.5)
-        dt = 0.005 * (cfg.hi - cfg.lo)
-    else:
-        X = inputs.uniform_points(cfg.n_live, cfg.d, cfg.lo, cfg.hi, seed=99)
-        dt = cfg.dt_init * (cfg.hi - cfg.lo)
-    Xo = _load_state(torch, eng, o, 0, X)
-    eng.write_vars(0, -math.inf, 0.0, dt, 0)
+        return X, 0.005 * (cfg.hi - cfg.lo)
+    return inputs.uniform_points(cfg.n_live, cfg.d, cfg.lo, cfg.hi, seed=99), cfg.dt_init * (cfg.hi - cfg.lo)
+
+
+def _prepare_trace(torch, eng, orc, r, T):
+    """Load the trace start state of run r into the engine and a fresh oracle;
+    record T steps of every walker of run r on the GPU."""
+    cfg = eng.cfgs[r]
+    o = orc.Oracle(cfg, trace_steps=T).init()
+    X, dt = _trace_state(cfg)
+    _load_state(torch, eng, o, r, X)
+    eng.write_vars(r, -math.inf, 0.0, dt, 0)
     o.set_state(dt=dt)
-    tx, tl, to = eng.set_trace(0, T)
-    eng.evidence_update()
-    o.evidence_update()
-    torch.cuda.synchronize()
-    np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
-    np.testing.assert_array_equal(_np(eng.survivors(0)), o.surv[:cfg.n_live - cfg.n_kill])
-    st = eng.stats()[0]
+    return o, eng.set_trace(r, T)
+
+
+def _compare_trace(torch, orc, eng, r, o, trace, tol, tau):
+    """After the kill and the walk: kill order, survivors, threshold, evidence,
+    starts exactly; per-step positions within tol relative (walkers masked from
+    the first step at which a floating-point decision is within tau of its
+    boundary), outside flags exactly, log L at the GPU's positions against the
+    oracle's likelihood."""
+    cfg = eng.cfgs[r]
+    tx, tl, to = trace
+    np.testing.assert_array_equal(_np(eng.killed(r)), o.killed)
+    np.testing.assert_array_equal(_np(eng.survivors(r)), o.surv[:cfg.n_live - cfg.n_kill])
+    st = eng.stats()[r]
     assert abs(st["lstar"] - o.st.lstar) <= tau * max(1.0, abs(o.st.lstar))
     assert abs(st["log_z"] - o.st.lz) < (1e-12 if tol < 1e-6 else 2e-5) * max(1.0, abs(o.st.lz))
     assert abs(st["log_x"] - o.st.lx) < 1e-13
-    eng.hss_walk()
-    o.hss_walk()
-    torch.cuda.synchronize()
-    np.testing.assert_array_equal(_np(eng.start(0)), o.start)
+    np.testing.assert_array_equal(_np(eng.start(r)), o.start)
     gx, gl, go = _np(tx).astype(np.float64), _np(tl), _np(to)
     width = cfg.hi - cfg.lo
     lstar = o.st.lstar
@@ -189,6 +194,58 @@ def _trace_check(torch, orc, cfg, tol, tau, tile_c=None, steps=20):
     assert worst < tol, worst
     assert masked <= max(2, 0.02 * cfg.n_kill), masked
     assert compared >= 0.9 * cfg.n_kill
+
+
+def _trace_check(torch, orc, cfg, tol, tau, tile_c=None, steps=20):
+    eng = _engine([cfg], tile_c)
+    if tile_c is not None:
+        c, g = eng.tile_shape(0)
+        assert g == (4 * tile_c[0] if cfg.precision == "bf16mma" else g)
+    o, trace = _prepare_trace(torch, eng, orc, 0, steps)
+    eng.evidence_update()
+    o.evidence_update()
+    torch.cuda.synchronize()
+    eng.hss_walk()
+    o.hss_walk()
+    torch.cuda.synchronize()
+    _compare_trace(torch, orc, eng, 0, o, trace, tol, tau)
+    eng.close()
+
+
+# the configurations bench.py times, at their full sizes
+FULL = [
+    ("shells32_n1000_fp32", lambda: inputs.config_shells(d=32, n_live=1000, seed=50), 1e-4, 1e-4),
+    ("gmm64_n4000_fp32", lambda: inputs.config_gmm(seed=51), 1e-4, 1e-4),
+    ("corr256_n2000_bf16", lambda: inputs.config_corr_gauss(seed=52), 1e-4, 1e-4),
+]
+
+
+@pytest.mark.parametrize("name,make,tol,tau", FULL, ids=[c[0] for c in FULL])
+def test_full_size_walk_trace_matches_oracle(torch, orc, name, make, tol, tau):
+    _trace_check(torch, orc, make(), tol, tau, steps=10)
+
+
+def test_batch64_sampled_runs_match_oracle(torch, orc):
+    """The 64-run batch in one launch per kernel (every walk class on its own
+    stream, as bench.py times it): three of its runs, one of each family, follow
+    the oracle step by step while the other 61 walk beside them."""
+    cfgs = inputs.config_batch()
+    eng = _engine(cfgs)
+    picks = {}
+    for r, c in enumerate(cfgs):
+        picks.setdefault(c.kind, r)
+    checks = {r: _prepare_trace(torch, eng, orc, r, 10) for r in picks.values()}
+    eng.evidence_update()
+    for o, _ in checks.values():
+        o.evidence_update()
+    torch.cuda.synchronize()
+    eng.hss_walk()
+    for o, _ in checks.values():
+        o.hss_walk()
+    torch.cuda.synchronize()
+    for r, (o, trace) in checks.items():
+        _compare_trace(torch, orc, eng, r, o, trace, 1e-4, 1e-4)
+    eng.close()
 
 
 @pytest.mark.parametrize("name,make,tol,tau", CASES, ids=[c[0] for c in CASES])
