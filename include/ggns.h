@@ -259,6 +259,36 @@ int ggns_loglike_vjp(ggns_ctx *ctx, int32_t run, const void *x_dev, int64_t n,
  * initialised) is scratch for the duration of the call.  Synchronises `stream`
  * (it polls), so it cannot be captured in a graph. */
 int64_t ggns_plain_workspace_bytes(const ggns_ctx *ctx);
+
+/* The walk with a likelihood the caller evaluates (for likelihoods written in a
+ * framework with automatic differentiation, the setting Section 3 describes:
+ * the gradient comes from differentiable programming).  Same method, streams,
+ * readings and outputs as ggns_hss_walk_plain, for one FP64 run, with every
+ * step split at the likelihood:
+ *   ggns_ext_begin    gathers the starts, draws the momenta and stream seeds
+ *                     and drifts every walker once (x = x_start + dt p0);
+ *   the caller        evaluates, for every walker m, log L and its gradient
+ *                     at x[:, m] into logl[m] and grad[:, m];
+ *   ggns_ext_step(t)  takes step t (outside test, reflection, noise, kept
+ *                     point, pruning, stop) and drifts the walkers that go on;
+ *                     active[t] counts them;
+ * until active[t] is 0 or t reaches n_steps_max - 1.  The walker outputs then
+ * sit where ggns_replace_dead reads them.  Buffers live in the caller's device
+ * workspace (256-byte aligned, at least ggns_ext_workspace_bytes(ctx, run),
+ * contents need not be initialised; the same workspace for the whole walk):
+ * ggns_ext_buffers returns x [d][n_kill] and grad [d][n_kill] (component-major,
+ * walker m in column m), logl [n_kill] and active [n_steps_max], all double but
+ * active (int32).  The live set's log L must come from the same likelihood
+ * (write it over the live_logl section after ggns_init); the run's likelihood
+ * family in its descriptor is then unused.  A run that is not GGNS_FP64 gives
+ * GGNS_EUNSUPPORTED.  All calls are asynchronous on `stream`. */
+int64_t ggns_ext_workspace_bytes(const ggns_ctx *ctx, int32_t run);
+int ggns_ext_buffers(const ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t workspace_bytes,
+                     double **x_dev, double **logl_dev, double **grad_dev, int32_t **active_dev);
+int ggns_ext_begin(ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t workspace_bytes,
+                   void *stream);
+int ggns_ext_step(ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t workspace_bytes,
+                  int32_t step, void *stream);
 int ggns_hss_walk_plain(ggns_ctx *ctx, void *workspace_dev, int64_t workspace_bytes, void *stream);
 
 int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out);

@@ -18,7 +18,8 @@ SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update
            "ggns_hss_walk", "ggns_replace_dead", "ggns_loglike_grad", "ggns_loglike_vjp",
            "ggns_run_layout", "ggns_read_stats", "ggns_read_stats_async", "ggns_write_vars",
            "ggns_set_trace", "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
-           "ggns_noise_normals", "ggns_set_dead_x", "ggns_free", "ggns_status_string")
+           "ggns_noise_normals", "ggns_set_dead_x", "ggns_ext_workspace_bytes", "ggns_ext_buffers",
+           "ggns_ext_begin", "ggns_ext_step", "ggns_free", "ggns_status_string")
 
 
 class ggns_run_desc(C.Structure):
@@ -102,6 +103,15 @@ def load() -> C.CDLL:
         L.ggns_noise_normals.restype = C.c_int
         L.ggns_set_dead_x.argtypes = [vp, i32, vp, i64]
         L.ggns_set_dead_x.restype = C.c_int
+        L.ggns_ext_workspace_bytes.argtypes = [vp, i32]
+        L.ggns_ext_workspace_bytes.restype = i64
+        dpp = C.POINTER(C.c_void_p)
+        L.ggns_ext_buffers.argtypes = [vp, i32, vp, i64, dpp, dpp, dpp, dpp]
+        L.ggns_ext_buffers.restype = C.c_int
+        L.ggns_ext_begin.argtypes = [vp, i32, vp, i64, vp]
+        L.ggns_ext_begin.restype = C.c_int
+        L.ggns_ext_step.argtypes = [vp, i32, vp, i64, i32, vp]
+        L.ggns_ext_step.restype = C.c_int
         L.ggns_free.argtypes = [vp]
         L.ggns_free.restype = None
         L.ggns_status_string.argtypes = [C.c_int]

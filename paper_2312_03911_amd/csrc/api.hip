@@ -423,6 +423,50 @@ int ggns_hss_walk_plain(ggns_ctx *ctx, void *workspace_dev, int64_t workspace_by
     return GGNS_OK;
 }
 
+namespace {
+int ext_check(const ggns_ctx *ctx, int32_t run, const void *ws, int64_t bytes) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size()) return GGNS_EINVAL;
+    if (ctx->plan.runs[run].prec != GGNS_FP64) return GGNS_EUNSUPPORTED;
+    if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 ||
+        bytes < plain_workspace_bytes(ctx->plan.runs[run]))
+        return GGNS_EINVAL;
+    return GGNS_OK;
+}
+}  // namespace
+
+int64_t ggns_ext_workspace_bytes(const ggns_ctx *ctx, int32_t run) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (run < 0 || run >= (int)ctx->plan.runs.size()) return GGNS_EINVAL;
+    return plain_workspace_bytes(ctx->plan.runs[run]);
+}
+
+int ggns_ext_buffers(const ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t workspace_bytes,
+                     double **x_dev, double **logl_dev, double **grad_dev, int32_t **active_dev) {
+    const int rc = ext_check(ctx, run, workspace_dev, workspace_bytes);
+    if (rc != GGNS_OK) return rc;
+    if (!x_dev || !logl_dev || !grad_dev || !active_dev) return GGNS_EINVAL;
+    ext_buffers(ctx->plan.runs[run], workspace_dev, x_dev, logl_dev, grad_dev, active_dev);
+    return GGNS_OK;
+}
+
+int ggns_ext_begin(ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t workspace_bytes,
+                   void *stream) {
+    const int rc = ext_check(ctx, run, workspace_dev, workspace_bytes);
+    if (rc != GGNS_OK) return rc;
+    return launch_ext_begin(ctx->arena, ctx->runs_dev(), run, ctx->plan.runs[run], workspace_dev,
+                            reinterpret_cast<hipStream_t>(stream));
+}
+
+int ggns_ext_step(ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t workspace_bytes,
+                  int32_t step, void *stream) {
+    const int rc = ext_check(ctx, run, workspace_dev, workspace_bytes);
+    if (rc != GGNS_OK) return rc;
+    if (step < 0 || step >= ctx->plan.runs[run].n_steps_max) return GGNS_EINVAL;
+    return launch_ext_step(ctx->arena, ctx->runs_dev(), run, ctx->plan.runs[run], workspace_dev, step,
+                           reinterpret_cast<hipStream_t>(stream));
+}
+
 int ggns_replace_dead(ggns_ctx *ctx, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
     launch_replace(ctx->arena, ctx->runs_dev(), (int)ctx->plan.runs.size(), ctx->max_kd,

@@ -266,6 +266,23 @@ __device__ __forceinline__ int uf_root(volatile int *par, int i) {
 
 }  // namespace
 
+// (cluster << 12 | slot) of the component roots of stopped clusters, the rest
+// above every key, sorted into key[] (1024 E entries)
+template <int E>
+__device__ void sort_roots(int n, const int *label, const int *par, const int *stopped,
+                           unsigned long long *key, int *slot) {
+    unsigned long long k[E];
+    int s[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = E * threadIdx.x + e;
+        k[e] = (i < n && stopped[label[i]] && par[i] == i)
+                   ? (((unsigned long long)label[i] << 12) | (unsigned long long)i) : ~0ull;
+        s[e] = 0;
+    }
+    sort_pairs<E>(k, s, key, slot);
+}
+
 // One workgroup per run: components for k = 1, 2, ... neighbours, the stop
 // rule per cluster, and the splits.
 __global__ void __launch_bounds__(kClThreads)
@@ -282,7 +299,8 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
     __shared__ int ccount[kClMax];
     __shared__ int changed;
     __shared__ int label[kMaxLive];
-    __shared__ uint32_t rkey[kMaxLive];
+    __shared__ unsigned long long rkey[kMaxLive];
+    __shared__ int rslot[kMaxLive];
     __shared__ int fpos[kClMax];
     const int n = R.n_live, t = threadIdx.x, T = blockDim.x;
     int32_t *label_g = at<int32_t>(arena, R.off_label);
@@ -341,34 +359,21 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
     // roots of the stopped clusters in ascending slot order: a sort of
     // (cluster << 12 | slot) keys of the roots, then per-cluster runs
     {
-        int NP = 1;
-        while (NP < n) NP <<= 1;
-        for (int i = t; i < NP; i += T)
-            rkey[i] = (i < n && stopped[label[i]] && par[i] == i)
-                          ? ((uint32_t)label[i] << 12) | (uint32_t)i : 0xFFFFFFFFu;
-        for (int size = 2; size <= NP; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                __syncthreads();
-                for (int i = t; i < (NP >> 1); i += T) {
-                    const int lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
-                    const bool asc = (lo & size) == 0;
-                    const uint32_t a = rkey[lo], b = rkey[hi];
-                    if ((a > b) == asc) { rkey[lo] = b; rkey[hi] = a; }
-                }
-            }
-        }
-        __syncthreads();
+        const int NP = (n <= 1024) ? 1024 : (n <= 2048 ? 2048 : 4096);   // entries sorted
+        if (n <= 1024) sort_roots<1>(n, label, par, stopped, rkey, rslot);
+        else if (n <= 2048) sort_roots<2>(n, label, par, stopped, rkey, rslot);
+        else sort_roots<4>(n, label, par, stopped, rkey, rslot);
         for (int j = t; j < n; j += T) {
-            const uint32_t kj = rkey[j];
-            if (kj == 0xFFFFFFFFu) continue;
+            const unsigned long long kj = rkey[j];
+            if (kj == ~0ull) continue;
             const int p = (int)(kj >> 12);
             if (j == 0 || (int)(rkey[j - 1] >> 12) != p) fpos[p] = j;
             if (j + 1 == NP || (int)(rkey[j + 1] >> 12) != p) nroot[p] = j + 1;   // end, for now
         }
         __syncthreads();
         for (int j = t; j < n; j += T) {
-            const uint32_t kj = rkey[j];
-            if (kj == 0xFFFFFFFFu) continue;
+            const unsigned long long kj = rkey[j];
+            if (kj == ~0ull) continue;
             const int p = (int)(kj >> 12), r = j - fpos[p];
             if (r < kClMax) roots[p][r] = (int)(kj & 0xFFFu);
         }

@@ -104,6 +104,12 @@ int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int
 int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, const void *x,
                    int64_t n, double *logl, void *grad, const double *gout, hipStream_t s);
 int64_t plain_workspace_bytes(const RunDev &R);
+int launch_ext_begin(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws,
+                     hipStream_t s);
+int launch_ext_step(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws, int t,
+                    hipStream_t s);
+void ext_buffers(const RunDev &R, void *ws, double **x, double **logl, double **grad,
+                 int32_t **active);
 int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws,
                       int poll_every, hipStream_t s);
 int launch_noise_normals(uint64_t seed, int iteration, int n_walkers, int n_blocks, int steps,

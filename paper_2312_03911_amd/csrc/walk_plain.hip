@@ -18,6 +18,7 @@ namespace {
 // consecutive threads touch consecutive addresses.
 struct PlainState {
     double *x, *p, *g, *out_l;  // x, p, g: [d][k]
+    double *l;      // [k] log L at x (external-likelihood walk: written by the caller)
     uint32_t *eps;  // [nb * 4][k] xoshiro states, nb = ceil(d / 4)
     uint32_t *res;  // [4][k]
     int32_t *s, *nref, *streak, *steps, *outs, *nprune, *nsave, *done;
@@ -39,13 +40,14 @@ __host__ __device__ inline int64_t plain_bytes(int k, int d, int n_steps_max, Pl
     double *p = (double *)take((int64_t)k * d * 8);
     double *g = (double *)take((int64_t)k * d * 8);
     double *ol = (double *)take((int64_t)k * 8);
+    double *lx = (double *)take((int64_t)k * 8);
     uint32_t *eps = (uint32_t *)take((int64_t)k * nb * 16);
     uint32_t *res = (uint32_t *)take((int64_t)k * 16);
     int32_t *ints[8];
     for (int i = 0; i < 8; ++i) ints[i] = (int32_t *)take((int64_t)k * 4);
     int32_t *act = (int32_t *)take((int64_t)n_steps_max * 4);
     if (st) {
-        st->x = x; st->p = p; st->g = g; st->out_l = ol; st->eps = eps; st->res = res;
+        st->x = x; st->p = p; st->g = g; st->out_l = ol; st->l = lx; st->eps = eps; st->res = res;
         st->s = ints[0]; st->nref = ints[1]; st->streak = ints[2]; st->steps = ints[3];
         st->outs = ints[4]; st->nprune = ints[5]; st->nsave = ints[6]; st->done = ints[7];
         st->active = act;
@@ -177,6 +179,12 @@ __global__ void plain_start_kernel(void *arena, const RunDev *__restrict__ runs,
     S.nref[m] = S.streak[m] = S.steps[m] = S.outs[m] = S.nprune[m] = S.nsave[m] = S.done[m] = 0;
 }
 
+// One step of every walker of the run.  EXT = false: drift, then log L and the
+// score from the run's own family.  EXT = true (external likelihood): the
+// caller has evaluated log L and the score at the already drifted positions
+// into the workspace; after the step the walkers that go on drift for the
+// next one, so the caller always evaluates at the current positions.
+template <bool EXT>
 __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, int run,
                                   unsigned char *ws, int t) {
     const RunDev &R = runs[run];
@@ -195,8 +203,13 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
     const double *prm = at<double>(arena, R.off_prm);
 
     // drift, log L and the score
-    for (int a = 0; a < d; ++a) x[a * k] += dt * p[a * k];
-    const double l = plain_loglike(R, prm, x, g, k);
+    double l;
+    if constexpr (EXT) {
+        l = S.l[m];
+    } else {
+        for (int a = 0; a < d; ++a) x[a * k] += dt * p[a * k];
+        l = plain_loglike(R, prm, x, g, k);
+    }
     bool viol = false;
     for (int a = 0; a < d; ++a) viol = viol || x[a * k] < R.lo || x[a * k] > R.hi;
     const bool out = viol || l <= lstar;
@@ -271,7 +284,23 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
                   (unsigned long long)(nsave == 0 ? 1 : 0));
     } else {
         atomicAdd(&S.active[t], 1);
+        if constexpr (EXT)
+            for (int a = 0; a < d; ++a) x[a * k] += dt * p[a * k];
     }
+}
+
+// External-likelihood walk, first step's positions: the starts drifted once.
+__global__ void ext_drift_kernel(void *arena, const RunDev *__restrict__ runs, int run,
+                                 unsigned char *ws) {
+    const RunDev &R = runs[run];
+    const Acc *acc = at<Acc>(arena, R.off_acc);
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (acc->state != GGNS_RUN_ACTIVE || m >= R.n_kill) return;
+    PlainState S;
+    plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, ws);
+    const int64_t k = R.n_kill;
+    const double dt = acc->dt;
+    for (int a = 0; a < R.d; ++a) S.x[a * k + m] += dt * S.p[a * k + m];
 }
 
 }  // namespace
@@ -289,8 +318,8 @@ int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev
     PlainState S;
     plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, w);
     for (int t = 0; t < R.n_steps_max; ++t) {
-        hipLaunchKernelGGL(plain_step_kernel, dim3(blocks), dim3(threads), 0, s, arena, runs_dev, run,
-                           w, t);
+        hipLaunchKernelGGL(plain_step_kernel<false>, dim3(blocks), dim3(threads), 0, s, arena, runs_dev,
+                           run, w, t);
         if (hipGetLastError() != hipSuccess) return GGNS_EHIP;
         if ((t + 1) % poll_every == 0 && t + 1 < R.n_steps_max) {
             int32_t n_active = 0;
@@ -301,6 +330,33 @@ int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev
         }
     }
     return GGNS_OK;
+}
+
+int launch_ext_begin(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws,
+                     hipStream_t s) {
+    const int threads = 256, blocks = (R.n_kill + threads - 1) / threads;
+    unsigned char *w = reinterpret_cast<unsigned char *>(ws);
+    hipLaunchKernelGGL(plain_start_kernel, dim3(blocks), dim3(threads), 0, s, arena, runs_dev, run, w);
+    hipLaunchKernelGGL(ext_drift_kernel, dim3(blocks), dim3(threads), 0, s, arena, runs_dev, run, w);
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+int launch_ext_step(void *arena, const RunDev *runs_dev, int run, const RunDev &R, void *ws, int t,
+                    hipStream_t s) {
+    const int threads = 256, blocks = (R.n_kill + threads - 1) / threads;
+    hipLaunchKernelGGL(plain_step_kernel<true>, dim3(blocks), dim3(threads), 0, s, arena, runs_dev, run,
+                       reinterpret_cast<unsigned char *>(ws), t);
+    return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+}
+
+void ext_buffers(const RunDev &R, void *ws, double **x, double **logl, double **grad,
+                 int32_t **active) {
+    PlainState S;
+    plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, reinterpret_cast<unsigned char *>(ws));
+    *x = S.x;
+    *logl = S.l;
+    *grad = S.g;
+    *active = S.active;
 }
 
 }  // namespace ggns
