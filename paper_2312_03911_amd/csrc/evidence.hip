@@ -105,10 +105,6 @@ __device__ __forceinline__ T block_exscan(T v, T ident, Op op, T *wtot) {
     return op(pre, excl);
 }
 
-__device__ double block_exscan_sum(double v, double *buf) {
-    return block_exscan<double>(v, 0.0, [](double a, double b) { return a + b; }, buf);
-}
-
 __device__ double block_exscan_lae(double v, double *buf) {
     return block_exscan<double>(v, -INFINITY, [](double a, double b) { return lae(a, b); }, buf);
 }

@@ -158,13 +158,6 @@ __device__ __forceinline__ void group_sum_n(T (&v)[N], int G) {
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T group_sum(T v, int G) {
-    T a[1] = {v};
-    group_sum_n<T, 1>(a, G);
-    return a[0];
-}
-
 __device__ __forceinline__ bool group_any(bool pred, int G) {
     const unsigned long long b = __ballot(pred);
     const int lane = threadIdx.x & 63;

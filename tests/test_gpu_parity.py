@@ -36,15 +36,20 @@ def _np(t):
 
 
 def _load_state(torch, eng, o, r, X):
-    """Same live set on both sides; each side evaluates its own log L."""
+    """Same live set on both sides: the positions the GPU holds (rounded to the
+    run's precision) and the log L the GPU computed for them.  The kill order
+    is an integer decision taken from these values, so both sides take it on
+    the same ones (an FP32 log L and the oracle's FP64 value of the same point
+    can order two points differently); the likelihood itself is compared on
+    its own, per step of the walk and in test_loglike_and_adjoint_match_oracle."""
     cfg = eng.cfgs[r]
     xd = torch.from_numpy(X).to(eng.device, eng._fdtype(r))
     eng.live_x(r).copy_(xd)
     l, _ = eng.loglike(r, eng.live_x(r).clone(), grad=False)
     eng.live_logl(r).copy_(l)
     Xo = _np(xd).astype(np.float64)          # the rounded positions the GPU holds
-    o.set_state(live_x=Xo, log_z=-math.inf, log_x=0.0, dt=cfg.dt_init * (cfg.hi - cfg.lo),
-                iteration=0)
+    o.set_state(live_x=Xo, live_logl=_np(l).astype(np.float64), log_z=-math.inf, log_x=0.0,
+                dt=cfg.dt_init * (cfg.hi - cfg.lo), iteration=0)
     torch.cuda.synchronize()
     return Xo
 
