@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-alt", action="store_true",
                     help="skip the untimed pass under the per-walker noise reading")
+    ap.add_argument("--graph", action="store_true",
+                    help="throughput passes replay each block of --poll iterations as one captured HIP graph")
     ap.add_argument("--tile", default="auto", choices=["auto", "default"],
                     help="walk tile shape: autotuned per group of like runs, or the library default")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -309,6 +311,17 @@ def main():
         evs = []
         pending, b = None, 0
         while True:
+            if args.graph and not record:
+                # the block as one captured graph (captured once: every pass
+                # re-initialises the same arena, so the launches' arguments,
+                # all inside the arena, stay valid)
+                eng.step_block(args.poll, use_graph=True)
+                nxt = eng.states_async(b & 1)
+                b += 1
+                if pending is not None and (pending() != _lib.RUN_ACTIVE).all():
+                    break
+                pending = nxt
+                continue
             for _ in range(args.poll):
                 eng.evidence_update()
                 if record:
@@ -404,7 +417,8 @@ def main():
                    "d": sorted({c.d for c in cfgs}), "n_live": sorted({c.n_live for c in cfgs}),
                    "kinds": sorted({c.kind for c in cfgs}), "precision": sorted({c.precision for c in cfgs}),
                    "evals_per_step": evals, "iterations": [s["iter"] for s in stats][:16],
-                   "tile": {"mode": args.tile, "coords_per_lane_x_lanes": shapes}},
+                   "tile": {"mode": args.tile, "coords_per_lane_x_lanes": shapes},
+                   "launch": "graph replay per block" if args.graph else "eager"},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": frac, "traffic": traffic_for(args.workload),
                      "kernel": ("walk_mfma_kernel" if bound == "mfma" or

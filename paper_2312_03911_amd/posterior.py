@@ -25,6 +25,39 @@ def normalized_log_weights(dead_logl, dead_logw, log_z: float) -> np.ndarray:
     return np.asarray(dead_logl, np.float64) + np.asarray(dead_logw, np.float64) - log_z
 
 
+def effective_sample_size(log_p) -> float:
+    """Kish's effective number of samples of normalised log weights."""
+    lp = np.asarray(log_p, np.float64)
+    w = np.exp(lp - lp.max())
+    return float(w.sum() ** 2 / (w * w).sum())
+
+
+def equal_weight_samples(x, log_p, n: int | None = None, seed: int = 0) -> np.ndarray:
+    """n equally weighted posterior samples from the weighted dead points, by
+    systematic resampling (one uniform offset, n evenly spaced draws through
+    the weight CDF), e.g. to train a downstream amortised sampler; n defaults
+    to the effective sample size."""
+    x = np.asarray(x)
+    lp = np.asarray(log_p, np.float64)
+    w = np.exp(lp - lp.max())
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    if n is None:
+        n = max(1, int(round(effective_sample_size(lp))))
+    u = (np.random.default_rng(seed).uniform() + np.arange(n)) / n
+    idx = np.minimum(np.searchsorted(cdf, u, side="right"), len(cdf) - 1)
+    return x[idx]
+
+
+def engine_posterior(engine, r: int):
+    """Dead-point positions of run r (kept with engine.keep_dead_x(r) before the
+    run) and their normalised log weights, after the run has finished."""
+    st = engine.stats()[r]
+    dl, dw = engine.dead(r)
+    lp = normalized_log_weights(dl.cpu().numpy(), dw.cpu().numpy(), st["log_z"])
+    return engine.dead_x(r).cpu().numpy(), lp
+
+
 def gmm_mode_report(x, log_p, cfg: RunConfig, weight_floor: float = 1e-12) -> dict:
     """Mode recovery of an equal-weight diagonal Gaussian mixture run.
 

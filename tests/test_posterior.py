@@ -1,4 +1,5 @@
-"""The mixture mode report on samples with known answers (host logic)."""
+"""Posterior post-processing on samples with known answers (host logic): the
+mixture mode report and equal-weight resampling."""
 import numpy as np
 
 from paper_2312_03911_amd import inputs
@@ -49,3 +50,19 @@ def test_far_sample_does_not_count_as_recovery():
 def test_normalized_log_weights():
     lw = normalized_log_weights([1.0, 2.0], [-3.0, -4.0], 0.5)
     np.testing.assert_allclose(lw, [-2.5, -2.5])
+
+
+def test_equal_weight_resampling_follows_the_weights():
+    """Systematic resampling: each point appears floor or ceil of n times its
+    weight, and the effective sample size of equal weights is their count."""
+    from paper_2312_03911_amd.posterior import effective_sample_size, equal_weight_samples
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0.0, 1.0, 50)
+    w /= w.sum()
+    x = np.arange(50)
+    n = 10000
+    s = equal_weight_samples(x, np.log(w), n=n, seed=5)
+    counts = np.bincount(s, minlength=50)
+    assert np.all(np.abs(counts - n * w) <= 1.0 + 1e-9)
+    assert abs(effective_sample_size(np.zeros(40)) - 40.0) < 1e-12
+    assert len(equal_weight_samples(x, np.zeros(50))) == 50
