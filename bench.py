@@ -257,8 +257,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-alt", action="store_true",
                     help="skip the untimed pass under the per-walker noise reading")
-    ap.add_argument("--graph", action="store_true",
-                    help="throughput passes replay each block of --poll iterations as one captured HIP graph")
+    ap.add_argument("--launch", default="graph", choices=["graph", "eager"],
+                    help="throughput passes: each block of --poll iterations replayed as one captured "
+                         "HIP graph, or launched kernel by kernel")
     ap.add_argument("--tile", default="auto", choices=["auto", "default"],
                     help="walk tile shape: autotuned per group of like runs, or the library default")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -311,7 +312,7 @@ def main():
         evs = []
         pending, b = None, 0
         while True:
-            if args.graph and not record:
+            if args.launch == "graph" and not record:
                 # the block as one captured graph (captured once: every pass
                 # re-initialises the same arena, so the launches' arguments,
                 # all inside the arena, stay valid)
@@ -418,7 +419,7 @@ def main():
                    "kinds": sorted({c.kind for c in cfgs}), "precision": sorted({c.precision for c in cfgs}),
                    "evals_per_step": evals, "iterations": [s["iter"] for s in stats][:16],
                    "tile": {"mode": args.tile, "coords_per_lane_x_lanes": shapes},
-                   "launch": "graph replay per block" if args.graph else "eager"},
+                   "launch": args.launch},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": frac, "traffic": traffic_for(args.workload),
                      "kernel": ("walk_mfma_kernel" if bound == "mfma" or
