@@ -179,6 +179,8 @@ __device__ __forceinline__ float m_sqrt(float v) { return __builtin_amdgcn_sqrtf
 __device__ __forceinline__ double m_sqrt(double v) { return sqrt(v); }
 __device__ __forceinline__ float m_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double m_div(double a, double b) { return a / b; }
+__device__ __forceinline__ float m_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double m_rsqrt(double v) { return 1.0 / sqrt(v); }
 
 // ---------------------------------------------------------------------------
 // Log-likelihood, score and the two reflection dot products p.g and g.g, in the
@@ -354,24 +356,29 @@ __device__ __forceinline__ LikOut<T> lik_shells(const ShellParams<T, C, KM> &P, 
             for (int l = k + 1; l < KM; ++l) v[q++] += u[k][c] * u[l][c];
     }
     group_sum_n<T, 2 * KM + NB>(v, G);
-    T lp[KM], rho[KM], coef[KM];
+    // rho_k = |u_k| and 1/rho_k from one reciprocal square root (0 at rho = 0,
+    // where the component's score term vanishes); the responsibilities
+    // exp(lp_k - l) are the log-sum-exp terms over their sum
+    T lp[KM], rho[KM], rinv[KM], ek[KM], coef[KM];
     T lmax = T(-INFINITY);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        rho[k] = m_sqrt(v[k]);
+        rinv[k] = (v[k] > T(0)) ? m_rsqrt(v[k]) : T(0);
+        rho[k] = v[k] * rinv[k];
         const T e = rho[k] - P.rad[k];
         lp[k] = P.lnrm[k] - T(0.5) * e * e * P.iw2[k];
         lmax = lp[k] > lmax ? lp[k] : lmax;
     }
     T sum = T(0);
 #pragma unroll
-    for (int k = 0; k < KM; ++k) sum += m_exp(lp[k] - lmax);
-    const T l = lmax + m_log(sum);
-#pragma unroll
     for (int k = 0; k < KM; ++k) {
-        const T c_k = -m_div(m_exp(lp[k] - l) * (rho[k] - P.rad[k]) * P.iw2[k], rho[k]);
-        coef[k] = (rho[k] > T(0)) ? c_k : T(0);
+        ek[k] = m_exp(lp[k] - lmax);
+        sum += ek[k];
     }
+    const T l = lmax + m_log(sum);
+    const T isum = m_div(T(1), sum);
+#pragma unroll
+    for (int k = 0; k < KM; ++k) coef[k] = -(ek[k] * isum) * (rho[k] - P.rad[k]) * P.iw2[k] * rinv[k];
     T pg = T(0), gg = T(0);
     int q = 2 * KM;
 #pragma unroll
@@ -413,13 +420,18 @@ __device__ __forceinline__ LikOut<T> lik_gmm(const GmmParams<T, C, KM> &P, int G
         q[k] = P.lnrm[k] - T(0.5) * q[k];   // log of component k
         lmax = q[k] > lmax ? q[k] : lmax;
     }
+    // the responsibilities exp(q_k - l) are the log-sum-exp terms over their sum
+    T resp[KM];
     T sum = T(0);
 #pragma unroll
-    for (int k = 0; k < KM; ++k) sum += m_exp(q[k] - lmax);
+    for (int k = 0; k < KM; ++k) {
+        resp[k] = m_exp(q[k] - lmax);
+        sum += resp[k];
+    }
     const T l = lmax + m_log(sum);
-    T resp[KM];
+    const T isum = m_div(T(1), sum);
 #pragma unroll
-    for (int k = 0; k < KM; ++k) resp[k] = m_exp(q[k] - l);
+    for (int k = 0; k < KM; ++k) resp[k] *= isum;
     T acc[2] = {T(0), T(0)};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
