@@ -167,15 +167,14 @@ def rng_rate(torch, L) -> float:
     return best
 
 
-def cpu_baseline(cfgs, budget_s: float = 12.0):
-    """The oracle on the host cores, on a bounded sample of the workload: its
-    runs in order (cycling if they finish early) until the time budget is used;
-    a run cut by the budget counts the iterations it completed."""
-    import oracle.oracle as O
-    O.build(force=False)
+def _oracle_sample(O, cfgs, budget_s: float):
+    """The workload's runs in order (cycling if they finish early) until the
+    budget is used; a run cut by the budget counts the iterations it did.
+    Returns evaluations, whole runs, iterations, the cut run's note, seconds
+    and (index, log Z) of every whole run."""
     t0 = time.perf_counter()
     ev, whole, its, j = 0, 0, 0, 0
-    last = ""
+    last, done = "", []
     while time.perf_counter() - t0 < budget_s:
         cfg = cfgs[j % len(cfgs)]
         o = O.Oracle(cfg).init()
@@ -185,15 +184,45 @@ def cpu_baseline(cfgs, budget_s: float = 12.0):
             it += 1
         if not o.active:
             whole += 1
+            if j < len(cfgs):
+                done.append((j, float(o.st.lz)))
         else:
             last = f" + {it} iterations of {cfg.name}"
         ev += o.st.evals
         its += it
         j += 1
-    dt = time.perf_counter() - t0
-    return {"value": ev / dt, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
+    return ev, whole, its, last, time.perf_counter() - t0, done
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfgs, budget_s: float = 12.0, budget_single_s: float = 6.0):
+    """The oracle on the host cores (OpenMP over walkers, every thread), on a
+    bounded sample of the workload, and single-threaded on a shorter one (its
+    results are identical: the random streams are counter-based)."""
+    import oracle.oracle as O
+    O.build(force=False)
+    cores = O.num_threads()
+    ev, whole, its, last, dt, done = _oracle_sample(O, cfgs, budget_s)
+    O.set_threads(1)
+    ev1, _, its1, _, dt1, _ = _oracle_sample(O, cfgs, budget_single_s)
+    O.set_threads(cores)
+    return {"value": ev / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{whole} whole runs{last} of the workload ({its} iterations, "
-                      f"{ev} evaluations) in {dt:.1f} s"}
+                      f"{ev} evaluations) in {dt:.1f} s",
+            "single_thread_value": ev1 / dt1,
+            "single_thread_sample": f"{its1} iterations, {ev1} evaluations in {dt1:.1f} s",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "whole_runs_log_z": done}
 
 
 def plain_baseline(cfgs, fused_value: float, fused_ms_per_run: float, fused_stats, truth,
@@ -246,10 +275,24 @@ def sweep_report(cfgs, stats, truth) -> dict:
             "loglog_slope_evals_vs_d": float(np.polyfit(np.log(ds), np.log(ev), 1)[0])}
 
 
+def run_environment(torch) -> dict:
+    """Versions, the device and its clocks as rocm-smi reports them."""
+    import subprocess
+    env = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None),
+           "device": torch.cuda.get_device_name(0)}
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+        env["clocks"] = [ln.strip() for ln in r.stdout.splitlines()
+                         if "sclk" in ln.lower() or "mclk" in ln.lower() or "fclk" in ln.lower()][:6]
+    except (OSError, subprocess.SubprocessError):
+        env["clocks"] = None
+    return env
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="shells32x10")
     ap.add_argument("--poll", type=int, default=8)
@@ -351,8 +394,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
+    pass_ms = []
     for _ in range(args.steps):
-        stats = full_run(False)
+        t1 = time.perf_counter()
+        stats = full_run(False)      # ends by reading the stats: the pass is complete
+        pass_ms.append(1e3 * (time.perf_counter() - t1))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # the same passes again with HIP events around every walk launch, for the
@@ -420,8 +466,12 @@ def main():
                    "evals_per_step": evals, "iterations": [s["iter"] for s in stats][:16],
                    "tile": {"mode": args.tile, "coords_per_lane_x_lanes": shapes},
                    "launch": args.launch},
+        "pass_ms": {"median": float(np.median(pass_ms)),
+                    "iqr": float(np.percentile(pass_ms, 75) - np.percentile(pass_ms, 25)),
+                    "min": float(np.min(pass_ms)), "max": float(np.max(pass_ms))},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": frac, "traffic": traffic_for(args.workload),
+                     "frac_resources_overlapped": max(t_valu, t_mfma) / walk_time_s,
                      "kernel": ("walk_mfma_kernel" if bound == "mfma" or
                                 all(c.precision == "bf16mma" for c in cfgs) else "walk_valu_kernel"),
                      "walk_ms_per_step": 1e3 * walk_time_s,
@@ -485,7 +535,16 @@ def main():
         res["plain_baseline"] = plain_baseline(cfgs, value, ms_per_step / len(cfgs), stats,
                                                truth)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(cfgs)
+        cb = cpu_baseline(cfgs)
+        done = cb.pop("whole_runs_log_z")
+        res["cpu_baseline"] = cb
+        if done:
+            # the same runs (same seeds) on the GPU against the FP64 oracle: FP32
+            # trajectories part from FP64 ones, so this is a statistical comparison
+            dzo = [stats[j]["log_z"] - lz for j, lz in done]
+            res["accuracy"]["logz_minus_oracle"] = {"runs": len(dzo), "mean": float(np.mean(dzo)),
+                                                    "max_abs": float(np.max(np.abs(dzo)))}
+    res["env"] = run_environment(torch)
     print(json.dumps(res), flush=True)
 
 
