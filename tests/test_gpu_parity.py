@@ -74,6 +74,19 @@ CASES = [
                                                      precision="bf16mma", n_steps_max=60), 1e-4, 1e-4),
     ("corr128_bf16", lambda: inputs.config_corr_gauss(d=128, n_live=256, seed=18, param_seed=9,
                                                       precision="bf16mma"), 1e-4, 1e-4),
+    # the largest shapes of the vector-ALU walk: 256 coordinates over 64 lanes
+    # (both cross-row butterfly levels) and 4096 live points
+    ("gauss_diag256_fp64", lambda: inputs.RunConfig(
+        kind="gauss_diag", d=256, n_live=300, lo=-6.0, hi=6.0, seed=25, n_steps_max=40,
+        precision="fp64", params=inputs.gauss_diag_params(np.linspace(-1, 1, 256), np.linspace(0.5, 1.5, 256))),
+     1e-10, 1e-9),
+    # (log L ~ -1e6 here: the masking band is tau |L*|, so tau is set where the
+    # FP32 error of such a sum, ~1e-6 relative, still sits well inside it)
+    ("gmm256_fp32", lambda: inputs.config_gmm(d=256, n_live=200, n_comp=3, seed=26, param_seed=11,
+                                              n_steps_max=40), 1e-4, 1e-5),
+    ("gauss_diag8_n4096_fp32", lambda: inputs.RunConfig(
+        kind="gauss_diag", d=8, n_live=4096, lo=-4.0, hi=4.0, seed=27, n_steps_max=30,
+        params=inputs.gauss_diag_params(np.zeros(8), np.full(8, 0.7))), 1e-4, 1e-4),
     # torus reward (hardware sin/cos in FP32, the library's in FP64)
     ("torus16_fp32", lambda: inputs.config_torus(d=16, n_live=400, seed=23), 1e-4, 1e-4),
     ("torus9_fp64", lambda: inputs.config_torus(d=9, n_live=200, seed=24, precision="fp64"),
