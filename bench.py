@@ -72,6 +72,11 @@ def workload(name: str):
         return inputs.replicate(inputs.config_gmm(cluster=1), 10, base_seed=2400)
     if name == "corr256":
         return [inputs.config_corr_gauss()]
+    if name == "corr256x10":
+        # the paper's 10-run protocol for the d=256 correlated Gaussian, one batch
+        return inputs.replicate(inputs.config_corr_gauss(), 10, base_seed=2300)
+    if name == "gmm64x10":
+        return inputs.replicate(inputs.config_gmm(), 10, base_seed=2400)
     if name == "batch64":
         return inputs.config_batch()
     if name == "torus_sweep":
