@@ -164,6 +164,7 @@ struct Class {
     int n_tiles;
     size_t lds;
     int waves = 0;       // matrix-core classes: wavefronts per group of 16 walkers
+    int gf = 0;          // vector walk: lanes per walker when every run of the class has 8, else 0
 };
 
 }  // namespace
@@ -201,14 +202,15 @@ namespace {
 // Walk tiles: one walker per lane group, kWalkThreads / G groups per block.
 // Init tiles: the same shape over the n_live prior draws.
 void build_classes(ggns_ctx *c) {
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;   // (prec, C, kind) -> runs
+    // (prec, C, kind, 8 if the run's groups have 8 lanes else 0) -> runs
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     std::vector<int> mfma_runs;
     for (int r = 0; r < (int)c->plan.runs.size(); ++r) {
         const RunDev &R = c->plan.runs[r];
         if (R.prec == GGNS_FP32_BF16MMA)
             mfma_runs.push_back(r);
         else
-            groups[std::make_tuple(R.prec, R.C, R.var)].push_back(r);
+            groups[std::make_tuple(R.prec, R.C, R.var, R.G == 8 ? 8 : 0)].push_back(r);
         c->max_kd = std::max<int>(c->max_kd, R.n_kill * R.d);
     }
     c->tiles_host.clear();
@@ -222,6 +224,7 @@ void build_classes(ggns_ctx *c) {
     for (auto &kv : groups) {
         Class w{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), false,
                 (int64_t)c->tiles_host.size(), 0, 0};
+        w.gf = std::get<3>(kv.first);
         size_t lds = 0;
         for (int r : kv.second) {
             const RunDev &R = c->plan.runs[r];
@@ -382,7 +385,7 @@ int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
             return launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
                                     w.n_tiles, w.C, w.waves, st);
         return launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                 w.n_tiles, w.prec, w.C, w.kind, w.lds, st);
+                                 w.n_tiles, w.prec, w.C, w.kind, w.gf, w.lds, st);
     };
     if (n == 0) return GGNS_OK;
     if (n == 1) return launch(ctx->walk_classes[0], s);

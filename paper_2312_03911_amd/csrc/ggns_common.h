@@ -97,7 +97,7 @@ void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_
 void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, int max_chunks, hipStream_t s);
 void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s);
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                      int prec, int C, int kind, size_t lds_bytes, hipStream_t s);
+                      int prec, int C, int kind, int gf, size_t lds_bytes, hipStream_t s);
 bool mfma_shape_ok(int d_pad, int waves);
 int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
                      int d_pad, int waves, hipStream_t s);

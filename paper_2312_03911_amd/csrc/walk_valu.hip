@@ -22,6 +22,8 @@
 // reduction latency.  The reservoir point lives in registers and is written
 // once, when the walker ends: the only HBM traffic of a walk is the gather of
 // its start point and that one row.
+#include <type_traits>
+
 #include "ggns_device.h"
 
 #ifndef GGNS_WALK_WAVES
@@ -80,7 +82,10 @@ __device__ __forceinline__ void momentum_draw(uint64_t seed, uint32_t m, uint32_
 
 }  // namespace
 
-template <typename T, int C, int VAR>
+// GF: the group size when fixed at compile time (8), else 0 (read from the run).
+// A fixed size folds the group-size branches of the reductions and the
+// broadcast away, so the step's common path has no branch taken.
+template <typename T, int C, int VAR, int GF>
 __global__ void __launch_bounds__(kWalkThreads, GGNS_WALK_WAVES)
 walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles) {
     constexpr int NB = (C + 3) / 4;
@@ -93,7 +98,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     __shared__ int next_walker;
     __shared__ unsigned long long blk_cnt[4];
 
-    const int d = R.d, dp = R.dp, G = R.G;
+    const int d = R.d, dp = R.dp, G = GF ? GF : R.G;
     const int ngroups = blockDim.x / G;
     const T *prm = at<T>(arena, R.off_prm);
     if (R.nprm_bytes_lds > 0) {
@@ -205,9 +210,17 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 }
             }
         }
-        if (walker_noise) {
-            // one normal per walker and step: the first of its stream (coordinate 0,
-            // held by the group's first lane)
+        // one normal per walker and step (noise_mode 1): the first of its stream
+        // (coordinate 0, held by the group's first lane)
+        if constexpr (GF == 8) {
+            // lane 0 of each quad to its quad, then the half-row mirror hands lanes
+            // 4..7 the copy held by lanes 3..0; selects, no branch
+            const T t = dpp_mov<kDppQuad0>(eps_c[0]);
+            const T u = dpp_mov<kDppHalfMirror>(t);
+            const T e0 = (gl < 4) ? t : u;
+#pragma unroll
+            for (int c = 0; c < C; ++c) eps_c[c] = walker_noise ? e0 : eps_c[c];
+        } else if (walker_noise) {
             const T e0 = __shfl(eps_c[0], gbase, 64);
 #pragma unroll
             for (int c = 0; c < C; ++c) eps_c[c] = e0;
@@ -267,40 +280,38 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 #pragma unroll
         for (int c = 0; c < C; ++c) xo[c] = take ? x[c] : xo[c];
         out_l = take ? (double)lk.l : out_l;
-        // pruning: back to the start with fresh momentum
-        if (prune_streak > 0 && streak >= prune_streak) {
-            if (active) {
+        // rare events, one branch: a prune (back to the start with fresh
+        // momentum), then the end of the walker (its kept point to HBM, the
+        // group takes the next walker of the tile); streak, nref and steps are
+        // the same on every lane of a group, so groups enter whole
+        const bool pruning = prune_streak > 0 && streak >= prune_streak;
+        const bool ends = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
+        if (__builtin_expect(active & (pruning | ends), 0)) {
+            if (pruning) {
                 const T *xs = live_x + (int64_t)s * d;
 #pragma unroll
                 for (int c = 0; c < C; ++c) x[c] = valid[c] ? xs[a0 + c] : T(0);
+                nprune += 1;
+                momentum_draw<T, C>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
+                nref = 0;
+                streak = 0;
             }
-            nprune += 1;
-            momentum_draw<T, C>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
-            nref = 0;
-            streak = 0;
-        }
-        const bool done = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
-        const bool need = active && done;
-        if (need) {
-            T *wo = walk_x + (int64_t)m * d;
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (valid[c]) wo[a0 + c] = xo[c];
-        }
-        if (need && gl == 0) {
-            walk_logl[m] = out_l;
-            c_outs += outs;
-            c_steps += steps;
-            c_prunes += nprune;
-            c_nosave += (nsave == 0) ? 1 : 0;
-        }
-        // the group takes the next walker of the tile
-        if (__any(need)) {
-            int nm = 0;
-            if (need && gl == 0) nm = atomicAdd(&next_walker, 1);
-            nm = __shfl(nm, gbase, 64);
+            const bool need = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
             if (need) {
-                m = nm;
+                T *wo = walk_x + (int64_t)m * d;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (valid[c]) wo[a0 + c] = xo[c];
+                int nm = 0;
+                if (gl == 0) {
+                    walk_logl[m] = out_l;
+                    c_outs += outs;
+                    c_steps += steps;
+                    c_prunes += nprune;
+                    c_nosave += (nsave == 0) ? 1 : 0;
+                    nm = atomicAdd(&next_walker, 1);
+                }
+                m = __shfl(nm, gbase, 64);
                 active = m < tile.m_end;
                 if (active) start_walker(m);
             }
@@ -325,29 +336,36 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     }
 }
 
+// FP32 classes whose runs all have groups of 8 lanes take the kernel with the
+// group size fixed; every other class reads it from the run.
 template <typename T, int C>
 static hipError_t launch_walk_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
-                                int var, size_t lds, hipStream_t s) {
-    GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_>), dim3(n_tiles),
-                                               dim3(kWalkThreads), lds, s, arena, runs, tiles));
+                                int var, int gf, size_t lds, hipStream_t s) {
+    if (std::is_same<T, float>::value && gf == 8) {
+        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 8>), dim3(n_tiles),
+                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
+    } else {
+        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 0>), dim3(n_tiles),
+                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
+    }
     return hipGetLastError();
 }
 
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int prec,
-                      int C, int var, size_t lds, hipStream_t s) {
+                      int C, int var, int gf, size_t lds, hipStream_t s) {
     hipError_t e = hipErrorInvalidValue;
     if (prec == GGNS_FP64) {
         switch (C) {
-            case 1: e = launch_walk_t<double, 1>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
-            case 2: e = launch_walk_t<double, 2>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
-            case 4: e = launch_walk_t<double, 4>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
+            case 1: e = launch_walk_t<double, 1>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
+            case 2: e = launch_walk_t<double, 2>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
+            case 4: e = launch_walk_t<double, 4>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
         }
     } else {
         switch (C) {
-            case 1: e = launch_walk_t<float, 1>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
-            case 2: e = launch_walk_t<float, 2>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
-            case 4: e = launch_walk_t<float, 4>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
-            case 8: e = launch_walk_t<float, 8>(arena, runs_dev, tiles, n_tiles, var, lds, s); break;
+            case 1: e = launch_walk_t<float, 1>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
+            case 2: e = launch_walk_t<float, 2>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
+            case 4: e = launch_walk_t<float, 4>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
+            case 8: e = launch_walk_t<float, 8>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
         }
     }
     return e == hipSuccess ? GGNS_OK : GGNS_EHIP;
