@@ -149,7 +149,6 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     bool active = m < tile.m_end;
     int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0;
     double out_l = 0.0;
-    unsigned long long c_outs = 0, c_steps = 0, c_prunes = 0, c_nosave = 0;
 
     auto start_walker = [&](int mm) {
         uint32_t w[4];
@@ -305,10 +304,12 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 int nm = 0;
                 if (gl == 0) {
                     walk_logl[m] = out_l;
-                    c_outs += outs;
-                    c_steps += steps;
-                    c_prunes += nprune;
-                    c_nosave += (nsave == 0) ? 1 : 0;
+                    // the walker's counts go straight to the block's totals (LDS),
+                    // so no per-lane counter rides through the step loop
+                    atomicAdd(&blk_cnt[0], (unsigned long long)outs);
+                    atomicAdd(&blk_cnt[1], (unsigned long long)steps);
+                    atomicAdd(&blk_cnt[2], (unsigned long long)nprune);
+                    if (nsave == 0) atomicAdd(&blk_cnt[3], 1ull);
                     nm = atomicAdd(&next_walker, 1);
                 }
                 m = __shfl(nm, gbase, 64);
@@ -318,12 +319,6 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
     }
 
-    if (gl == 0 && c_steps > 0) {
-        atomicAdd(&blk_cnt[0], c_outs);
-        atomicAdd(&blk_cnt[1], c_steps);
-        atomicAdd(&blk_cnt[2], c_prunes);
-        atomicAdd(&blk_cnt[3], c_nosave);
-    }
     __syncthreads();
     if (threadIdx.x == 0 && blk_cnt[1] > 0) {
         atomicAdd(&acc->it_outs, blk_cnt[0]);
