@@ -164,7 +164,7 @@ struct Class {
     int n_tiles;
     size_t lds;
     int waves = 0;       // matrix-core classes: wavefronts per group of 16 walkers
-    int gf = 0;          // vector walk: lanes per walker when every run of the class has 8, else 0
+    int gf = 0;          // vector FP32 walk: lanes per walker (4, 8 or 16) shared by the class, else 0
 };
 
 }  // namespace
@@ -202,7 +202,8 @@ namespace {
 // Walk tiles: one walker per lane group, kWalkThreads / G groups per block.
 // Init tiles: the same shape over the n_live prior draws.
 void build_classes(ggns_ctx *c) {
-    // (prec, C, kind, 8 if the run's groups have 8 lanes else 0) -> runs
+    // (prec, C, kind, fixed group size) -> runs; FP32 runs with groups of 4, 8 or
+    // 16 lanes get a kernel with that size fixed at compile time
     std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     std::vector<int> mfma_runs;
     for (int r = 0; r < (int)c->plan.runs.size(); ++r) {
@@ -210,7 +211,9 @@ void build_classes(ggns_ctx *c) {
         if (R.prec == GGNS_FP32_BF16MMA)
             mfma_runs.push_back(r);
         else
-            groups[std::make_tuple(R.prec, R.C, R.var, R.G == 8 ? 8 : 0)].push_back(r);
+            groups[std::make_tuple(R.prec, R.C, R.var,
+                                   (R.prec == GGNS_FP32 && (R.G == 4 || R.G == 8 || R.G == 16)) ? R.G : 0)]
+                .push_back(r);
         c->max_kd = std::max<int>(c->max_kd, R.n_kill * R.d);
     }
     c->tiles_host.clear();

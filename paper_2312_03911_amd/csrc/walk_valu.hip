@@ -82,7 +82,7 @@ __device__ __forceinline__ void momentum_draw(uint64_t seed, uint32_t m, uint32_
 
 }  // namespace
 
-// GF: the group size when fixed at compile time (8), else 0 (read from the run).
+// GF: the group size when fixed at compile time (4, 8 or 16), else 0 (read from the run).
 // A fixed size folds the group-size branches of the reductions and the
 // broadcast away, so the step's common path has no branch taken.
 template <typename T, int C, int VAR, int GF>
@@ -211,12 +211,19 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
         // one normal per walker and step (noise_mode 1): the first of its stream
         // (coordinate 0, held by the group's first lane)
-        if constexpr (GF == 8) {
-            // lane 0 of each quad to its quad, then the half-row mirror hands lanes
-            // 4..7 the copy held by lanes 3..0; selects, no branch
-            const T t = dpp_mov<kDppQuad0>(eps_c[0]);
-            const T u = dpp_mov<kDppHalfMirror>(t);
-            const T e0 = (gl < 4) ? t : u;
+        if constexpr (GF == 4 || GF == 8 || GF == 16) {
+            // lane 0 of each quad to its quad; the half-row mirror then hands lanes
+            // 4..7 the copy held by lanes 3..0, and the row mirror lanes 8..15 the
+            // copy of lanes 7..0; selects, no branch
+            T e0 = dpp_mov<kDppQuad0>(eps_c[0]);
+            if constexpr (GF >= 8) {
+                const T u = dpp_mov<kDppHalfMirror>(e0);
+                e0 = (gl & 4) ? u : e0;
+            }
+            if constexpr (GF >= 16) {
+                const T u = dpp_mov<kDppMirror>(e0);
+                e0 = (gl & 8) ? u : e0;
+            }
 #pragma unroll
             for (int c = 0; c < C; ++c) eps_c[c] = walker_noise ? e0 : eps_c[c];
         } else if (walker_noise) {
@@ -331,13 +338,20 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     }
 }
 
-// FP32 classes whose runs all have groups of 8 lanes take the kernel with the
-// group size fixed; every other class reads it from the run.
+// FP32 classes whose runs all have groups of 4, 8 or 16 lanes take the kernel
+// with the group size fixed; every other class reads it from the run.
 template <typename T, int C>
 static hipError_t launch_walk_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
                                 int var, int gf, size_t lds, hipStream_t s) {
-    if (std::is_same<T, float>::value && gf == 8) {
+    constexpr bool f32 = std::is_same<T, float>::value;
+    if (f32 && gf == 4) {
+        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 4>), dim3(n_tiles),
+                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
+    } else if (f32 && gf == 8) {
         GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 8>), dim3(n_tiles),
+                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
+    } else if (f32 && gf == 16) {
+        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 16>), dim3(n_tiles),
                                                    dim3(kWalkThreads), lds, s, arena, runs, tiles));
     } else {
         GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 0>), dim3(n_tiles),

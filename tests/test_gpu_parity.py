@@ -127,6 +127,18 @@ def test_kill_and_walk_trace_match_oracle(torch, orc, name, make, tol, tau):
     _trace_check(torch, orc, make(), tol, tau)
 
 
+# every coordinates-per-lane choice of the FP32 vector walk on d = 32 (groups of
+# 32, 16, 8 and 4 lanes; 16, 8 and 4 run the kernels with the group size fixed
+# at compile time), in both noise readings
+VALU_SHAPES = [(c, noise) for c in (1, 2, 4, 8) for noise in ("component", "walker")]
+
+
+@pytest.mark.parametrize("c,noise", VALU_SHAPES, ids=[f"c{c}_{n}" for c, n in VALU_SHAPES])
+def test_valu_walk_shapes_match_oracle(torch, orc, c, noise):
+    cfg = inputs.config_shells(d=32, n_live=300, seed=400 + c, noise=noise, n_steps_max=60)
+    _trace_check(torch, orc, cfg, 1e-4, 1e-4, tile_c=[c], steps=20)
+
+
 # every tile shape of the matrix-core walk: (d, wavefronts per 16 walkers)
 MMA_SHAPES = [(20, 1), (20, 2), (64, 1), (64, 4), (72, 3), (128, 2), (128, 8), (150, 5),
               (180, 6), (200, 7), (256, 4), (256, 8)]
