@@ -372,12 +372,12 @@ __device__ __forceinline__ LikOut<T> lik_shells(const ShellParams<T, C, KM> &P, 
         lp[k] = P.lnrm[k] - T(0.5) * e * e * P.iw2[k];
         lmax = lp[k] > lmax ? lp[k] : lmax;
     }
-    T sum = T(0);
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        ek[k] = m_exp(lp[k] - lmax);
-        sum += ek[k];
-    }
+    for (int k = 0; k < KM; ++k) ek[k] = m_exp(lp[k] - lmax);
+    // the terms are >= 0, so starting from the first equals adding it to zero
+    T sum = ek[0];
+#pragma unroll
+    for (int k = 1; k < KM; ++k) sum += ek[k];
     const T l = lmax + m_log(sum);
     const T isum = m_div(T(1), sum);
 #pragma unroll
@@ -425,12 +425,11 @@ __device__ __forceinline__ LikOut<T> lik_gmm(const GmmParams<T, C, KM> &P, int G
     }
     // the responsibilities exp(q_k - l) are the log-sum-exp terms over their sum
     T resp[KM];
-    T sum = T(0);
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        resp[k] = m_exp(q[k] - lmax);
-        sum += resp[k];
-    }
+    for (int k = 0; k < KM; ++k) resp[k] = m_exp(q[k] - lmax);
+    T sum = resp[0];   // terms >= 0: the same as adding the first to zero
+#pragma unroll
+    for (int k = 1; k < KM; ++k) sum += resp[k];
     const T l = lmax + m_log(sum);
     const T isum = m_div(T(1), sum);
 #pragma unroll

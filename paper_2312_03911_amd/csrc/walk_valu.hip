@@ -129,6 +129,14 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     const T dt = (T)acc->dt;
     const uint32_t it = (uint32_t)acc->iter;
     const T lo = (T)R.lo, hi = (T)R.hi, dpn = (T)R.delta_p;
+    // the prior box per coordinate; padding coordinates get an unbounded one,
+    // so the outside test needs no validity mask
+    T blo[C], bhi[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        blo[c] = valid[c] ? lo : T(-INFINITY);
+        bhi[c] = valid[c] ? hi : T(INFINITY);
+    }
     const uint64_t seed = R.seed;
     const int nsurv = R.n_live - R.n_kill;
     const int min_ref = R.min_ref, max_ref = R.max_ref, n_steps_max = R.n_steps_max;
@@ -243,7 +251,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             // bitwise, not short-circuit: no branches in the step
-            vm[c] = valid[c] & ((x[c] < lo) | (x[c] > hi));
+            vm[c] = (x[c] < blo[c]) | (x[c] > bhi[c]);
             vany = vany | vm[c];
         }
         const bool viol = group_any(vany, G);
@@ -266,9 +274,11 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         const bool use_g = out && !viol && isfinite(lk.gg) && lk.gg > T(0);
         const bool flip_all = out && !viol && !use_g;
         const T f = use_g ? m_div(T(2) * lk.pg, lk.gg) : T(0);
+        // a coordinate outside the box makes the step outside (viol), so vm[c]
+        // needs no "and out"
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const bool flip = flip_all | (out & vm[c]);
+            const bool flip = flip_all | vm[c];
             const T pr = (flip ? -p[c] : p[c]) - f * g[c];
             // momentum noise, componentwise: p *= 1 + delta_p * eps
             p[c] = pr * (T(1) + dpn * eps_c[c]);
