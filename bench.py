@@ -351,12 +351,7 @@ def main():
         # block and read one block later, so the stream never drains between
         # blocks (the block enqueued after the last run stopped is no-ops)
         from paper_2312_03911_amd import _lib
-        import ctypes as C
-        eng.close()
-        eng.ctx = C.c_void_p()
-        _lib.check(eng.L.ggns_init(C.byref(eng.ctx), eng.descs, len(cfgs), eng.params.data_ptr(),
-                                   eng.params.numel(), eng.arena.data_ptr(), eng.arena_bytes,
-                                   eng._stream()), "ggns_init")
+        eng.reset()
         evs = []
         pending, b = None, 0
         while True:

@@ -111,6 +111,18 @@ class Engine:
             self.L.ggns_free(self.ctx)
             self.ctx = C.c_void_p()
 
+    def reset(self):
+        """Re-initialise every run on the same arena (same descriptors and
+        parameters): prior draws and accumulators start afresh.  A captured
+        block graph stays valid (its launches' arguments all point into the
+        arena); traces and dead-position buffers set on the old context are not
+        carried over."""
+        self.close()
+        _lib.check(self.L.ggns_init(C.byref(self.ctx), self.descs, len(self.cfgs),
+                                    self.params.data_ptr(), self.params.numel(),
+                                    self.arena.data_ptr(), self.arena_bytes, self._stream()),
+                   "ggns_init")
+
     def __del__(self):
         try:
             self.close()
