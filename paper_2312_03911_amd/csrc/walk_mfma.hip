@@ -111,7 +111,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     float *trace_x = reinterpret_cast<float *>(R.trace_x);
     const int k = R.n_kill;
 
-    float x[L], p[L], y[L];
+    float x[L], p[L], y[L], xo[L];   // xo: the walker's reservoir point, written when it ends
     Xoshiro eps[L / 4];
     Xoshiro res;
     int m = tile.m_begin + slot;
@@ -119,7 +119,13 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     bool active = m < tile.m_end;
     int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0;
     double out_l = 0.0;
-    unsigned long long c_outs = 0, c_steps = 0, c_prunes = 0, c_nosave = 0;
+    // the prior box per dimension; padding dimensions get an unbounded one
+    float blo[L], bhi[L];
+#pragma unroll
+    for (int c = 0; c < L; ++c) {
+        blo[c] = VALID(c) ? lo : -INFINITY;
+        bhi[c] = VALID(c) ? hi : INFINITY;
+    }
 
     auto start_walker = [&](int mm) {
         uint32_t w[4];
@@ -131,11 +137,10 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             if (R.cluster_mode) at<int32_t>(arena, R.off_start_cl)[mm] = cl;
         }
         const float *xs = live_x + (int64_t)s * d;
-        float *wo = walk_x + (int64_t)mm * d;
 #pragma unroll
         for (int c = 0; c < L; ++c) {
             x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
-            if (VALID(c)) wo[a0 + c] = x[c];
+            xo[c] = x[c];
         }
         out_l = live_logl[s];
         momentum_lane<L>(seed, (uint32_t)mm, it, 0u, a0, d, p);
@@ -162,7 +167,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             for (int c = 0; c < L; ++c) {
                 x[c] = x[c] + dt * p[c];
                 rb[c] = (__bf16)(x[c] - mu[c]);
-                vany = vany | (VALID(c) & ((x[c] < lo) | (x[c] > hi)));
+                vany = vany | (x[c] < blo[c]) | (x[c] > bhi[c]);
             }
             __bf16 *dst = rbuf + slot * RS + a0;
 #pragma unroll
@@ -253,8 +258,9 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = 4 * i + j;
-                const bool vm = VALID(c) & ((x[c] < lo) | (x[c] > hi));
-                const bool flip = flip_all | (out & vm);
+                // a dimension outside the box makes the step outside (viol)
+                const bool vm = (x[c] < blo[c]) | (x[c] > bhi[c]);
+                const bool flip = flip_all | vm;
                 const float pr = (flip ? -p[c] : p[c]) + f * y[c];   // p - f g with g = -y
                 p[c] = pr * (1.0f + dpn * z[j]);
             }
@@ -266,51 +272,53 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         nsave += keep ? 1 : 0;
         const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32))
                                         : (nsave == 0));
-        if (take && active) {
-            float *wo = walk_x + (int64_t)m * d;
 #pragma unroll
-            for (int c = 0; c < L; ++c)
-                if (VALID(c)) wo[a0 + c] = x[c];
-            out_l = (double)l;
-        }
-        if (prune_streak > 0 && streak >= prune_streak) {
-            if (active) {
+        for (int c = 0; c < L; ++c) xo[c] = take ? x[c] : xo[c];
+        out_l = take ? (double)l : out_l;
+        // rare events, one branch: a prune (back to the start with fresh
+        // momentum), then the end of walkers (kept point to HBM, the slot takes
+        // the next walker of the tile).  Slot states are the same in every lane
+        // of a slot and every wavefront, so all wavefronts take the branch together
+        const bool pruning = prune_streak > 0 && streak >= prune_streak;
+        const bool ends = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
+        if (__builtin_expect(__any(active & (pruning | ends)), 0)) {
+            if (active & pruning) {
                 const float *xs = live_x + (int64_t)s * d;
 #pragma unroll
                 for (int c = 0; c < L; ++c) x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
+                nprune += 1;
+                momentum_lane<L>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
+                nref = 0;
+                streak = 0;
             }
-            nprune += 1;
-            momentum_lane<L>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
-            nref = 0;
-            streak = 0;
+            const bool need = active && !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
+            if (need) {
+                float *wo = walk_x + (int64_t)m * d;
+#pragma unroll
+                for (int c = 0; c < L; ++c)
+                    if (VALID(c)) wo[a0 + c] = xo[c];
+                if (lead) {
+                    walk_logl[m] = out_l;
+                    // the walker's counts go straight to the block's totals (LDS)
+                    atomicAdd(&blk_cnt[0], (unsigned long long)outs);
+                    atomicAdd(&blk_cnt[1], (unsigned long long)steps);
+                    atomicAdd(&blk_cnt[2], (unsigned long long)nprune);
+                    if (nsave == 0) atomicAdd(&blk_cnt[3], 1ull);
+                }
+            }
+            // finished slots take the next walkers of the tile in slot order;
+            // every lane of every wavefront sees the same mask and computes the same ids
+            const uint32_t fin = (uint32_t)(__ballot(need) & 0xFFFFull);
+            if (need) {
+                m = next + __popc(fin & ((1u << slot) - 1u));
+                active = m < tile.m_end;
+                if (active) start_walker(m);
+            }
+            next += __popc(fin);
         }
-        const bool done = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
-        const bool need = active && done;
-        if (need && lead) {
-            walk_logl[m] = out_l;
-            c_outs += outs;
-            c_steps += steps;
-            c_prunes += nprune;
-            c_nosave += (nsave == 0) ? 1 : 0;
-        }
-        // finished slots take the next walkers of the tile in slot order; every
-        // lane of every wavefront sees the same mask and computes the same ids
-        const uint32_t fin = (uint32_t)(__ballot(need) & 0xFFFFull);
-        if (need) {
-            m = next + __popc(fin & ((1u << slot) - 1u));
-            active = m < tile.m_end;
-            if (active) start_walker(m);
-        }
-        next += __popc(fin);
     }
 
 #undef VALID
-    if (lead && c_steps > 0) {
-        atomicAdd(&blk_cnt[0], c_outs);
-        atomicAdd(&blk_cnt[1], c_steps);
-        atomicAdd(&blk_cnt[2], c_prunes);
-        atomicAdd(&blk_cnt[3], c_nosave);
-    }
     __syncthreads();
     if (threadIdx.x == 0 && blk_cnt[1] > 0) {
         atomicAdd(&acc->it_outs, blk_cnt[0]);
