@@ -95,6 +95,24 @@ def test_pipelined_run_matches_synchronous_run(torch):
     b.close()
 
 
+def test_reset_and_graph_replay_repeat_the_whole_run(torch):
+    """Engine.reset re-initialises the runs on the same arena: a whole run
+    replayed through the block graph captured before the reset gives the same
+    stats, bitwise, as the first run and as a fresh engine (the benchmark's and
+    the tuner's pass protocol)."""
+    cfgs = _small_mix()
+    a = _engine(cfgs)
+    s1 = a.run(poll_every=4, use_graph=True)
+    a.reset()
+    s2 = a.run(poll_every=4, use_graph=True)
+    b = _engine(cfgs)
+    s3 = b.run(poll_every=4)
+    for x, y, z in zip(s1, s2, s3):
+        assert x == y == z
+    a.close()
+    b.close()
+
+
 def test_checkpoint_and_resume_is_exact(torch):
     cfgs = _small_mix()
     a = _engine(cfgs)
