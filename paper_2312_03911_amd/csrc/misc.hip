@@ -202,32 +202,46 @@ init_points_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__r
 }
 
 // Walker outputs into the killed slots; dt update from out_frac; next iteration.
+// A work item is four consecutive coordinates of one walker's row (and, for the
+// row's first item, its log L and cluster label): the killed slot is read once
+// per item, the four loads of the row issue together, and the index arithmetic
+// stays in 32 bits.
 template <typename T>
-__device__ void scatter_points(void *arena, const RunDev &R, int64_t e0, int64_t stride) {
-    const int d = R.d, k = R.n_kill;
-    const int32_t *killed = at<int32_t>(arena, R.off_killed);
-    const T *wx = at<T>(arena, R.off_walk_x);
-    T *lx = at<T>(arena, R.off_live_x);
-    for (int64_t e = e0; e < (int64_t)k * d; e += stride) {
-        const int m = (int)(e / d), a = (int)(e % d);
-        lx[(int64_t)killed[m] * d + a] = wx[e];
-    }
+__device__ __forceinline__ void scatter_item(const RunDev &R, const int32_t *killed, const T *wx,
+                                             T *lx, int m, int c0) {
+    const int d = R.d;
+    const int slot = killed[m];
+    const T *src = wx + (int64_t)m * d + c0;
+    T v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (c0 + j < d) ? src[j] : T(0);
+    T *dst = lx + (int64_t)slot * d + c0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (c0 + j < d) dst[j] = v[j];
 }
 
 __global__ void replace_kernel(void *arena, const RunDev *__restrict__ runs) {
     const RunDev &R = runs[blockIdx.y];
     Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
-    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (R.prec == GGNS_FP64)
-        scatter_points<double>(arena, R, e0, stride);
-    else
-        scatter_points<float>(arena, R, e0, stride);
+    const int k = R.n_kill, nchunk = (R.d + 3) >> 2;
+    const int items = k * nchunk;
+    const int i0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     const int32_t *killed = at<int32_t>(arena, R.off_killed);
     const double *wl = at<double>(arena, R.off_walk_logl);
     double *ll = at<double>(arena, R.off_live_logl);
-    for (int64_t m = e0; m < R.n_kill; m += stride) ll[killed[m]] = wl[m];
+    const bool f64 = R.prec == GGNS_FP64;
+    for (int it = i0; it < items; it += stride) {
+        const int m = it / nchunk, c0 = (it - m * nchunk) << 2;
+        if (f64)
+            scatter_item<double>(R, killed, at<double>(arena, R.off_walk_x),
+                                 at<double>(arena, R.off_live_x), m, c0);
+        else
+            scatter_item<float>(R, killed, at<float>(arena, R.off_walk_x),
+                                at<float>(arena, R.off_live_x), m, c0);
+        if (c0 == 0) ll[killed[m]] = wl[m];
+    }
     if (R.cluster_mode) {
         // the new point joins the cluster its walker was spawned in; the
         // workgroup counts its joins in LDS and adds them with one atomic per
@@ -238,7 +252,7 @@ __global__ void replace_kernel(void *arena, const RunDev *__restrict__ runs) {
         ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
         for (int p = threadIdx.x; p < kClMax; p += blockDim.x) joins[p] = 0;
         __syncthreads();
-        for (int64_t m = e0; m < R.n_kill; m += stride) {
+        for (int m = i0; m < k; m += stride) {
             label[killed[m]] = scl[m];
             atomicAdd(&joins[scl[m]], 1);
         }
@@ -353,9 +367,10 @@ int launch_init_class(void *arena, const RunDev *runs_dev, const Tile *tiles, in
 }
 
 void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s) {
-    int bx = (max_kd + 1023) / 1024;
+    // about one four-coordinate item per thread for the largest run
+    int bx = (max_kd / 4 + 255) / 256;
     if (bx < 1) bx = 1;
-    if (bx > 64) bx = 64;
+    if (bx > 1024) bx = 1024;
     hipLaunchKernelGGL(replace_kernel, dim3(bx, n_runs), dim3(256), 0, s, arena, runs_dev);
 }
 
