@@ -117,6 +117,9 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.nprm = (int32_t)converted_size(R.var, D.d, R.dp);
         const int64_t prm_bytes = (int64_t)R.nprm * es;
         R.nprm_bytes_lds = (prm_bytes <= 48 * 1024) ? (int32_t)prm_bytes : 0;
+        // the mixture walk reads its staged block every step (at most
+        // kMaxComp (2 kMaxD + 4) doubles = 32.9 KB, so always staged)
+        if (R.var == VAR_GMM && R.nprm_bytes_lds == 0) return GGNS_EUNSUPPORTED;
         R.dead_cap = (int64_t)D.n_kill * D.max_iter + D.n_live;
         R.off_acc = off; off = align_up(off + (int64_t)sizeof(Acc));
         R.off_prm = off; off = align_up(off + prm_bytes);
@@ -178,6 +181,7 @@ struct ggns_ctx {
     int64_t n_params = 0;
     std::vector<Tile> tiles_host;
     std::vector<Class> walk_classes, init_classes;
+    int n_simd = 1024;   // SIMDs of the device (256 compute units x 4 on MI355X)
     int max_kd = 1;
     bool any_cluster = false, any_fp64 = false, any_fp32 = false;
     int max_live = 0;
@@ -239,6 +243,15 @@ void build_classes(ggns_ctx *c) {
         }
         w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
         w.lds = lds;
+        // a mixture class with more wavefronts than the device has SIMDs is
+        // bound by occupancy: its kernel reads the staged block every step
+        // instead of holding it in registers
+        if (w.kind == VAR_GMM) {
+            int64_t waves = 0;
+            for (int r : kv.second)
+                waves += ((int64_t)c->plan.runs[r].n_kill * c->plan.runs[r].G + 63) / 64;
+            if (waves > c->n_simd) w.kind = VAR_GMM_STAGED;
+        }
         c->walk_classes.push_back(w);
     }
     for (auto &kv : groups) {
@@ -293,6 +306,13 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
     c->arena_bytes = arena_bytes;
     c->params = params_dev;
     c->n_params = n_params;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            c->n_simd = 4 * cus;   // four SIMDs per compute unit
+    }
     build_classes(c);
     for (const RunDev &R : c->plan.runs) {
         if (R.cluster_mode) {

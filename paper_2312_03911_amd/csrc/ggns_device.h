@@ -244,11 +244,15 @@ struct ShellParams {
     }
 };
 
+// Mixture block: per component mu[dp], 1/sigma^2[dp], the log normaliser, padded
+// to a multiple of four elements.
+__host__ __device__ inline int gmm_stride(int dp) { return (2 * dp + 4) & ~3; }
+
 template <typename T, int C, int KM>
 struct GmmParams {
     T mu[KM][C], iv[KM][C], lnrm[KM];
     __device__ __forceinline__ void load(const T *prm, int dp, int a0) {
-        const int stride = 2 * dp + 1;
+        const int stride = gmm_stride(dp);
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
 #pragma unroll
@@ -259,7 +263,62 @@ struct GmmParams {
             lnrm[k] = prm[k * stride + 2 * dp];
         }
     }
+    __device__ __forceinline__ void row(int k, T (&m)[C], T (&v)[C]) const {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            m[c] = mu[k][c];
+            v[c] = iv[k][c];
+        }
+    }
 };
+
+template <typename T, int C>
+__device__ __forceinline__ void load_row(const T *p, T (&out)[C]);
+
+// The same block left where the walk staged it (LDS) and read at every
+// evaluation: 2 KM C fewer registers per lane, for walk classes with more
+// wavefronts than the chip has SIMDs, where occupancy decides the rate.
+template <typename T, int C, int KM>
+struct GmmParamsStaged {
+    const T *lane;   // component 0's mu at this lane's first coordinate
+    int stride, dp;
+    T lnrm[KM];
+    __device__ __forceinline__ void load(const T *prm, int dp_, int a0) {
+        dp = dp_;
+        stride = gmm_stride(dp_);
+        lane = prm + a0;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) lnrm[k] = prm[k * stride + 2 * dp_];
+    }
+    __device__ __forceinline__ void row(int k, T (&m)[C], T (&v)[C]) const {
+        load_row<T, C>(lane + k * stride, m);
+        load_row<T, C>(lane + k * stride + dp, v);
+    }
+};
+
+// C consecutive values from p, with 16-byte loads where C allows (the mixture
+// block's rows start on 16-byte boundaries for C a multiple of 4 in FP32 and
+// of 2 in FP64: its stride is a multiple of four elements and a0, dp are
+// multiples of C).
+template <typename T, int C>
+__device__ __forceinline__ void load_row(const T *p, T (&out)[C]) {
+    if constexpr (sizeof(T) == 4 && C % 4 == 0) {
+#pragma unroll
+        for (int c = 0; c < C; c += 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(p + c);
+            out[c] = v.x; out[c + 1] = v.y; out[c + 2] = v.z; out[c + 3] = v.w;
+        }
+    } else if constexpr (sizeof(T) == 8 && C % 2 == 0) {
+#pragma unroll
+        for (int c = 0; c < C; c += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(p + c);
+            out[c] = v.x; out[c + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c] = p[c];
+    }
+}
 
 template <typename T, int C>
 struct TorusParams {
@@ -401,18 +460,20 @@ __device__ __forceinline__ LikOut<T> lik_shells(const ShellParams<T, C, KM> &P, 
     return {l, pg, gg};
 }
 
-template <typename T, int C, int KM>
-__device__ __forceinline__ LikOut<T> lik_gmm(const GmmParams<T, C, KM> &P, int G, const T (&x)[C],
-                                             const T (&p)[C], T (&g)[C]) {
+template <typename T, int C, int KM, typename PT>
+__device__ __forceinline__ LikOut<T> lik_gmm(const PT &P, int G, const T (&x)[C], const T (&p)[C],
+                                             T (&g)[C]) {
     T q[KM];
     T u[KM][C];
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
+        T mu[C], iv[C];
+        P.row(k, mu, iv);
         q[k] = T(0);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const T r = x[c] - P.mu[k][c];
-            u[k][c] = r * P.iv[k][c];
+            const T r = x[c] - mu[c];
+            u[k][c] = r * iv[c];
             q[k] += r * u[k][c];
         }
     }
@@ -507,7 +568,10 @@ enum {
     VAR_GMM = 3,
     VAR_SHELLS8 = 4,
     VAR_GAUSS_FULL_BF16 = 5,
-    VAR_TORUS = 6
+    VAR_TORUS = 6,
+    // walk kernels only: the mixture with its block read from LDS every step
+    // (chosen per walk class, never a run's own variant)
+    VAR_GMM_STAGED = 7
 };
 
 __host__ __device__ inline int lik_variant(int kind, int K, int prec) {
@@ -535,6 +599,8 @@ template <typename T, int C>
 struct ParamsOf<T, C, VAR_GMM> { using type = GmmParams<T, C, kMaxComp>; };
 template <typename T, int C>
 struct ParamsOf<T, C, VAR_TORUS> { using type = TorusParams<T, C>; };
+template <typename T, int C>
+struct ParamsOf<T, C, VAR_GMM_STAGED> { using type = GmmParamsStaged<T, C, kMaxComp>; };
 
 template <typename T, int C, int VAR>
 __device__ __forceinline__ LikOut<T> lik_step(const typename ParamsOf<T, C, VAR>::type &P, int d,
@@ -543,7 +609,7 @@ __device__ __forceinline__ LikOut<T> lik_step(const typename ParamsOf<T, C, VAR>
     if constexpr (VAR == VAR_GAUSS_DIAG) return lik_gauss_diag<T, C>(P, G, x, p, g);
     else if constexpr (VAR == VAR_SHELLS2) return lik_shells<T, C, 2>(P, G, x, p, g);
     else if constexpr (VAR == VAR_SHELLS8) return lik_shells<T, C, kMaxComp>(P, G, x, p, g);
-    else if constexpr (VAR == VAR_GMM) return lik_gmm<T, C, kMaxComp>(P, G, x, p, g);
+    else if constexpr (VAR == VAR_GMM || VAR == VAR_GMM_STAGED) return lik_gmm<T, C, kMaxComp>(P, G, x, p, g);
     else if constexpr (VAR == VAR_TORUS) return lik_torus<T, C>(P, G, x, p, g);
     else if constexpr (VAR == VAR_GAUSS_FULL_BF16)
         return lik_gauss_full<T, C, true>(P.prm, d, a0, G, x, p, g, xch);
@@ -552,7 +618,8 @@ __device__ __forceinline__ LikOut<T> lik_step(const typename ParamsOf<T, C, VAR>
 
 // Component slots of a variant's converted block.
 __host__ __device__ inline int variant_slots(int var) {
-    return var == VAR_SHELLS2 ? 2 : ((var == VAR_SHELLS8 || var == VAR_GMM) ? kMaxComp : 1);
+    return var == VAR_SHELLS2 ? 2
+                              : ((var == VAR_SHELLS8 || var == VAR_GMM || var == VAR_GMM_STAGED) ? kMaxComp : 1);
 }
 
 // Elements of the converted parameter block (run precision) for a variant.
@@ -564,7 +631,7 @@ __host__ __device__ inline int64_t converted_size(int var, int d, int dp) {
         case VAR_GAUSS_FULL_BF16: return (int64_t)d + 1 + (int64_t)d * d;
         case VAR_SHELLS2: return 2 * ((int64_t)dp + 3);
         case VAR_SHELLS8: return kMaxComp * ((int64_t)dp + 3);
-        default: return kMaxComp * (2 * (int64_t)dp + 1);
+        default: return kMaxComp * (int64_t)gmm_stride(dp);
     }
 }
 

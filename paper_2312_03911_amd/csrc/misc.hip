@@ -65,7 +65,7 @@ __device__ void convert_params(const RunDev &R, const double *raw, T *out) {
     } else {
         for (int kk = 0; kk < slots; ++kk) {
             const double *mu = raw + kk * 2 * d, *sg = mu + d;
-            T *o = out + kk * (2 * dp + 1);
+            T *o = out + kk * gmm_stride(dp);
             for (int a = t; a < dp; a += nt) {
                 const bool on = kk < K && a < d;
                 o[a] = on ? (T)mu[a] : T(0);
@@ -79,6 +79,7 @@ __device__ void convert_params(const RunDev &R, const double *raw, T *out) {
                 } else {
                     o[2 * dp] = (T)(-INFINITY);
                 }
+                for (int a = 2 * dp + 1; a < gmm_stride(dp); ++a) o[a] = T(0);
             }
         }
     }

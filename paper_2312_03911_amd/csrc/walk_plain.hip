@@ -125,7 +125,7 @@ __device__ double plain_loglike(const RunDev &R, const double *prm, const double
         return l;
     }
     for (int c = 0; c < K; ++c) {
-        const double *o = prm + c * (2 * dp + 1);
+        const double *o = prm + c * gmm_stride(dp);
         double q = 0.0;
         for (int a = 0; a < d; ++a) q += o[dp + a] * (x(a) - o[a]) * (x(a) - o[a]);
         lp[c] = o[2 * dp] - 0.5 * q;
@@ -134,7 +134,7 @@ __device__ double plain_loglike(const RunDev &R, const double *prm, const double
     }
     for (int a = 0; a < d; ++a) gset(a, 0.0);
     for (int c = 0; c < K; ++c) {
-        const double *o = prm + c * (2 * dp + 1);
+        const double *o = prm + c * gmm_stride(dp);
         const double resp = exp(lp[c] - l);
         for (int a = 0; a < d; ++a) gadd(a, -resp * o[dp + a] * (x(a) - o[a]));
     }

@@ -123,7 +123,10 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 #pragma unroll
     for (int c = 0; c < C; ++c) valid[c] = a0 + c < d;
     typename ParamsOf<T, C, VAR>::type P;
-    P.load(prm, dp, a0);
+    if constexpr (VAR == VAR_GMM_STAGED)
+        P.load(reinterpret_cast<const T *>(smem), dp, a0);   // always staged (checked on the host)
+    else
+        P.load(prm, dp, a0);
 
     const double lstar = acc->lstar;
     const T dt = (T)acc->dt;
@@ -350,23 +353,31 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 
 // FP32 classes whose runs all have groups of 4, 8 or 16 lanes take the kernel
 // with the group size fixed; every other class reads it from the run.
+template <typename T, int C, int VAR>
+static void launch_gf(int gf, int n_tiles, size_t lds, hipStream_t s, void *arena,
+                      const RunDev *runs, const Tile *tiles) {
+    const dim3 grid(n_tiles), block(kWalkThreads);
+    if constexpr (std::is_same<T, float>::value) {
+        if (gf == 4)
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 4>), grid, block, lds, s, arena, runs, tiles);
+        else if (gf == 8)
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 8>), grid, block, lds, s, arena, runs, tiles);
+        else if (gf == 16)
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 16>), grid, block, lds, s, arena, runs, tiles);
+        else
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 0>), grid, block, lds, s, arena, runs, tiles);
+    } else {
+        hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 0>), grid, block, lds, s, arena, runs, tiles);
+    }
+}
+
 template <typename T, int C>
 static hipError_t launch_walk_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
                                 int var, int gf, size_t lds, hipStream_t s) {
-    constexpr bool f32 = std::is_same<T, float>::value;
-    if (f32 && gf == 4) {
-        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 4>), dim3(n_tiles),
-                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
-    } else if (f32 && gf == 8) {
-        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 8>), dim3(n_tiles),
-                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
-    } else if (f32 && gf == 16) {
-        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 16>), dim3(n_tiles),
-                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
-    } else {
-        GGNS_DISPATCH_KIND(var, hipLaunchKernelGGL((walk_valu_kernel<T, C, KIND_, 0>), dim3(n_tiles),
-                                                   dim3(kWalkThreads), lds, s, arena, runs, tiles));
-    }
+    if (var == VAR_GMM_STAGED)
+        launch_gf<T, C, VAR_GMM_STAGED>(gf, n_tiles, lds, s, arena, runs, tiles);
+    else
+        GGNS_DISPATCH_KIND(var, (launch_gf<T, C, KIND_>(gf, n_tiles, lds, s, arena, runs, tiles)));
     return hipGetLastError();
 }
 

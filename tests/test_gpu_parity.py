@@ -278,6 +278,27 @@ def test_batch64_sampled_runs_match_oracle(torch, orc):
     eng.close()
 
 
+def test_staged_mixture_walk_matches_oracle(torch, orc):
+    """A mixture walk class with more wavefronts than the device has SIMDs
+    (three d = 64 runs of 4000 live points: 3 x 2000 walkers x 16 lanes = 1500
+    wavefronts against 1024 SIMDs) runs the kernel that reads the parameter
+    block from LDS at every step; two of its runs follow the oracle step by step."""
+    cfgs = inputs.replicate(inputs.config_gmm(seed=53), 3, base_seed=53)
+    eng = _engine(cfgs)
+    checks = {r: _prepare_trace(torch, eng, orc, r, 10) for r in (0, 2)}
+    eng.evidence_update()
+    for o, _ in checks.values():
+        o.evidence_update()
+    torch.cuda.synchronize()
+    eng.hss_walk()
+    for o, _ in checks.values():
+        o.hss_walk()
+    torch.cuda.synchronize()
+    for r, (o, trace) in checks.items():
+        _compare_trace(torch, orc, eng, r, o, trace, 1e-4, 1e-4)
+    eng.close()
+
+
 @pytest.mark.parametrize("name,make,tol,tau", CASES, ids=[c[0] for c in CASES])
 def test_loglike_and_adjoint_match_oracle(torch, orc, name, make, tol, tau):
     cfg = make()
