@@ -136,6 +136,7 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.off_live_logl = off; off = align_up(off + (int64_t)D.n_live * 8);
         R.off_killed = off; off = align_up(off + (int64_t)D.n_kill * 4);
         R.off_surv = off; off = align_up(off + (int64_t)(D.n_live - D.n_kill) * 4);
+        R.off_surv_sorted = off; off = align_up(off + (int64_t)(D.n_live - D.n_kill) * 4);
         R.off_start = off; off = align_up(off + (int64_t)D.n_kill * 4);
         R.off_walk_x = off; off = align_up(off + (int64_t)D.n_kill * D.d * es);
         R.off_walk_logl = off; off = align_up(off + (int64_t)D.n_kill * 8);

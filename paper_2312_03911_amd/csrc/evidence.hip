@@ -154,6 +154,60 @@ __device__ double block_sum_once(double v, double *sc) {
 // update9 in batch form), with its n log L held E per thread: termination
 // test, kill order, dead records and evidence, volumes, survivors.  The run's
 // accumulators are read once, at the start, next to the log L loads.
+// The n log L of a run in slot order as (key, slot) pairs, E per thread.
+template <int E>
+__device__ __forceinline__ void load_pairs(const double *ll, int n, unsigned long long (&kk)[E],
+                                           int (&ss)[E], double &vmax, bool &bad) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = E * threadIdx.x + e;
+        if (i < n) {
+            const double v = ll[i];
+            bad = bad | isnan(v);
+            vmax = v > vmax ? v : vmax;
+            kk[e] = order_key(v);
+            ss[e] = i;
+        } else {
+            kk[e] = ~0ull;
+            ss[e] = 0x7FFFFFFF;
+        }
+    }
+}
+
+// Pairs (log L key, slot) of the list entries slots[i], i < m, two per thread.
+__device__ __forceinline__ void gather_pairs(const double *ll, const int32_t *slots, int m,
+                                             unsigned long long (&kk)[2], int (&ss)[2],
+                                             double &vmax, bool &bad) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int i = 2 * threadIdx.x + e;
+        if (i < m) {
+            const int sl = slots[i];
+            const double v = ll[sl];
+            bad = bad | isnan(v);
+            vmax = v > vmax ? v : vmax;
+            kk[e] = order_key(v);
+            ss[e] = sl;
+        } else {
+            kk[e] = ~0ull;
+            ss[e] = 0x7FFFFFFF;
+        }
+    }
+}
+
+// Entries of the ascending (key, slot) list lk/ls[0, m) smaller than (kv, sv)
+// (m <= 4095; the pairs are distinct, so no entry equals it).
+__device__ __forceinline__ int count_below(const unsigned long long *lk, const int *ls, int m,
+                                           unsigned long long kv, int sv) {
+    int pos = 0;
+#pragma unroll
+    for (int step = 2048; step > 0; step >>= 1) {
+        const int q = pos + step;
+        if (q <= m && kv_greater(kv, sv, lk[q - 1], ls[q - 1])) pos = q;
+    }
+    return pos;
+}
+
 template <int E>
 __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_sweep,
                               unsigned long long *key, int *slot, unsigned char *dead_flag,
@@ -165,19 +219,20 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
     int ss[E];
     double vmax = -INFINITY;
     bool bad = false;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = E * t + e;
-        if (i < n) {
-            const double v = ll[i];
-            bad = bad | isnan(v);
-            vmax = v > vmax ? v : vmax;
-            kk[e] = order_key(v);
-            ss[e] = i;
-        } else {
-            kk[e] = ~0ull;
-            ss[e] = 0x7FFFFFFF;
-        }
+    // Large runs (E = 4) whose previous kill left its order behind: the k new
+    // points are the only unsorted ones (the survivors' log L are unchanged
+    // since that kill), so they are sorted alone (2048 entries) and merged with
+    // the survivors' list; the result is the same total order as the full sort
+    unsigned long long ka[2], kb[2];
+    int sa[2], sb[2];
+    bool merge = false;
+    if constexpr (E == 4)
+        merge = R.cluster_mode == 0 && acc->order_ok != 0 && k <= 2048 && n - k <= 2048;
+    if (merge) {
+        gather_pairs(ll, at<int32_t>(arena, R.off_killed), k, ka, sa, vmax, bad);
+        gather_pairs(ll, at<int32_t>(arena, R.off_surv_sorted), n - k, kb, sb, vmax, bad);
+    } else {
+        load_pairs<E>(ll, n, kk, ss, vmax, bad);
     }
     // the accumulator fields this launch reads (the termination test's and the
     // kill's), loaded once
@@ -215,7 +270,58 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
     double xl = a.log_xl_max;
     const int stop = termination_decision(R, &a, lmax, final_sweep, &xl);
     if (t == 0) acc->log_xl_max = xl;
-    sort_pairs<E>(kk, ss, key, slot);   // ends with a barrier
+    if (merge) {
+        // the survivors' list above the 2048-entry range the new points sort in;
+        // it must still be in order (no log L of a survivor changed), else the
+        // whole set is sorted after all
+        const int nb = n - k;
+        unsigned long long *bk = key + 2048;
+        int *bs = slot + 2048;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int i = 2 * t + e;
+            if (i < nb) {
+                bk[i] = kb[e];
+                bs[i] = sb[e];
+            }
+        }
+        __syncthreads();
+        bool unsorted = false;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int i = 2 * t + e;
+            if (i + 1 < nb) unsorted = unsorted | kv_greater(bk[i], bs[i], bk[i + 1], bs[i + 1]);
+        }
+        merge = __syncthreads_or(unsorted) == 0;
+        if (merge) {
+            sort_pairs<2>(ka, sa, key, slot);   // the new points, ascending in [0, k)
+            int pa[2], pb[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int i = 2 * t + e;
+                pa[e] = (i < k) ? i + count_below(bk, bs, nb, ka[e], sa[e]) : -1;
+                pb[e] = (i < nb) ? i + count_below(key, slot, k, kb[e], sb[e]) : -1;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (pa[e] >= 0) {
+                    key[pa[e]] = ka[e];
+                    slot[pa[e]] = sa[e];
+                }
+                if (pb[e] >= 0) {
+                    key[pb[e]] = kb[e];
+                    slot[pb[e]] = sb[e];
+                }
+            }
+            __syncthreads();
+        } else {
+            double vm2 = -INFINITY;
+            bool bad2 = false;
+            load_pairs<E>(ll, n, kk, ss, vm2, bad2);
+        }
+    }
+    if (!merge) sort_pairs<E>(kk, ss, key, slot);   // ends with a barrier
 
     const bool clm = R.cluster_mode != 0;
     ClusterTab *tab = clm ? at<ClusterTab>(arena, R.off_cltab) : nullptr;
@@ -317,6 +423,14 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
     for (int j = t; j < k; j += T) {
         killed[j] = slot[j];
         dead_flag[slot[j]] = 1;
+    }
+    if constexpr (E == 4) {
+        // the survivors in kill order, for the next iteration's merge
+        if (!clm && k <= 2048 && n - k <= 2048) {
+            int32_t *so = at<int32_t>(arena, R.off_surv_sorted);
+            for (int j = t; j < n - k; j += T) so[j] = slot[k + j];
+            if (t == 0) acc->order_ok = 1;
+        }
     }
     if (clm) return;   // cluster mode: cluster_group_kernel groups the survivors
     __syncthreads();

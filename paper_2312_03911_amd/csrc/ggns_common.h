@@ -47,6 +47,7 @@ struct RunDev {
     int32_t cluster_mode, cluster_kmax;
     int64_t off_label, off_cltab, off_members, off_knn, off_start_cl;
     int64_t off_knn_part, off_knn_part_s;   // per query and share: partial neighbour lists
+    int64_t off_surv_sorted;   // survivors of the last kill in (log L, slot) order
     int64_t off_fin;           // run summary: five FP64 partials per chunk of dead records
     int32_t fin_chunks, pad_fin;   // chunks of kFinChunk records covering dead_cap
 };
@@ -74,7 +75,8 @@ struct Acc {
     long long iter, evals, n_dead, steps_out, steps_in, prunes, nosave;
     unsigned long long it_outs, it_steps;
     int32_t state, summary_pending;
-    int32_t n_clusters, pad_acc;   // cluster indices in use (cluster mode)
+    int32_t n_clusters;            // cluster indices in use (cluster mode)
+    int32_t order_ok;              // 1: killed[] and surv_sorted[] hold the last kill's order
 };
 
 // A walk work item: walkers [m_begin, m_end) of one run.

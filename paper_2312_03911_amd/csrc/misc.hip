@@ -136,6 +136,8 @@ __global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, con
         // the torus reward is a likelihood only where S + c > 0 for every x: c > d
         if (R.kind == GGNS_LIK_TORUS && !(raw[2] > (double)R.d)) acc->state = GGNS_RUN_NONFINITE;
         acc->n_clusters = R.cluster_mode ? 1 : 0;
+        acc->order_ok = 0;
+        acc->summary_pending = 0;
         if (R.cluster_mode) {
             ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
             for (int p = 0; p < kClMax; ++p) {

@@ -348,6 +348,72 @@ def test_gauss2d_fp64_full_run_matches_oracle(torch, orc, term_kind):
         eng.close()
 
 
+def test_gauss2d_fp64_large_run_matches_oracle(torch, orc):
+    """A whole FP64 run at 4096 live points, where every kill after the first
+    sorts only the new points and merges them with the previous survivors'
+    order: the run reproduces the oracle's (iterations, evaluations, log Z,
+    dead records)."""
+    cfg = inputs.config_gauss2d(seed=2105, n_live=4096)
+    eng = _engine([cfg])
+    st = eng.run(poll_every=4)[0]
+    o = orc.Oracle(cfg).run()
+    assert st["state"] == o.st.state == 1
+    assert st["iter"] == o.st.iter and st["iter"] > 3
+    assert st["evals"] == o.st.evals
+    assert abs(st["log_z"] - o.st.lz) < 1e-9
+    dl, dw = eng.dead(0)
+    ol, ow = o.dead()
+    np.testing.assert_allclose(_np(dl), ol, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(_np(dw), ow, rtol=1e-12, atol=1e-11)
+    eng.close()
+
+
+# (n, k, perturb a survivor): the second kill merges the new points with the
+# first kill's survivor order when k <= 2048 and n - k <= 2048 and the
+# survivors are untouched; a changed survivor (or the sizes) make it sort all
+MERGE_SIZES = [(4096, 2048, False), (3000, 1500, False), (2500, 2000, False), (4095, 2048, False),
+               (2049, 1, False), (4000, 1900, False), (4096, 2048, True), (3000, 1500, True)]
+
+
+@pytest.mark.parametrize("n,k,perturb", MERGE_SIZES,
+                         ids=[f"n{n}_k{k}" + ("_perturbed" if p else "") for n, k, p in MERGE_SIZES])
+def test_second_kill_order_matches_oracle(torch, orc, n, k, perturb):
+    """Two kills on identical live sets with exact ties, the killed slots
+    refilled with new log L (tied among themselves and with survivors) before
+    the second: both kill orders, survivors, thresholds and evidences match the
+    oracle exactly."""
+    d = 3
+    cfg = inputs.RunConfig(kind="gauss_diag", d=d, n_live=n, n_kill=k, lo=-3.0, hi=3.0,
+                           precision="fp64", seed=90 + n + k,
+                           params=inputs.gauss_diag_params(np.zeros(d), np.ones(d)))
+    X = inputs.uniform_points(n, d, cfg.lo, cfg.hi, seed=n + 5 * k)
+    rng = np.random.default_rng(n * 11 + k)
+    L = np.round(rng.normal(-5.0, 2.0, size=n), 1)
+    eng = _engine([cfg])
+    o = orc.Oracle(cfg).init()
+    for kill in range(2):
+        eng.live_x(0).copy_(torch.from_numpy(X).to(eng.device))
+        eng.live_logl(0).copy_(torch.from_numpy(L).to(eng.device))
+        eng.write_vars(0, -math.inf, 0.0, 0.1, 0)
+        o.set_state(live_x=X, live_logl=L, log_z=-math.inf, log_x=0.0, dt=0.1, iteration=0)
+        eng.evidence_update()
+        o.evidence_update()
+        torch.cuda.synchronize()
+        killed = _np(eng.killed(0))
+        np.testing.assert_array_equal(killed, o.killed)
+        np.testing.assert_array_equal(_np(eng.survivors(0)), o.surv[:n - k])
+        st = eng.stats()[0]
+        assert st["lstar"] == o.st.lstar
+        assert abs(st["log_z"] - o.st.lz) < 1e-12 * max(1.0, abs(o.st.lz))
+        # refill the killed slots above the threshold, with ties
+        L = L.copy()
+        L[killed] = np.round(o.st.lstar + np.abs(rng.normal(0.0, 1.5, size=k)), 1)
+        if perturb:
+            surv = np.setdiff1d(np.arange(n), killed)
+            L[surv[rng.integers(len(surv))]] = np.round(L.max() + 1.0, 1)
+    eng.close()
+
+
 KILL_SIZES = [(4096, 2048, 8), (4096, 1, 3), (4095, 4094, 2), (2049, 1024, 5), (2048, 1000, 1),
               (1537, 1536, 3), (1025, 512, 2), (1024, 512, 4), (7, 3, 2), (2, 1, 1)]
 
