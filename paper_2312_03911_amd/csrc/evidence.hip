@@ -174,13 +174,14 @@ __device__ __forceinline__ void load_pairs(const double *ll, int n, unsigned lon
     }
 }
 
-// Pairs (log L key, slot) of the list entries slots[i], i < m, two per thread.
+// Pairs (log L key, slot) of the list entries slots[i], i < m, H per thread.
+template <int H>
 __device__ __forceinline__ void gather_pairs(const double *ll, const int32_t *slots, int m,
-                                             unsigned long long (&kk)[2], int (&ss)[2],
+                                             unsigned long long (&kk)[H], int (&ss)[H],
                                              double &vmax, bool &bad) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int i = 2 * threadIdx.x + e;
+    for (int e = 0; e < H; ++e) {
+        const int i = H * threadIdx.x + e;
         if (i < m) {
             const int sl = slots[i];
             const double v = ll[sl];
@@ -219,18 +220,21 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
     int ss[E];
     double vmax = -INFINITY;
     bool bad = false;
-    // Large runs (E = 4) whose previous kill left its order behind: the k new
-    // points are the only unsorted ones (the survivors' log L are unchanged
-    // since that kill), so they are sorted alone (2048 entries) and merged with
-    // the survivors' list; the result is the same total order as the full sort
-    unsigned long long ka[2], kb[2];
-    int sa[2], sb[2];
+    // Runs of more than 1024 live points (E = 2, 4) whose previous kill left
+    // its order behind: the k new points are the only unsorted ones (the
+    // survivors' log L are unchanged since that kill), so they are sorted alone
+    // (512 E entries) and merged with the survivors' list; the result is the
+    // same total order as the full sort
+    constexpr int H = (E >= 2) ? E / 2 : 1;   // pairs per thread of each list
+    constexpr int SN = 1024 * H;                // entries of the new points' sort
+    unsigned long long ka[H], kb[H];
+    int sa[H], sb[H];
     bool merge = false;
-    if constexpr (E == 4)
-        merge = R.cluster_mode == 0 && acc->order_ok != 0 && k <= 2048 && n - k <= 2048;
+    if constexpr (E >= 2)
+        merge = R.cluster_mode == 0 && acc->order_ok != 0 && k <= SN && n - k <= SN;
     if (merge) {
-        gather_pairs(ll, at<int32_t>(arena, R.off_killed), k, ka, sa, vmax, bad);
-        gather_pairs(ll, at<int32_t>(arena, R.off_surv_sorted), n - k, kb, sb, vmax, bad);
+        gather_pairs<H>(ll, at<int32_t>(arena, R.off_killed), k, ka, sa, vmax, bad);
+        gather_pairs<H>(ll, at<int32_t>(arena, R.off_surv_sorted), n - k, kb, sb, vmax, bad);
     } else {
         load_pairs<E>(ll, n, kk, ss, vmax, bad);
     }
@@ -271,15 +275,15 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
     const int stop = termination_decision(R, &a, lmax, final_sweep, &xl);
     if (t == 0) acc->log_xl_max = xl;
     if (merge) {
-        // the survivors' list above the 2048-entry range the new points sort in;
-        // it must still be in order (no log L of a survivor changed), else the
-        // whole set is sorted after all
+        // the survivors' list above the range the new points sort in; it must
+        // still be in order (no log L of a survivor changed), else the whole
+        // set is sorted after all
         const int nb = n - k;
-        unsigned long long *bk = key + 2048;
-        int *bs = slot + 2048;
+        unsigned long long *bk = key + SN;
+        int *bs = slot + SN;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int i = 2 * t + e;
+        for (int e = 0; e < H; ++e) {
+            const int i = H * t + e;
             if (i < nb) {
                 bk[i] = kb[e];
                 bs[i] = sb[e];
@@ -288,23 +292,23 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
         __syncthreads();
         bool unsorted = false;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int i = 2 * t + e;
+        for (int e = 0; e < H; ++e) {
+            const int i = H * t + e;
             if (i + 1 < nb) unsorted = unsorted | kv_greater(bk[i], bs[i], bk[i + 1], bs[i + 1]);
         }
         merge = __syncthreads_or(unsorted) == 0;
         if (merge) {
-            sort_pairs<2>(ka, sa, key, slot);   // the new points, ascending in [0, k)
-            int pa[2], pb[2];
+            sort_pairs<H>(ka, sa, key, slot);   // the new points, ascending in [0, k)
+            int pa[H], pb[H];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int i = 2 * t + e;
+            for (int e = 0; e < H; ++e) {
+                const int i = H * t + e;
                 pa[e] = (i < k) ? i + count_below(bk, bs, nb, ka[e], sa[e]) : -1;
                 pb[e] = (i < nb) ? i + count_below(key, slot, k, kb[e], sb[e]) : -1;
             }
             __syncthreads();
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
+            for (int e = 0; e < H; ++e) {
                 if (pa[e] >= 0) {
                     key[pa[e]] = ka[e];
                     slot[pa[e]] = sa[e];
@@ -424,9 +428,9 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
         killed[j] = slot[j];
         dead_flag[slot[j]] = 1;
     }
-    if constexpr (E == 4) {
+    if constexpr (E >= 2) {
         // the survivors in kill order, for the next iteration's merge
-        if (!clm && k <= 2048 && n - k <= 2048) {
+        if (!clm && k <= SN && n - k <= SN) {
             int32_t *so = at<int32_t>(arena, R.off_surv_sorted);
             for (int j = t; j < n - k; j += T) so[j] = slot[k + j];
             if (t == 0) acc->order_ok = 1;

@@ -348,12 +348,13 @@ def test_gauss2d_fp64_full_run_matches_oracle(torch, orc, term_kind):
         eng.close()
 
 
-def test_gauss2d_fp64_large_run_matches_oracle(torch, orc):
-    """A whole FP64 run at 4096 live points, where every kill after the first
-    sorts only the new points and merges them with the previous survivors'
-    order: the run reproduces the oracle's (iterations, evaluations, log Z,
-    dead records)."""
-    cfg = inputs.config_gauss2d(seed=2105, n_live=4096)
+@pytest.mark.parametrize("n", [2000, 4096])
+def test_gauss2d_fp64_large_run_matches_oracle(torch, orc, n):
+    """Whole FP64 runs at 2000 and 4096 live points, where every kill after
+    the first sorts only the new points and merges them with the previous
+    survivors' order: the runs reproduce the oracle's (iterations, evaluations,
+    log Z, dead records)."""
+    cfg = inputs.config_gauss2d(seed=2105 + n, n_live=n)
     eng = _engine([cfg])
     st = eng.run(poll_every=4)[0]
     o = orc.Oracle(cfg).run()
@@ -369,10 +370,13 @@ def test_gauss2d_fp64_large_run_matches_oracle(torch, orc):
 
 
 # (n, k, perturb a survivor): the second kill merges the new points with the
-# first kill's survivor order when k <= 2048 and n - k <= 2048 and the
-# survivors are untouched; a changed survivor (or the sizes) make it sort all
+# first kill's survivor order when both lists fit the sort of the new points
+# (1024 entries up to 2048 live points, 2048 above) and the survivors are
+# untouched; a changed survivor (or the sizes) make it sort all
 MERGE_SIZES = [(4096, 2048, False), (3000, 1500, False), (2500, 2000, False), (4095, 2048, False),
-               (2049, 1, False), (4000, 1900, False), (4096, 2048, True), (3000, 1500, True)]
+               (2049, 1, False), (4000, 1900, False), (4096, 2048, True), (3000, 1500, True),
+               (2000, 1000, False), (2048, 1024, False), (1500, 500, False), (1100, 50, False),
+               (2000, 1000, True)]
 
 
 @pytest.mark.parametrize("n,k,perturb", MERGE_SIZES,
