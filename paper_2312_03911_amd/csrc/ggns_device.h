@@ -431,8 +431,17 @@ __device__ __forceinline__ LikOut<T> lik_shells(const ShellParams<T, C, KM> &P, 
         lp[k] = P.lnrm[k] - T(0.5) * e * e * P.iw2[k];
         lmax = lp[k] > lmax ? lp[k] : lmax;
     }
+    if constexpr (KM == 2) {
+        // the larger component's term is exp(0) = 1: one exponential, of
+        // -|lp0 - lp1| (= the smaller one's lp - lmax, exactly)
+        const T dl = lp[0] - lp[1];
+        const T e = m_exp(-fabs(dl));
+        ek[0] = (dl >= T(0)) ? T(1) : e;
+        ek[1] = (dl >= T(0)) ? e : T(1);
+    } else {
 #pragma unroll
-    for (int k = 0; k < KM; ++k) ek[k] = m_exp(lp[k] - lmax);
+        for (int k = 0; k < KM; ++k) ek[k] = m_exp(lp[k] - lmax);
+    }
     // the terms are >= 0, so starting from the first equals adding it to zero
     T sum = ek[0];
 #pragma unroll
