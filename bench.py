@@ -172,6 +172,34 @@ def rng_rate(torch, L) -> float:
     return best
 
 
+def probe_rates(torch, L) -> dict:
+    """TFLOP/s this build reaches on the vector ALU (FP32 FMA chains, one FMA
+    per lane and instruction, as the walks are compiled) and on the BF16 matrix
+    cores (the walk's 16x16x32 MFMA), at eight wavefronts per SIMD: best of
+    three launches of ggns_probe_valu / ggns_probe_mfma after a warm-up."""
+    import ctypes as C
+    blocks = 2048
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda:0")
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {}
+    for name, fn, iters, flop_per_round in (
+            ("valu_fp32_fma", L.ggns_probe_valu, 4096, blocks * 256 * 16.0),
+            ("mfma_bf16", L.ggns_probe_mfma, 2048, blocks * 4 * 4 * 16384.0)):
+        if fn(blocks, 8, 0.5, 0.25, out.data_ptr(), s) != 0:
+            raise RuntimeError(f"{name} probe failed")
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        best = 0.0
+        for _ in range(3):
+            a.record()
+            fn(blocks, iters, 0.5, 0.25, out.data_ptr(), s)
+            b.record()
+            b.synchronize()
+            best = max(best, flop_per_round * iters / (a.elapsed_time(b) / 1e3) / 1e12)
+        res[name] = best
+    return res
+
+
 def _oracle_sample(O, cfgs, budget_s: float):
     """The workload's runs in order (cycling if they finish early) until the
     budget is used; a run cut by the budget counts the iterations it did.
@@ -426,7 +454,8 @@ def main():
     steps_total = sum(s["steps_out"] + s["steps_in"] for s in stats)
     out_frac = sum(s["steps_out"] for s in stats) / max(steps_total, 1)
     r_rng = rng_rate(torch, eng.L)
-    t_valu = t_mfma = t_bound = 0.0
+    reach = probe_rates(torch, eng.L)
+    t_valu = t_mfma = t_bound = t_reach = 0.0
     flops_valu = flops_mfma = normals = 0.0
     for c, s in zip(cfgs, stats):
         e = s["steps_out"] + s["steps_in"]
@@ -439,6 +468,10 @@ def main():
         t_valu += tv
         t_mfma += tm
         t_bound += max(tv, tm)
+        # the same bound at the rates the probes reach (FP32 vector and BF16
+        # matrix cores; FP64 runs keep the published vector peak)
+        pv_r = pv if c.precision == "fp64" else reach["valu_fp32_fma"] * 1e12
+        t_reach += max(fv / pv_r + c.d * e / rr, fm / (reach["mfma_bf16"] * 1e12))
         flops_valu += fv
         flops_mfma += fm
         normals += c.d * e
@@ -487,7 +520,9 @@ def main():
                      "valu_flops_per_step": flops_valu, "mfma_flops_per_step": flops_mfma,
                      "normals_per_step": normals, "normals_per_s_peak": r_rng,
                      "t_bound_ms": 1e3 * t_bound, "t_valu_ms": 1e3 * t_valu,
-                     "t_mfma_ms": 1e3 * t_mfma},
+                     "t_mfma_ms": 1e3 * t_mfma,
+                     "probe_tflops": reach,
+                     "frac_of_probed_rates": t_reach / walk_time_s},
         "accuracy": {"noise": "per component",
                      "logz_minus_closed_form_mean": float(np.mean(dz)),
                      "logz_minus_closed_form_sd": float(np.std(dz)),

@@ -346,6 +346,23 @@ int ggns_noise_normals(uint64_t seed, int32_t iteration, int32_t n_walkers, int3
                        int32_t steps, float *normals_dev, uint32_t *words_dev, float *checksum_dev,
                        void *stream);
 
+/* Device-rate probes, for the roofline: the rates this build reaches on the
+ * vector ALU and on the matrix cores, beside the published peaks.  `blocks`
+ * workgroups of 256 threads, each thread running `iters` rounds.
+ * ggns_probe_valu: eight independent FP32 chains v <- fma(v, a, b) per
+ * thread, started at v = (lane mod 64) / 64 + chain (16 iters FLOP per
+ * thread; the walk's compilation: one FMA per lane and instruction).
+ * ggns_probe_mfma: four independent v_mfma_f32_16x16x32_bf16 accumulations
+ * per wavefront with every A entry a and every B entry b rounded to BF16
+ * (16384 iters FLOP per accumulator and wavefront); each accumulator entry
+ * gains 32 a b per round.
+ * out_dev[thread] = the sum of the thread's chains or accumulator entries;
+ * out_dev holds blocks * 256 floats, caller-owned device memory.  Enqueued on
+ * `stream`.  GGNS_EINVAL for blocks outside [1, 2^20], iters < 0 or a null
+ * out_dev. */
+int ggns_probe_valu(int32_t blocks, int32_t iters, float a, float b, float *out_dev, void *stream);
+int ggns_probe_mfma(int32_t blocks, int32_t iters, float a, float b, float *out_dev, void *stream);
+
 void ggns_free(ggns_ctx *ctx);
 
 const char *ggns_status_string(int code);

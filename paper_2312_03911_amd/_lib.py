@@ -19,7 +19,8 @@ SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update
            "ggns_run_layout", "ggns_read_stats", "ggns_read_stats_async", "ggns_write_vars",
            "ggns_set_trace", "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
            "ggns_noise_normals", "ggns_set_dead_x", "ggns_ext_workspace_bytes", "ggns_ext_buffers",
-           "ggns_ext_begin", "ggns_ext_step", "ggns_free", "ggns_status_string")
+           "ggns_ext_begin", "ggns_ext_step", "ggns_probe_valu", "ggns_probe_mfma", "ggns_free",
+           "ggns_status_string")
 
 
 class ggns_run_desc(C.Structure):
@@ -101,6 +102,9 @@ def load() -> C.CDLL:
         L.ggns_hss_walk_plain.argtypes = [vp, vp, i64, vp]
         L.ggns_noise_normals.argtypes = [C.c_uint64, i32, i32, i32, i32, vp, vp, vp, vp]
         L.ggns_noise_normals.restype = C.c_int
+        for name in ("ggns_probe_valu", "ggns_probe_mfma"):
+            getattr(L, name).argtypes = [i32, i32, C.c_float, C.c_float, vp, vp]
+            getattr(L, name).restype = C.c_int
         L.ggns_set_dead_x.argtypes = [vp, i32, vp, i64]
         L.ggns_set_dead_x.restype = C.c_int
         L.ggns_ext_workspace_bytes.argtypes = [vp, i32]

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libggns.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "walk_valu.hip", "walk_mfma.hip", "walk_plain.hip", "clusters.hip", "evidence.hip", "misc.hip"]
+SOURCES = ["api.hip", "walk_valu.hip", "walk_mfma.hip", "walk_plain.hip", "clusters.hip", "evidence.hip", "misc.hip",
+           "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -73,3 +73,13 @@ def test_null_context_rejected():
     assert L.ggns_evidence_update(None, 0, None) == _lib.GGNS_ESTATE
     assert L.ggns_replace_dead(None, None) == _lib.GGNS_ESTATE
     assert L.ggns_status_string(_lib.GGNS_EINVAL) == b"invalid argument"
+
+
+def test_probe_arguments_are_checked():
+    """The device-rate probes reject bad sizes before touching the device."""
+    L = _lib.load()
+    for fn in (L.ggns_probe_valu, L.ggns_probe_mfma):
+        assert fn(0, 10, 0.5, 0.25, 8, None) == _lib.GGNS_EINVAL
+        assert fn((1 << 20) + 1, 10, 0.5, 0.25, 8, None) == _lib.GGNS_EINVAL
+        assert fn(4, -1, 0.5, 0.25, 8, None) == _lib.GGNS_EINVAL
+        assert fn(4, 10, 0.5, 0.25, None, None) == _lib.GGNS_EINVAL
