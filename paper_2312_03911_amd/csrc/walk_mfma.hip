@@ -13,7 +13,7 @@
 // its dp/W rows of P, as ready-made BF16 A operands, in registers for the whole
 // walk.  Within a wavefront lane l serves walker slot l % 16 and owns the
 // L = dp / (4W) consecutive dimensions a0 = w dp/W + (l/16) L ... of it,
-// holding x, p, mu and y = P r for them in registers.  With the output rows
+// holding x, p, mu, y = P r and the reservoir point for them in registers.  With the output rows
 // relabelled (row 4q+j of the wavefront's M-block mb is dimension
 // w dp/W + q L + 4 mb + j) the accumulator lands on the lane that owns those
 // dimensions.  Per step each lane writes its BF16 residuals to LDS, every
@@ -21,7 +21,8 @@
 // rows padded against bank conflicts), and the per-wavefront partial sums of
 // r.y, p.y, y.y and the box test meet in LDS; two workgroup barriers a step.
 // All wavefronts take the same decisions for a walker from the same sums, and
-// refill finished slots from the tile in slot order, so no atomics are needed.
+// refill finished slots from the tile in slot order, so the refill needs no
+// atomics.
 #include "ggns_device.h"
 
 namespace ggns {
