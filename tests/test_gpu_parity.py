@@ -348,12 +348,12 @@ def test_gauss2d_fp64_full_run_matches_oracle(torch, orc, term_kind):
         eng.close()
 
 
-@pytest.mark.parametrize("n", [2000, 4096])
+@pytest.mark.parametrize("n", [1000, 2000, 4096])
 def test_gauss2d_fp64_large_run_matches_oracle(torch, orc, n):
-    """Whole FP64 runs at 2000 and 4096 live points, where every kill after
-    the first sorts only the new points and merges them with the previous
-    survivors' order: the runs reproduce the oracle's (iterations, evaluations,
-    log Z, dead records)."""
+    """Whole FP64 runs at 1000, 2000 and 4096 live points (above 1024 every kill
+    after the first sorts only the new points and merges them with the previous
+    survivors' order): the runs reproduce the oracle's (iterations,
+    evaluations, log Z, dead records)."""
     cfg = inputs.config_gauss2d(seed=2105 + n, n_live=n)
     eng = _engine([cfg])
     st = eng.run(poll_every=4)[0]
@@ -369,14 +369,16 @@ def test_gauss2d_fp64_large_run_matches_oracle(torch, orc, n):
     eng.close()
 
 
-# (n, k, perturb a survivor): the second kill merges the new points with the
-# first kill's survivor order when both lists fit the sort of the new points
-# (1024 entries up to 2048 live points, 2048 above) and the survivors are
-# untouched; a changed survivor (or the sizes) make it sort all
+# (n, k, perturb a survivor): above 1024 live points the second kill merges
+# the new points with the first kill's survivor order when both lists fit the
+# sort of the new points (1024 entries up to 2048 live points, 2048 above) and
+# the survivors are untouched; a changed survivor, the sizes or a live set of
+# at most 1024 make it sort all
 MERGE_SIZES = [(4096, 2048, False), (3000, 1500, False), (2500, 2000, False), (4095, 2048, False),
                (2049, 1, False), (4000, 1900, False), (4096, 2048, True), (3000, 1500, True),
                (2000, 1000, False), (2048, 1024, False), (1500, 500, False), (1100, 50, False),
-               (2000, 1000, True)]
+               (2000, 1000, True), (1000, 500, False), (1024, 512, False), (700, 300, False),
+               (600, 50, False), (64, 32, False), (1000, 500, True)]
 
 
 @pytest.mark.parametrize("n,k,perturb", MERGE_SIZES,
