@@ -488,7 +488,7 @@ def main():
     dz = [s["log_z"] - t for s, t in zip(stats, truth)]
     zs = [d / max(s["sigma_kl"], 1e-12) for d, s in zip(dz, stats)]
     res = {
-        "metric": "likelihood+grad evals/sec in HSS walks (logZ error stated); roofline fraction",
+        "metric": "likelihood+grad evals/sec in HSS walks at stated logZ error; roofline fraction",
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
