@@ -191,7 +191,10 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     if (active) start_walker(m);
     const bool walker_noise = R.noise_mode != 0;
 
-    while (__any(active)) {
+    // the wavefront's walkers can only end inside the rare-event branch, so
+    // whether any is left is a uniform flag updated there, not a vote per step
+    bool any_left = __any(active);
+    while (any_left) {
         // this step's noise and reservoir draw do not depend on the step, so
         // they are generated first and overlap the reduction latency
         T eps_c[C];
@@ -305,7 +308,9 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         // the same on every lane of a group, so groups enter whole
         const bool pruning = prune_streak > 0 && streak >= prune_streak;
         const bool ends = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
-        if (__builtin_expect(active & (pruning | ends), 0)) {
+        const bool rare = active & (pruning | ends);
+        if (__builtin_expect(__any(rare), 0)) {
+          if (rare) {
             if (pruning) {
                 const T *xs = live_x + (int64_t)s * d;
 #pragma unroll
@@ -336,6 +341,8 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 active = m < tile.m_end;
                 if (active) start_walker(m);
             }
+          }
+          any_left = __any(active);
         }
     }
 
