@@ -158,7 +158,10 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     if (active) start_walker(m);
     __syncthreads();
 
-    while (__any(active)) {
+    // slots can only end inside the rare-event branch, so whether any walker
+    // is left is a uniform flag updated there (the same in every wavefront)
+    bool any_left = __any(active);
+    while (any_left) {
         const uint32_t ures = res.next();
         // drift; BF16 residuals of the lane's dimensions to LDS
         bool vany = false;
@@ -316,6 +319,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 if (active) start_walker(m);
             }
             next += __popc(fin);
+            any_left = __any(active);
         }
     }
 
