@@ -243,7 +243,6 @@ def cpu_baseline(cfgs, budget_s: float = 12.0, budget_single_s: float = 6.0):
     bounded sample of the workload, and single-threaded on a shorter one (its
     results are identical: the random streams are counter-based)."""
     import oracle.oracle as O
-    O.build(force=False)
     cores = O.num_threads()
     ev, whole, its, last, dt, done = _oracle_sample(O, cfgs, budget_s)
     O.set_threads(1)

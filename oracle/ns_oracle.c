@@ -40,20 +40,30 @@
  *   R5  a zero or non-finite gradient reflects p -> -p.
  *   R6  leaving the prior box counts as outside and takes precedence; the
  *       momentum component of every violated axis is negated.
- *   R7  eps is drawn per component and applied to every walker at every step,
- *       after any reflection.  The algorithm writes eps ~ N(0,1); the other
- *       reading, one normal per walker and step (the first normal of that
- *       walker's step stream) scaling all components alike, is available as
- *       noise_mode = 1.
- *   R8  a point is saved when it is inside the slice and this walker has made
- *       at least min_ref reflections (per walker, not the batch minimum).
- *   R9  the saved set is per walker and sampled uniformly by a size-one
- *       reservoir (Vitter's Algorithm R).
+ *   R7  the noise eps of p *= (1 + delta_p eps): one normal per walker and
+ *       step (the first normal of that walker's step stream) scaling all
+ *       components alike (noise_mode 1, the default); per component
+ *       (noise_mode 0); or, as an option that is not the paper's formula, an
+ *       isotropic vector p += delta_p (|p| / sqrt d) eps (noise_mode 2).
+ *       Applied to every walker at every step, after any reflection.
+ *   R8  a point is saved when it is inside the slice and the batch minimum
+ *       of num_reflections has reached min_ref (save_mode 1, the algorithm's
+ *       condition with its "<" read as ">=", as the text of Section 3 and the
+ *       Appendix C table say); save_mode 0 uses the walker's own count.
+ *   R9  x_saved is sampled per walker: one uniform pick from the walker's
+ *       own saved points by a size-one reservoir (Vitter's Algorithm R;
+ *       draw_mode 0, the default), or the batch's saved points are pooled and
+ *       k points drawn uniformly with replacement (draw_mode 1).
  *   R10 empty saved set: output the last in-slice point, else the start point.
- *   R11 a walker stops at max_ref reflections, capped at n_steps_max steps;
- *       max_ref = 0 selects a fixed number of steps (n_steps_max).
+ *   R11 the walk loops while the batch minimum of num_reflections is below
+ *       max_ref (stop_mode 1, the algorithm's loop condition), for at most
+ *       n_steps_max steps; stop_mode 0 stops each walker at its own max_ref
+ *       (the Appendix C wording); max_ref = 0 selects a fixed number of steps
+ *       (n_steps_max) for every walker.
  *   R12 pruning: prune_streak consecutive outside steps reset the walker to its
- *       start point with fresh momentum and zero reflections.
+ *       start point with fresh momentum; the reflection count is kept under
+ *       the batch-minimum loop (it never decreases) and restarts from zero
+ *       when each walker stops on its own.
  *   R13 one dt per run, updated once per iteration from that run's out_frac.
  *   R14 dt_init is in units of the prior width.
  *   R16 batch kill with n_p = n, n-1, ..., n-k+1 (the Xbar convention).
@@ -339,7 +349,10 @@ typedef struct {
     int32_t noise_mode;         /* R7: 0 per component, 1 one normal per walker */
     int32_t cluster_mode;       /* C1-C10: 0 one cluster, 1 cluster recognition and spawning */
     int32_t cluster_kmax;       /* C2: largest neighbour count tried */
-    int32_t knn_fp32;           /* C2: neighbour distances in FP32 (the engine's precision) */
+    int32_t stop_mode;          /* R11: 0 each walker at its own max_ref, 1 batch minimum */
+    int32_t save_mode;          /* R8: 0 the walker's own count, 1 the batch minimum */
+    int32_t draw_mode;          /* R9: 0 one pick per walker, 1 pooled x_saved */
+    int32_t pad_desc;
 } orc_desc;
 
 enum { ST_ACTIVE = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3 };
@@ -373,6 +386,8 @@ typedef struct {
     int32_t *surv_off;     /* [ORC_CL_MAX + 1] */
     int32_t *start_cl;     /* [n_kill] cluster of each walker */
     int32_t n_clusters, n_splits;
+    int32_t split_kmax;    /* the largest neighbour count at which a split was made */
+    int32_t pad3;
 } orc_state;
 
 /* Step 1 of the outer loop: n_live uniform prior draws and their likelihoods
@@ -406,6 +421,7 @@ int orc_init(const orc_desc *D, const double *prm, orc_state *S)
         for (int i = 0; i < n; ++i) S->label[i] = 0;
         S->n_clusters = 1;
         S->n_splits = 0;
+        S->split_kmax = 0;
         S->clx[0] = 0.0;
         S->cn[0] = n;
     }
@@ -499,14 +515,13 @@ static void final_sweep(const orc_desc *D, orc_state *S)
  *   C1  cluster finding runs at the start of every iteration that goes on,
  *       once for each existing cluster (clusters created in this iteration
  *       are not re-examined in it);
- *   C2  for k = 2, 3, ...: link every point of the cluster to its k nearest
- *       other points of the cluster (squared Euclidean distance summed over
- *       coordinates in order with fused multiply-adds, in the engine's
- *       precision: FP64 for FP64 runs, FP32 otherwise; ties by slot),
- *       take the connected components of the undirected graph and their
- *       sizes; stop at the first k whose sorted sizes equal those of k - 1 and
- *       use that k's components.  k runs up to min(cluster_kmax, m - 1) for m
- *       points; if it never stops, or m < 3, the cluster stays whole;
+ *   C2  for k = 2, 3, ..., m - 1 (m points in the cluster): link every point
+ *       to its k nearest other points of the cluster (FP64 Euclidean
+ *       distance, ties by slot), take the connected components of the
+ *       undirected graph and their sizes; stop at the first k whose sorted
+ *       sizes equal those of k - 1 and use that k's components.  If it never
+ *       stops, or m < 3, the cluster stays whole.  cluster_kmax > 0 caps k
+ *       (an option; 0 runs the loop as the algorithm writes it);
  *   C3  the components, ordered by their smallest slot, become clusters: the
  *       first keeps the old index, the others take new indices (at most
  *       ORC_CL_MAX clusters; a split that would exceed it is not made); the
@@ -524,26 +539,13 @@ static void final_sweep(const orc_desc *D, orc_state *S)
  * ------------------------------------------------------------------------ */
 #define ORC_CL_MAX 64
 
-/* Squared distance summed over coordinates in order with fused multiply-adds
- * (s <- fma(t, t, s), correctly rounded), in the precision the engine ranks
- * neighbours in (the ranks are integer decisions): FP64 for FP64 runs, FP32
- * otherwise. */
-static int g_knn_fp32 = 0;
-
+/* Squared Euclidean distance (FP64). */
 static double dist2(const double *a, const double *b, int d)
 {
-    if (g_knn_fp32) {
-        float s = 0.0f;
-        for (int i = 0; i < d; ++i) {
-            float t = (float)a[i] - (float)b[i];
-            s = fmaf(t, t, s);
-        }
-        return (double)s;
-    }
     double s = 0.0;
     for (int i = 0; i < d; ++i) {
         double t = a[i] - b[i];
-        s = fma(t, t, s);
+        s += t * t;
     }
     return s;
 }
@@ -626,13 +628,24 @@ static void find_clusters(const orc_desc *D, orc_state *S)
         for (int i = 0; i < n; ++i)
             if (S->label[i] == p) idx[m++] = i;
         if (m < 3) continue;
-        int K = D->cluster_kmax < m - 1 ? D->cluster_kmax : m - 1;
-        if (K < 2) continue;
+        int kend = m - 1;
+        if (D->cluster_kmax > 0 && D->cluster_kmax < kend) kend = D->cluster_kmax;
+        if (kend < 2) continue;
+        /* the neighbour lists are computed for the first K neighbours and
+         * extended (K doubled) when k passes K: a list for K is a prefix of
+         * the list for any larger K, the order (distance, slot) being total */
+        int K = kend < 8 ? kend : 8;
         int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * K);
-        g_knn_fp32 = D->knn_fp32;
         knn_lists(S->live_x, d, idx, m, K, nb);
         int nprev = -1, found = 0, nc = 0;
-        for (int k = 2; k <= K; ++k) {
+        int k;
+        for (k = 2; k <= kend; ++k) {
+            if (k > K) {
+                K = 2 * K < kend ? 2 * K : kend;
+                free(nb);
+                nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * K);
+                knn_lists(S->live_x, d, idx, m, K, nb);
+            }
             nc = components(m, k, K, nb, root, sz);
             int same = (nc == nprev);
             for (int t = 0; same && t < nc; ++t) same = (sz[t] == prev[t]);
@@ -661,6 +674,7 @@ static void find_clusters(const orc_desc *D, orc_state *S)
         }
         S->n_clusters += nc - 1;
         S->n_splits += 1;
+        if (k > S->split_kmax) S->split_kmax = k;
         free(cnt);
     }
     free(idx); free(root); free(best); free(sz); free(prev);
@@ -746,12 +760,22 @@ int orc_evidence_update(const orc_desc *D, orc_state *S, int force_final)
 }
 
 /* One walker of the batched HSS walk (Algorithm GGNS HSS; Eq. reflection;
- * readings R4-R12).  Reports its outside steps, steps, prunes and whether it
- * saved no point. */
-static void walk_one(const orc_desc *D, const double *prm, orc_state *S, int m,
-                     int64_t *outs_o, int64_t *steps_o, int64_t *prunes_o, int64_t *nosave_o)
+ * readings R4-R12): its position, start, momentum, streams and counters. */
+typedef struct {
+    int m, s;
+    double *x, *x0, *p, *g, *eps, *out;
+    uint32_t *xs;          /* one xoshiro state per block of four coordinates (EPS) */
+    uint32_t xr[4];        /* reservoir stream (RES) */
+    double l0, l, out_l;   /* start log L, current log L, log L of the kept point */
+    int nref, streak, steps, outs, n_prune, outside, done;
+    int64_t nsave;
+} orc_walker;
+
+/* Start walker m: its start slot (uniform over the survivors, or cluster
+ * first, C5), x = x0, p ~ N(0, I) from stream P0, and its stream states. */
+static void walker_start(const orc_desc *D, orc_state *S, int m, orc_walker *W)
 {
-    int d = D->d, k = D->n_kill, nsurv = D->n_live - D->n_kill;
+    int d = D->d, nsurv = D->n_live - D->n_kill;
     uint32_t it = (uint32_t)S->iter;
     uint32_t u[4];
     stream_draw(D->seed, 0u, (uint32_t)m, it, TAG_START, 0u, u);
@@ -778,113 +802,239 @@ static void walk_one(const orc_desc *D, const double *prm, orc_state *S, int m,
         s = S->surv[(int)(((uint64_t)u[0] * (uint64_t)nsurv) >> 32)];
     }
     S->start[m] = s;
-    double *x = (double *)malloc(sizeof(double) * d);
-    double *x0 = (double *)malloc(sizeof(double) * d);
-    double *p = (double *)malloc(sizeof(double) * d);
-    double *g = (double *)malloc(sizeof(double) * d);
-    double *eps = (double *)malloc(sizeof(double) * (d + 4));
+    memset(W, 0, sizeof(*W));
+    W->m = m;
+    W->s = s;
+    W->x = (double *)malloc(sizeof(double) * d);
+    W->x0 = (double *)malloc(sizeof(double) * d);
+    W->p = (double *)malloc(sizeof(double) * d);
+    W->g = (double *)malloc(sizeof(double) * d);
+    W->eps = (double *)malloc(sizeof(double) * (d + 4));
     int nb = (d + 3) / 4;
-    uint32_t *xs = (uint32_t *)malloc(sizeof(uint32_t) * 4 * nb);
-    memcpy(x0, S->live_x + (int64_t)s * d, sizeof(double) * d);
-    memcpy(x, x0, sizeof(double) * d);
-    double l0 = S->live_logl[s];
-    normals_philox(D->seed, (uint32_t)m, it, TAG_P0, 0u, d, p);
+    W->xs = (uint32_t *)malloc(sizeof(uint32_t) * 4 * nb);
+    memcpy(W->x0, S->live_x + (int64_t)s * d, sizeof(double) * d);
+    memcpy(W->x, W->x0, sizeof(double) * d);
+    W->l0 = S->live_logl[s];
+    normals_philox(D->seed, (uint32_t)m, it, TAG_P0, 0u, d, W->p);
     for (int b = 0; b < nb; ++b) {
         stream_draw(D->seed, (uint32_t)b, (uint32_t)m, it, TAG_EPS, 0u, u);
-        xoshiro_seed(xs + 4 * b, u);
+        xoshiro_seed(W->xs + 4 * b, u);
     }
-    uint32_t xr[4];
     stream_draw(D->seed, 0u, (uint32_t)m, it, TAG_RES, 0u, u);
-    xoshiro_seed(xr, u);
+    xoshiro_seed(W->xr, u);
+    /* the output starts as the start point (reading R10's last fallback) */
+    W->out = S->out_x + (int64_t)m * d;
+    memcpy(W->out, W->x0, sizeof(double) * d);
+    W->out_l = W->l0;
+}
 
-    double *out = S->out_x + (int64_t)m * d;
-    memcpy(out, x0, sizeof(double) * d);
-    double out_l = l0;
-    int nref = 0, streak = 0, steps = 0, outs = 0, n_prune = 0;
-    int64_t nsave = 0;
+static void walker_free(orc_walker *W)
+{
+    free(W->x); free(W->x0); free(W->p); free(W->g); free(W->eps); free(W->xs);
+}
+
+/* One step of Algorithm GGNS HSS for one walker: x += p dt; log L and its
+ * gradient; outside test (box first, R6; then log L <= L*, R2); reflection
+ * (Eq. reflection with the normal at the outside point, R4/R5; box faces
+ * flip their axes, R6); noise p *= (1 + delta_p eps) (R7); reflection count,
+ * outside streak and pruning (R12: back to the start with fresh momentum;
+ * the reflection count restarts only when walkers stop one by one, so that
+ * the batch minimum of a whole-batch stop never decreases).  Returns the
+ * reservoir word of this step. */
+static uint32_t walker_step(const orc_desc *D, const double *prm, orc_state *S, orc_walker *W)
+{
+    int d = D->d, k = D->n_kill, m = W->m;
     double dt = S->dt, lstar = S->lstar;
-    while (steps < D->n_steps_max && (D->max_ref == 0 || nref < D->max_ref)) {
-        double l;
-        for (int a = 0; a < d; ++a) x[a] = x[a] + dt * p[a];
-        orc_loglike(D->kind, D->n_comp, prm, d, x, &l, g, D->bf16);
-        int box = 0;
-        for (int a = 0; a < d; ++a)
-            if (x[a] < D->lo || x[a] > D->hi) box = 1;
-        int outside = box || (l <= lstar);
-        if (S->trace_x && steps < S->trace_steps) {
-            int64_t row = (int64_t)steps * k + m;
-            memcpy(S->trace_x + row * d, x, sizeof(double) * d);
-            S->trace_logl[row] = l;
-            S->trace_out[row] = outside;
-        }
-        steps += 1;
-        if (outside) {
-            if (box) {
-                for (int a = 0; a < d; ++a)
-                    if (x[a] < D->lo || x[a] > D->hi) p[a] = -p[a];
+    double *x = W->x, *p = W->p, *g = W->g;
+    for (int a = 0; a < d; ++a) x[a] = x[a] + dt * p[a];
+    orc_loglike(D->kind, D->n_comp, prm, d, x, &W->l, g, D->bf16);
+    int box = 0;
+    for (int a = 0; a < d; ++a)
+        if (x[a] < D->lo || x[a] > D->hi) box = 1;
+    int outside = box || (W->l <= lstar);
+    if (S->trace_x && W->steps < S->trace_steps) {
+        int64_t row = (int64_t)W->steps * k + m;
+        memcpy(S->trace_x + row * d, x, sizeof(double) * d);
+        S->trace_logl[row] = W->l;
+        S->trace_out[row] = outside;
+    }
+    W->steps += 1;
+    if (outside) {
+        if (box) {
+            for (int a = 0; a < d; ++a)
+                if (x[a] < D->lo || x[a] > D->hi) p[a] = -p[a];
+        } else {
+            double pg = 0.0, gg = 0.0;
+            for (int a = 0; a < d; ++a) { pg += p[a] * g[a]; gg += g[a] * g[a]; }
+            if (isfinite(gg) && gg > 0.0) {
+                /* p' = p - 2 (p.n) n with n = g / |g| */
+                double f = 2.0 * pg / gg;
+                for (int a = 0; a < d; ++a) p[a] = p[a] - f * g[a];
             } else {
-                double pg = 0.0, gg = 0.0;
-                for (int a = 0; a < d; ++a) { pg += p[a] * g[a]; gg += g[a] * g[a]; }
-                if (isfinite(gg) && gg > 0.0) {
-                    /* p' = p - 2 (p.n) n with n = g / |g| */
-                    double f = 2.0 * pg / gg;
-                    for (int a = 0; a < d; ++a) p[a] = p[a] - f * g[a];
-                } else {
-                    for (int a = 0; a < d; ++a) p[a] = -p[a];
-                }
+                for (int a = 0; a < d; ++a) p[a] = -p[a];
             }
-        }
-        for (int b = 0; b < nb; ++b) {
-            uint32_t w[4];
-            for (int j = 0; j < 4; ++j) w[j] = orc_xoshiro_next(xs + 4 * b);
-            orc_box_muller4(w, eps + 4 * b);
-        }
-        for (int a = 0; a < d; ++a)
-            p[a] = p[a] * (1.0 + D->delta_p * (D->noise_mode ? eps[0] : eps[a]));
-        uint32_t ures = orc_xoshiro_next(xr);
-        nref += outside;
-        outs += outside;
-        streak = outside ? streak + 1 : 0;
-        if (!outside) {
-            if (nref >= D->min_ref) {
-                nsave += 1;
-                /* keep this point with probability 1/nsave (Algorithm R) */
-                if ((uint64_t)ures * (uint64_t)nsave < ((uint64_t)1 << 32)) {
-                    memcpy(out, x, sizeof(double) * d);
-                    out_l = l;
-                }
-            } else if (nsave == 0) {
-                memcpy(out, x, sizeof(double) * d);   /* last in-slice point */
-                out_l = l;
-            }
-        }
-        if (D->prune_streak > 0 && streak >= D->prune_streak) {
-            memcpy(x, x0, sizeof(double) * d);
-            n_prune += 1;
-            normals_philox(D->seed, (uint32_t)m, it, TAG_P0, (uint32_t)n_prune, d, p);
-            nref = 0;
-            streak = 0;
         }
     }
-    S->out_logl[m] = out_l;
-    *outs_o = outs;
-    *steps_o = steps;
-    *prunes_o = n_prune;
-    *nosave_o = (nsave == 0);
-    free(x); free(x0); free(p); free(g); free(eps); free(xs);
+    int nb = (d + 3) / 4;
+    for (int b = 0; b < nb; ++b) {
+        uint32_t w[4];
+        for (int j = 0; j < 4; ++j) w[j] = orc_xoshiro_next(W->xs + 4 * b);
+        orc_box_muller4(w, W->eps + 4 * b);
+    }
+    if (D->noise_mode == 2) {
+        /* isotropic: p += delta_p (|p| / sqrt d) eps, eps ~ N(0, I_d) */
+        double pp = 0.0;
+        for (int a = 0; a < d; ++a) pp += p[a] * p[a];
+        double sc = D->delta_p * sqrt(pp / d);
+        for (int a = 0; a < d; ++a) p[a] = p[a] + sc * W->eps[a];
+    } else {
+        for (int a = 0; a < d; ++a)
+            p[a] = p[a] * (1.0 + D->delta_p * (D->noise_mode ? W->eps[0] : W->eps[a]));
+    }
+    uint32_t ures = orc_xoshiro_next(W->xr);
+    W->outside = outside;
+    W->nref += outside;
+    W->outs += outside;
+    W->streak = outside ? W->streak + 1 : 0;
+    if (D->prune_streak > 0 && W->streak >= D->prune_streak) {
+        memcpy(x, W->x0, sizeof(double) * d);
+        W->n_prune += 1;
+        normals_philox(D->seed, (uint32_t)m, (uint32_t)S->iter, TAG_P0, (uint32_t)W->n_prune, d, p);
+        if (D->stop_mode == 0) W->nref = 0;
+        W->streak = 0;
+    }
+    return ures;
+}
+
+/* Keep the point of this step (trajectory preservation, R8-R10): an
+ * in-slice point that may be saved enters the walker's size-one reservoir
+ * with probability 1/nsave (Vitter's Algorithm R, decided on the integer
+ * word: keep iff word * nsave < 2^32); before the first saved point the
+ * output tracks the last in-slice point. */
+static void walker_keep(const orc_desc *D, orc_walker *W, int may_save, uint32_t ures)
+{
+    if (W->outside) return;
+    if (may_save) {
+        W->nsave += 1;
+        if ((uint64_t)ures * (uint64_t)W->nsave < ((uint64_t)1 << 32)) {
+            memcpy(W->out, W->x, sizeof(double) * D->d);
+            W->out_l = W->l;
+        }
+    } else if (W->nsave == 0) {
+        memcpy(W->out, W->x, sizeof(double) * D->d);
+        W->out_l = W->l;
+    }
+}
+
+/* A walker on its own, stopping at its own max_ref-th reflection (R11, the
+ * per-walker reading of the loop condition) or after n_steps_max steps. */
+static void walk_one(const orc_desc *D, const double *prm, orc_state *S, orc_walker *W)
+{
+    while (W->steps < D->n_steps_max && (D->max_ref == 0 || W->nref < D->max_ref)) {
+        uint32_t ures = walker_step(D, prm, S, W);
+        walker_keep(D, W, W->nref >= D->min_ref, ures);
+    }
+    S->out_logl[W->m] = W->out_l;
+}
+
+/* The saved trajectory points of the whole batch, in the order the
+ * algorithm appends them (step by step, walkers in index order). */
+typedef struct {
+    double *x, *l;
+    int64_t n, cap;
+} orc_pool;
+
+static void pool_add(orc_pool *P, const double *x, double l, int d)
+{
+    if (P->n == P->cap) {
+        P->cap = P->cap ? 2 * P->cap : 1024;
+        P->x = (double *)realloc(P->x, sizeof(double) * (size_t)P->cap * d);
+        P->l = (double *)realloc(P->l, sizeof(double) * (size_t)P->cap);
+    }
+    memcpy(P->x + P->n * d, x, sizeof(double) * d);
+    P->l[P->n] = l;
+    P->n += 1;
+}
+
+/* All k walkers in lockstep, as Algorithm GGNS HSS writes the loop: every
+ * step moves every walker that is still going; the loop runs while the
+ * batch minimum of num_reflections is below max_ref (stop_mode 1) or while
+ * any walker is below it (stop_mode 0: each walker stops at its own
+ * max_ref), for at most n_steps_max steps.  A point is saved when it is
+ * in-slice and either the batch minimum (save_mode 1) or the walker's own
+ * count (save_mode 0) has reached min_ref.  The new points are one pick per
+ * walker from its own saved points (draw_mode 0) or k uniform draws with
+ * replacement from the pooled x_saved of the whole batch (draw_mode 1,
+ * stream RES with sub 1, word 0 of walker slot j: index floor(u * N / 2^32)). */
+static void walk_lockstep(const orc_desc *D, const double *prm, orc_state *S, orc_walker *W)
+{
+    int k = D->n_kill, d = D->d;
+    uint32_t *ures = (uint32_t *)malloc(sizeof(uint32_t) * k);
+    orc_pool pool = {NULL, NULL, 0, 0};
+    for (int t = 0; t < D->n_steps_max; ++t) {
+        int minref = W[0].nref, going = 0;
+        for (int m = 0; m < k; ++m) {
+            if (W[m].nref < minref) minref = W[m].nref;
+            going += !W[m].done;
+        }
+        if (D->max_ref > 0 && (D->stop_mode == 1 ? minref >= D->max_ref : going == 0)) break;
+#pragma omp parallel for schedule(static)
+        for (int m = 0; m < k; ++m)
+            if (!W[m].done) ures[m] = walker_step(D, prm, S, &W[m]);
+        minref = W[0].nref;
+        for (int m = 1; m < k; ++m)
+            if (W[m].nref < minref) minref = W[m].nref;
+        for (int m = 0; m < k; ++m) {
+            if (W[m].done) continue;
+            int may_save = D->save_mode == 1 ? minref >= D->min_ref : W[m].nref >= D->min_ref;
+            if (D->draw_mode == 1) {
+                if (!W[m].outside && may_save) pool_add(&pool, W[m].x, W[m].l, d);
+                else walker_keep(D, &W[m], 0, 0u);   /* the fallback point only */
+            } else {
+                walker_keep(D, &W[m], may_save, ures[m]);
+            }
+            if (D->stop_mode == 0 && D->max_ref > 0 && W[m].nref >= D->max_ref) W[m].done = 1;
+        }
+    }
+    if (D->draw_mode == 1) {
+        for (int j = 0; j < k; ++j) {
+            if (pool.n == 0) continue;
+            uint32_t u[4];
+            stream_draw(D->seed, 0u, (uint32_t)j, (uint32_t)S->iter, TAG_RES, 1u, u);
+            int64_t idx = (int64_t)(((uint64_t)u[0] * (uint64_t)pool.n) >> 32);
+            memcpy(W[j].out, pool.x + idx * d, sizeof(double) * d);
+            W[j].out_l = pool.l[idx];
+            W[j].nsave = 1;
+        }
+    }
+    for (int m = 0; m < k; ++m) S->out_logl[m] = W[m].out_l;
+    free(pool.x);
+    free(pool.l);
+    free(ures);
 }
 
 int orc_hss_walk(const orc_desc *D, const double *prm, orc_state *S)
 {
     if (S->state != ST_ACTIVE) return 0;
     int k = D->n_kill;
-    int64_t outs = 0, steps = 0, prunes = 0, nosave = 0;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : outs, steps, prunes, nosave)
-    for (int m = 0; m < k; ++m) {
-        int64_t o, st, pr, ns;
-        walk_one(D, prm, S, m, &o, &st, &pr, &ns);
-        outs += o; steps += st; prunes += pr; nosave += ns;
+    orc_walker *W = (orc_walker *)malloc(sizeof(orc_walker) * k);
+    for (int m = 0; m < k; ++m) walker_start(D, S, m, &W[m]);
+    if (D->stop_mode == 0 && D->save_mode == 0 && D->draw_mode == 0) {
+        /* every walker is independent of the others */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int m = 0; m < k; ++m) walk_one(D, prm, S, &W[m]);
+    } else {
+        walk_lockstep(D, prm, S, W);
     }
+    int64_t outs = 0, steps = 0, prunes = 0, nosave = 0;
+    for (int m = 0; m < k; ++m) {
+        outs += W[m].outs;
+        steps += W[m].steps;
+        prunes += W[m].n_prune;
+        nosave += (W[m].nsave == 0);
+        walker_free(&W[m]);
+    }
+    free(W);
     S->it_outs = outs;
     S->it_steps = steps;
     S->steps_out += outs;

@@ -44,7 +44,8 @@ class _Desc(C.Structure):
                 ("term_kind", C.c_int32), ("max_iter", C.c_int32),
                 ("term_tol", C.c_double), ("seed", C.c_uint64),
                 ("noise_mode", C.c_int32), ("cluster_mode", C.c_int32),
-                ("cluster_kmax", C.c_int32), ("knn_fp32", C.c_int32)]
+                ("cluster_kmax", C.c_int32), ("stop_mode", C.c_int32),
+                ("save_mode", C.c_int32), ("draw_mode", C.c_int32), ("pad_desc", C.c_int32)]
 
 
 _PD = C.POINTER(C.c_double)
@@ -67,17 +68,27 @@ class _State(C.Structure):
                 ("trace_x", _PD), ("trace_logl", _PD), ("trace_out", _PI),
                 ("trace_steps", C.c_int32), ("pad2", C.c_int32),
                 ("label", _PI), ("clx", _PD), ("cn", _PI), ("surv_off", _PI), ("start_cl", _PI),
-                ("n_clusters", C.c_int32), ("n_splits", C.c_int32)]
+                ("n_clusters", C.c_int32), ("n_splits", C.c_int32),
+                ("split_kmax", C.c_int32), ("pad3", C.c_int32)]
 
 CL_MAX = 64
 
 
+def stale() -> bool:
+    """True when libns_oracle.so is missing or older than its source."""
+    return not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+
+
 def lib():
+    """The compiled oracle.  It is never compiled here: a process that has
+    started the GPU may not start a compiler, so a missing or stale library is
+    an error (build it first with build(), or __graft_entry__.build())."""
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-                build(force=True)
+            if stale():
+                raise RuntimeError("oracle/libns_oracle.so is missing or older than ns_oracle.c: "
+                                   "run __graft_entry__.build() (or oracle.oracle.build()) first")
             L = C.CDLL(_LIB)
             L.orc_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
             L.orc_xoshiro_next.argtypes = [C.POINTER(C.c_uint32)]
@@ -190,7 +201,9 @@ class Oracle:
                           seed=C.c_uint64(int(cfg.seed) & (2**64 - 1)),
                           noise_mode=cfg.noise_id, cluster_mode=int(cfg.cluster),
                           cluster_kmax=int(cfg.cluster_kmax),
-                          knn_fp32=int(cfg.precision != "fp64"))
+                          stop_mode=int(getattr(cfg, "stop_id", 0)),
+                          save_mode=int(getattr(cfg, "save_id", 0)),
+                          draw_mode=int(getattr(cfg, "draw_id", 0)))
         self.params = np.ascontiguousarray(cfg.params, dtype=np.float64)
         cap = k * cfg.max_iter + n
         self.live_x = np.zeros((n, d))

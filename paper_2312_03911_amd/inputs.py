@@ -27,7 +27,10 @@ import numpy as np
 
 KINDS = {"gauss_diag": 0, "gauss_full": 1, "shells": 2, "gmm_diag": 3, "torus": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16mma": 2}
-NOISE = {"component": 0, "walker": 1}
+NOISE = {"component": 0, "walker": 1, "isotropic": 2}
+STOP = {"walker": 0, "batch": 1}
+SAVE = {"walker": 0, "batch": 1}
+DRAW = {"walker": 0, "pooled": 1}
 
 
 @dataclasses.dataclass
@@ -58,9 +61,12 @@ class RunConfig:
     max_iter: int = 0             # 0 -> a generous bound from d, width and n_live
     seed: int = 0
     name: str = ""
-    noise: str = "component"      # eps of p *= 1 + delta_p eps: "component" or "walker"
+    noise: str = "walker"         # eps of p *= 1 + delta_p eps: one per walker ("walker"), per coordinate ("component"), isotropic (oracle only)
     cluster: int = 0              # 1: cluster recognition and volume-proportional spawning
     cluster_kmax: int = 8         # largest neighbour count the cluster finding tries
+    stop: str = ""                # walk ends at the batch minimum of reflections ("batch") or each walker's own ("walker"); "" = batch with max_ref > 0
+    save: str = ""                # points saved once the batch minimum ("batch") or the walker's own count ("walker") reaches min_ref; "" = batch with max_ref > 0
+    draw: str = "walker"          # new point: one pick per walker ("walker") or pooled draws from all saved points ("pooled", oracle only)
 
     def __post_init__(self):
         self.params = np.ascontiguousarray(self.params, dtype=np.float64)
@@ -84,6 +90,19 @@ class RunConfig:
     @property
     def noise_id(self) -> int:
         return NOISE[self.noise]
+
+    @property
+    def stop_id(self) -> int:
+        # a fixed-step walk (max_ref == 0) has no reflection loop: per walker
+        return STOP[self.stop or ("batch" if self.max_ref > 0 else "walker")]
+
+    @property
+    def save_id(self) -> int:
+        return SAVE[self.save or ("batch" if self.max_ref > 0 else "walker")]
+
+    @property
+    def draw_id(self) -> int:
+        return DRAW[self.draw]
 
     def replace(self, **kw) -> "RunConfig":
         return dataclasses.replace(self, **kw)

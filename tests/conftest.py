@@ -15,6 +15,11 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the HIP engine")
+    # the oracle is compiled before any test runs (and so before any GPU
+    # call of this process) when its library is missing or stale
+    import oracle.oracle as O
+    if O.stale():
+        O.build(force=True)
 
 
 @pytest.fixture(scope="session")
