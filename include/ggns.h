@@ -134,13 +134,25 @@ typedef struct {
                                 224: 8 only); default
                                 d_pad / 32.  Other values: GGNS_EUNSUPPORTED. */
     int32_t noise_mode;      /* the eps of p <- p (1 + delta_p eps) (Algorithm GGNS HSS):
-                                0 = one normal per coordinate (default reading),
-                                1 = one normal per walker and step, the first of its stream */
+                                1 = one normal per walker and step, the first of its stream
+                                (default reading), 0 = one normal per coordinate */
     int32_t cluster_mode;    /* 1: cluster recognition and spawning in proportion to the clusters'
                                 prior volumes (Section 3, mode collapse mitigation; Algorithm GGNS
                                 with its cluster-finding algorithm; Eqs. update0, update2, new0);
                                 0: one cluster.  sigma_mom is not computed in cluster mode. */
     int32_t cluster_kmax;    /* largest neighbour count the cluster finding tries, 2..8 */
+    int32_t walk_mode;       /* reflection-mode walks (max_ref > 0), Algorithm GGNS HSS:
+                                1 = the loop runs while the minimum of num_reflections over the
+                                run's n_kill walkers is below max_ref (every walker moves until the
+                                last one reaches it, at most n_steps_max steps), and a point is
+                                saved once that minimum has reached min_ref; each walker returns a
+                                uniform pick of its own saved points.  Enqueued as two launches: a
+                                first walk of each walker to its own max_ref-th reflection, then
+                                its continuation to the run's stopping step (a walker whose first
+                                walk reached the saving window is walked again from its start).
+                                0 = each walker stops at its own max_ref-th reflection and saves
+                                after its own min_ref-th.  Must be 0 when max_ref == 0. */
+    int32_t reserved0;       /* 0 */
 } ggns_run_desc;
 
 /* Byte offsets (from the arena base) of one run's arrays. */
@@ -182,6 +194,9 @@ typedef struct {
     int64_t prunes;          /* pruning resets */
     int64_t nosave;          /* walks that saved no point (fell back to the last in-slice point) */
     int64_t it_outs, it_steps;    /* counters of the last walk (out_frac) */
+    int64_t replayed;        /* walk_mode 1: walker steps walked a second time (a walker whose first
+                                walk reached the saving window is walked again from its start);
+                                not counted in evals */
     int32_t state;           /* GGNS_RUN_* */
     int32_t n_clusters;      /* cluster mode: cluster indices in use (removed ones included); else 0 */
 } ggns_run_stats;
@@ -272,13 +287,17 @@ int64_t ggns_plain_workspace_bytes(const ggns_ctx *ctx);
  *   ggns_ext_step(t)  takes step t (outside test, reflection, noise, kept
  *                     point, pruning, stop) and drifts the walkers that go on;
  *                     active[t] counts them;
- * until active[t] is 0 or t reaches n_steps_max - 1.  The walker outputs then
+ * until active[t] is 0 or t reaches n_steps_max - 1.  A walk_mode 1 run (the
+ * batch-minimum loop) takes one call more, t = n_steps_max, that applies the
+ * save rule of the last step (each call applies the one of the step before it,
+ * once the run's minimum reflection count after that step is known); its
+ * log L and gradient inputs are not read.  The walker outputs then
  * sit where ggns_replace_dead reads them.  Buffers live in the caller's device
  * workspace (256-byte aligned, at least ggns_ext_workspace_bytes(ctx, run),
  * contents need not be initialised; the same workspace for the whole walk):
  * ggns_ext_buffers returns x [d][n_kill] and grad [d][n_kill] (component-major,
- * walker m in column m), logl [n_kill] and active [n_steps_max], all double but
- * active (int32).  The live set's log L must come from the same likelihood
+ * walker m in column m), logl [n_kill] and active [n_steps_max + 1], all double
+ * but active (int32).  The live set's log L must come from the same likelihood
  * (write it over the live_logl section after ggns_init); the run's likelihood
  * family in its descriptor is then unused.  A run that is not GGNS_FP64 gives
  * GGNS_EUNSUPPORTED.  All calls are asynchronous on `stream`. */

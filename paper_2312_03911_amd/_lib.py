@@ -34,7 +34,8 @@ class ggns_run_desc(C.Structure):
                 ("dt_down", C.c_double), ("dt_up", C.c_double),
                 ("term_kind", C.c_int32), ("max_iter", C.c_int32), ("term_tol", C.c_double),
                 ("seed", C.c_uint64), ("tile_c", C.c_int32), ("noise_mode", C.c_int32),
-                ("cluster_mode", C.c_int32), ("cluster_kmax", C.c_int32)]
+                ("cluster_mode", C.c_int32), ("cluster_kmax", C.c_int32),
+                ("walk_mode", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class ggns_layout(C.Structure):
@@ -52,7 +53,7 @@ class ggns_run_stats(C.Structure):
                 ("iter", C.c_int64), ("evals", C.c_int64), ("n_dead", C.c_int64),
                 ("steps_out", C.c_int64), ("steps_in", C.c_int64), ("prunes", C.c_int64),
                 ("nosave", C.c_int64), ("it_outs", C.c_int64), ("it_steps", C.c_int64),
-                ("state", C.c_int32), ("n_clusters", C.c_int32)]
+                ("replayed", C.c_int64), ("state", C.c_int32), ("n_clusters", C.c_int32)]
 
 
 class ggns_run_vars(C.Structure):

@@ -42,6 +42,10 @@ bool valid_desc(const ggns_run_desc &r) {
     if (r.noise_mode != 0 && r.noise_mode != 1) return false;
     if (r.cluster_mode != 0 && r.cluster_mode != 1) return false;
     if (r.cluster_mode && (r.cluster_kmax < 2 || r.cluster_kmax > kKnnMax)) return false;
+    if (r.walk_mode != 0 && r.walk_mode != 1) return false;
+    // the batch-minimum loop needs a reflection count to stop on, and its
+    // saving window starts no later than its end
+    if (r.walk_mode == 1 && (r.max_ref < 1 || r.min_ref > r.max_ref)) return false;
     return true;
 }
 
@@ -101,6 +105,7 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
         R.out_hi = D.out_hi; R.out_lo = D.out_lo; R.dt_down = D.dt_down; R.dt_up = D.dt_up;
         R.term_tol = D.term_tol; R.seed = D.seed; R.param_offset = D.param_offset;
         R.noise_mode = D.noise_mode;
+        R.walk_mode = D.walk_mode;
         R.cluster_mode = D.cluster_mode;
         R.cluster_kmax = D.cluster_mode ? D.cluster_kmax : 0;
         const bool mma = D.precision == GGNS_FP32_BF16MMA;
@@ -156,6 +161,16 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
             R.off_label = R.off_cltab = R.off_members = R.off_knn = R.off_start_cl = -1;
             R.off_knn_part = R.off_knn_part_s = -1;
         }
+        if (D.walk_mode == 1) {
+            // walker states between the two walk launches, over the padded
+            // dimension of the run's walk kernel
+            const int wdp = mma ? (D.d + 31) / 32 * 32 : (R.dp + 3) / 4 * 4;
+            R.wstate_stride = walker_state_bytes(wdp, (int)es);
+            R.off_wstate = off; off = align_up(off + (int64_t)D.n_kill * R.wstate_stride);
+        } else {
+            R.off_wstate = -1;
+            R.wstate_stride = 0;
+        }
     }
     P.total = off;
     return GGNS_OK;
@@ -169,6 +184,7 @@ struct Class {
     size_t lds;
     int waves = 0;       // matrix-core classes: wavefronts per group of 16 walkers
     int gf = 0;          // vector FP32 walk: lanes per walker (4, 8 or 16) shared by the class, else 0
+    bool any_batch = false;   // some run of the class walks the batch-minimum loop
 };
 
 }  // namespace
@@ -244,6 +260,7 @@ void build_classes(ggns_ctx *c) {
         }
         w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
         w.lds = lds;
+        for (int r : kv.second) w.any_batch = w.any_batch || c->plan.runs[r].walk_mode == 1;
         // a mixture class with more wavefronts than the device has SIMDs is
         // bound by occupancy: its kernel reads the staged block every step
         // instead of holding it in registers
@@ -273,7 +290,10 @@ void build_classes(ggns_ctx *c) {
             Class w{GGNS_FP32_BF16MMA, kv.first.first, GGNS_LIK_GAUSS_FULL, true,
                     (int64_t)c->tiles_host.size(), 0, 0};
             w.waves = kv.first.second;
-            for (int r : kv.second) add_tiles(r, c->plan.runs[r].n_kill, 16);
+            for (int r : kv.second) {
+                add_tiles(r, c->plan.runs[r].n_kill, 16);
+                w.any_batch = w.any_batch || c->plan.runs[r].walk_mode == 1;
+            }
             w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
             c->walk_classes.push_back(w);
         }
@@ -360,6 +380,15 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
 
 }  // namespace
 
+namespace ggns {
+int64_t walker_state_bytes(int d_pad, int elem_bytes) {
+    // x, p and the fallback point (elem_bytes each), one noise stream word per
+    // coordinate (four per block of four), the reservoir stream (16 bytes),
+    // six counters and the fallback log L, padded to 80 bytes
+    return (int64_t)(3 * elem_bytes + 4) * d_pad + 80;
+}
+}  // namespace ggns
+
 extern "C" {
 
 int64_t ggns_arena_bytes(const ggns_run_desc *runs, int32_t n_runs) {
@@ -404,12 +433,21 @@ int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const size_t n = ctx->walk_classes.size();
-    auto launch = [&](const Class &w, hipStream_t st) {
+    auto launch_phase = [&](const Class &w, int phase, hipStream_t st) {
         if (w.mfma)
             return launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                    w.n_tiles, w.C, w.waves, st);
+                                    w.n_tiles, w.C, w.waves, phase, st);
         return launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                 w.n_tiles, w.prec, w.C, w.kind, w.gf, w.lds, st);
+                                 w.n_tiles, w.prec, w.C, w.kind, w.gf, w.lds, phase, st);
+    };
+    // a class with batch-minimum runs walks twice: the first walk fixes each
+    // run's window, the second finishes every run of the class
+    auto launch = [&](const Class &w, hipStream_t st) {
+        if (w.any_batch) {
+            const int rc = launch_phase(w, 1, st);
+            if (rc != GGNS_OK) return rc;
+        }
+        return launch_phase(w, 2, st);
     };
     if (n == 0) return GGNS_OK;
     if (n == 1) return launch(ctx->walk_classes[0], s);
@@ -489,7 +527,10 @@ int ggns_ext_step(ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t works
                   int32_t step, void *stream) {
     const int rc = ext_check(ctx, run, workspace_dev, workspace_bytes);
     if (rc != GGNS_OK) return rc;
-    if (step < 0 || step >= ctx->plan.runs[run].n_steps_max) return GGNS_EINVAL;
+    // the batch-minimum loop takes one call more (step == n_steps_max): the
+    // save rule of the last step
+    const RunDev &R = ctx->plan.runs[run];
+    if (step < 0 || step >= R.n_steps_max + (R.walk_mode == 1 ? 1 : 0)) return GGNS_EINVAL;
     return launch_ext_step(ctx->arena, ctx->runs_dev(), run, ctx->plan.runs[run], workspace_dev, step,
                            reinterpret_cast<hipStream_t>(stream));
 }

@@ -410,6 +410,8 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
             acc->lstar = key_value(key[k - 1]);
             acc->it_outs = 0ull;
             acc->it_steps = 0ull;
+            acc->win_a = 0;
+            acc->win_b = 0;
         }
     }
     if (stop) {

@@ -38,7 +38,10 @@ struct RunDev {
     double *trace_logl;
     int32_t *trace_out;
     int32_t trace_steps, mw;   // mw: wavefronts per group of 16 walkers (matrix-core walk)
-    int32_t noise_mode, pad;   // 1: one noise normal per walker and step
+    int32_t noise_mode;        // 1: one noise normal per walker and step
+    int32_t walk_mode;         // 1: the batch-minimum loop (first walk, then its continuation)
+    int64_t off_wstate;        // walk_mode 1: walker states at the end of the first walk
+    int64_t wstate_stride;     // bytes per walker of off_wstate
     // positions of the dead points (posterior samples), caller-owned; null when off
     void *dead_x;
     int64_t dead_x_cap;        // rows of dead_x
@@ -77,6 +80,8 @@ struct Acc {
     int32_t state, summary_pending;
     int32_t n_clusters;            // cluster indices in use (cluster mode)
     int32_t order_ok;              // 1: killed[] and surv_sorted[] hold the last kill's order
+    int32_t win_a, win_b;          // walk_mode 1: the saving window [win_a, win_b] of this walk
+    unsigned long long replayed;   // walk_mode 1: steps walked again
 };
 
 // A walk work item: walkers [m_begin, m_end) of one run.
@@ -98,11 +103,15 @@ void launch_evidence(void *arena, const RunDev *runs_dev, int n_runs, int final_
                      int any_cluster, hipStream_t s);
 void launch_finalize(void *arena, const RunDev *runs_dev, int n_runs, int max_chunks, hipStream_t s);
 void launch_replace(void *arena, const RunDev *runs_dev, int n_runs, int max_kd, hipStream_t s);
+// phase 1: first walk of the batch-minimum loop (walk_mode 1 runs; others
+// return at once); phase 2: its continuation, or the per-walker walk
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                      int prec, int C, int kind, int gf, size_t lds_bytes, hipStream_t s);
+                      int prec, int C, int kind, int gf, size_t lds_bytes, int phase, hipStream_t s);
 bool mfma_shape_ok(int d_pad, int waves);
 int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                     int d_pad, int waves, hipStream_t s);
+                     int d_pad, int waves, int phase, hipStream_t s);
+// bytes of one walker's saved state between the two walk launches
+int64_t walker_state_bytes(int d_pad, int elem_bytes);
 int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, const void *x,
                    int64_t n, double *logl, void *grad, const double *gout, hipStream_t s);
 int64_t plain_workspace_bytes(const RunDev &R);

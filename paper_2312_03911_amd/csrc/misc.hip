@@ -132,6 +132,8 @@ __global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, con
         acc->n_dead = 0;
         acc->steps_out = acc->steps_in = acc->prunes = acc->nosave = 0;
         acc->it_outs = acc->it_steps = 0ull;
+        acc->win_a = acc->win_b = 0;
+        acc->replayed = 0ull;
         acc->state = GGNS_RUN_ACTIVE;
         // the torus reward is a likelihood only where S + c > 0 for every x: c > d
         if (R.kind == GGNS_LIK_TORUS && !(raw[2] > (double)R.d)) acc->state = GGNS_RUN_NONFINITE;
@@ -453,6 +455,7 @@ __global__ void gather_acc_kernel(void *arena, const RunDev *__restrict__ runs, 
     o.iter = a.iter; o.evals = a.evals; o.n_dead = a.n_dead; o.steps_out = a.steps_out;
     o.steps_in = a.steps_in; o.prunes = a.prunes; o.nosave = a.nosave;
     o.it_outs = (int64_t)a.it_outs; o.it_steps = (int64_t)a.it_steps;
+    o.replayed = (int64_t)a.replayed;
     o.state = a.state; o.n_clusters = a.n_clusters;
     mirror[r] = o;
 }

@@ -22,7 +22,10 @@
 // r.y, p.y, y.y and the box test meet in LDS; two workgroup barriers a step.
 // All wavefronts take the same decisions for a walker from the same sums, and
 // refill finished slots from the tile in slot order, so the refill needs no
-// atomics.
+// atomics.  The batch-minimum loop (walk_mode 1) runs as the vector-ALU walk
+// runs it: a first walk of each walker to its own max_ref-th reflection that
+// leaves its state and the run's saving window, then the continuation to the
+// window's end.
 #include "ggns_device.h"
 
 namespace ggns {
@@ -59,17 +62,23 @@ __device__ __forceinline__ void momentum_lane(uint64_t seed, uint32_t m, uint32_
 // L dimensions per lane, W wavefronts per group of 16 walkers; dp = 4 L W.
 template <int L, int W>
 __global__ void __launch_bounds__(64 * W, 1)
-walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles) {
+walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+                 int phase) {
     constexpr int DP = 4 * L * W, MBW = L / 4, KB = DP / 32, RS = DP + 8;
     const Tile tile = tiles[blockIdx.x];
     const RunDev &R = runs[tile.run];
     Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
+    // phase 1: first walk of the batch-minimum loop (walk_mode 1 runs only);
+    // phase 2: its continuation, or the whole per-walker walk (walk_mode 0)
+    const bool batch = R.walk_mode == 1;
+    if (phase == 1 && !batch) return;
+    const bool first = phase == 1, cont = phase == 2 && batch;
 
     __shared__ __align__(16) __bf16 rbuf[16 * RS];       // residuals of the 16 slots
     __shared__ __align__(16) floatx4 part[W * 16];       // per-wavefront partial sums
     __shared__ float eps0s[16];                          // noise_mode 1: each slot's normal
-    __shared__ unsigned long long blk_cnt[4];
+    __shared__ unsigned long long blk_cnt[5];
 
     const int d = R.d;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -93,7 +102,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 #pragma unroll
     for (int c = 0; c < L; ++c) mu[c] = VALID(c) ? prm[a0 + c] : 0.0f;
     const float cst = prm[d];
-    if (threadIdx.x < 4) blk_cnt[threadIdx.x] = 0ull;
+    if (threadIdx.x < 5) blk_cnt[threadIdx.x] = 0ull;
 
     const double lstar = acc->lstar;
     const float dt = (float)acc->dt;
@@ -111,6 +120,14 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     double *walk_logl = at<double>(arena, R.off_walk_logl);
     float *trace_x = reinterpret_cast<float *>(R.trace_x);
     const int k = R.n_kill;
+    // stop and save rules of this launch (as in the vector-ALU walk)
+    const int never = n_steps_max + 1;
+    const int win_a = cont ? acc->win_a : 0, win_b = cont ? acc->win_b : 0;
+    const int keep_ref = batch ? (first ? INT_MAX : 0) : min_ref;
+    const int keep_step = cont ? win_a : 0;
+    const int end_steps = cont ? win_b : n_steps_max;
+    const int end_ref = cont ? 0 : max_ref;
+    unsigned char *wst = batch ? at<unsigned char>(arena, R.off_wstate) : nullptr;
 
     float x[L], p[L], y[L], xo[L];   // xo: the walker's reservoir point, written when it ends
     Xoshiro eps[L / 4];
@@ -118,7 +135,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     int m = tile.m_begin + slot;
     int next = tile.m_begin + 16;      // same in every lane: slots refill in slot order
     bool active = m < tile.m_end;
-    int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0;
+    int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0, a_step = never;
     double out_l = 0.0;
     // the prior box per dimension; padding dimensions get an unbounded one
     float blo[L], bhi[L];
@@ -153,9 +170,106 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         draw4(seed, 0u, (uint32_t)mm, it, TAG_RES, 0u, w);
         res.seed(w);
         nref = streak = steps = outs = nprune = nsave = 0;
+        a_step = never;
     };
 
-    if (active) start_walker(m);
+    // walker state between the two launches (layout as in the vector-ALU walk)
+    auto wrow = [&](int mm) { return wst + (int64_t)mm * R.wstate_stride; };
+    auto save_walker = [&]() {
+        unsigned char *row = wrow(m);
+        float *sx = reinterpret_cast<float *>(row), *sp = sx + DP, *so = sp + DP;
+        uint32_t *se = reinterpret_cast<uint32_t *>(so + DP);
+#pragma unroll
+        for (int c = 0; c < L; ++c) {
+            sx[a0 + c] = x[c];
+            sp[a0 + c] = p[c];
+            so[a0 + c] = xo[c];
+        }
+#pragma unroll
+        for (int i = 0; i < L / 4; ++i) {
+            uint32_t *e = se + 4 * ((a0 >> 2) + i);
+            e[0] = eps[i].s0; e[1] = eps[i].s1; e[2] = eps[i].s2; e[3] = eps[i].s3;
+        }
+        if (lead) {
+            uint32_t *sr = se + DP;
+            sr[0] = res.s0; sr[1] = res.s1; sr[2] = res.s2; sr[3] = res.s3;
+            int32_t *si = reinterpret_cast<int32_t *>(sr + 4);
+            si[0] = nref; si[1] = streak; si[2] = nprune; si[3] = outs; si[4] = steps;
+            *reinterpret_cast<double *>(si + 6) = out_l;
+            atomicMax(&acc->win_a, a_step);
+            atomicMax(&acc->win_b, steps);
+        }
+    };
+    auto acquire = [&](int mm) {
+        if (cont) {
+            const unsigned char *row = wrow(mm);
+            const float *sx = reinterpret_cast<const float *>(row), *sp = sx + DP, *so = sp + DP;
+            const uint32_t *se = reinterpret_cast<const uint32_t *>(so + DP);
+            const uint32_t *sr = se + DP;
+            const int32_t *si = reinterpret_cast<const int32_t *>(sr + 4);
+            const int b = si[4];
+            if (b < win_a) {
+                s = at<int32_t>(arena, R.off_start)[mm];
+#pragma unroll
+                for (int c = 0; c < L; ++c) {
+                    x[c] = sx[a0 + c];
+                    p[c] = sp[a0 + c];
+                    xo[c] = so[a0 + c];
+                }
+#pragma unroll
+                for (int i = 0; i < L / 4; ++i) {
+                    const uint32_t *e = se + 4 * ((a0 >> 2) + i);
+                    eps[i].s0 = e[0]; eps[i].s1 = e[1]; eps[i].s2 = e[2]; eps[i].s3 = e[3];
+                }
+                res.s0 = sr[0]; res.s1 = sr[1]; res.s2 = sr[2]; res.s3 = sr[3];
+                nref = si[0]; streak = si[1]; nprune = si[2]; outs = si[3]; steps = b;
+                nsave = 0;
+                out_l = *reinterpret_cast<const double *>(si + 6);
+                return;
+            }
+            start_walker(mm);
+            if (lead) atomicAdd(&blk_cnt[4], (unsigned long long)b);
+            return;
+        }
+        start_walker(mm);
+    };
+    auto emit = [&]() {
+        if (first) {
+            save_walker();
+            return;
+        }
+        float *wo = walk_x + (int64_t)m * d;
+#pragma unroll
+        for (int c = 0; c < L; ++c)
+            if (VALID(c)) wo[a0 + c] = xo[c];
+        if (lead) {
+            walk_logl[m] = out_l;
+            // the walker's counts go straight to the block's totals (LDS)
+            atomicAdd(&blk_cnt[0], (unsigned long long)outs);
+            atomicAdd(&blk_cnt[1], (unsigned long long)steps);
+            atomicAdd(&blk_cnt[2], (unsigned long long)nprune);
+            if (nsave == 0) atomicAdd(&blk_cnt[3], 1ull);
+        }
+    };
+    // slots whose walker is done emit it and take the next walkers of the tile
+    // in slot order, until each has a walker with steps to go (or none is
+    // left); every lane of every wavefront sees the same masks
+    auto retire = [&](bool need) {
+        while (__any(need)) {
+            if (need) emit();
+            const uint32_t fin = (uint32_t)(__ballot(need) & 0xFFFFull);
+            if (need) {
+                m = next + __popc(fin & ((1u << slot) - 1u));
+                active = m < tile.m_end;
+                if (active) acquire(m);
+            }
+            next += __popc(fin);
+            need = need && active && steps >= end_steps;
+        }
+    };
+
+    if (active) acquire(m);
+    retire(active && steps >= end_steps);
     __syncthreads();
 
     // slots can only end inside the rare-event branch, so whether any walker
@@ -272,7 +386,8 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         nref += out ? 1 : 0;
         outs += out ? 1 : 0;
         streak = out ? streak + 1 : 0;
-        const bool keep = !out && nref >= min_ref;
+        a_step = (a_step == never && nref >= min_ref) ? steps : a_step;
+        const bool keep = !out && nref >= keep_ref && steps >= keep_step;
         nsave += keep ? 1 : 0;
         const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32))
                                         : (nsave == 0));
@@ -284,7 +399,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         // the next walker of the tile).  Slot states are the same in every lane
         // of a slot and every wavefront, so all wavefronts take the branch together
         const bool pruning = prune_streak > 0 && streak >= prune_streak;
-        const bool ends = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
+        const bool ends = !(steps < end_steps && (end_ref == 0 || nref < end_ref));
         if (__builtin_expect(__any(active & (pruning | ends)), 0)) {
             if (active & pruning) {
                 const float *xs = live_x + (int64_t)s * d;
@@ -292,39 +407,19 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 for (int c = 0; c < L; ++c) x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
                 nprune += 1;
                 momentum_lane<L>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
-                nref = 0;
+                // the batch minimum never decreases: its count is kept
+                nref = batch ? nref : 0;
                 streak = 0;
             }
-            const bool need = active && !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
-            if (need) {
-                float *wo = walk_x + (int64_t)m * d;
-#pragma unroll
-                for (int c = 0; c < L; ++c)
-                    if (VALID(c)) wo[a0 + c] = xo[c];
-                if (lead) {
-                    walk_logl[m] = out_l;
-                    // the walker's counts go straight to the block's totals (LDS)
-                    atomicAdd(&blk_cnt[0], (unsigned long long)outs);
-                    atomicAdd(&blk_cnt[1], (unsigned long long)steps);
-                    atomicAdd(&blk_cnt[2], (unsigned long long)nprune);
-                    if (nsave == 0) atomicAdd(&blk_cnt[3], 1ull);
-                }
-            }
-            // finished slots take the next walkers of the tile in slot order;
-            // every lane of every wavefront sees the same mask and computes the same ids
-            const uint32_t fin = (uint32_t)(__ballot(need) & 0xFFFFull);
-            if (need) {
-                m = next + __popc(fin & ((1u << slot) - 1u));
-                active = m < tile.m_end;
-                if (active) start_walker(m);
-            }
-            next += __popc(fin);
+            retire(active && !(steps < end_steps && (end_ref == 0 || nref < end_ref)));
             any_left = __any(active);
         }
     }
 
 #undef VALID
     __syncthreads();
+    if (threadIdx.x == 0 && blk_cnt[4] > 0)
+        atomicAdd(&acc->replayed, blk_cnt[4]);
     if (threadIdx.x == 0 && blk_cnt[1] > 0) {
         atomicAdd(&acc->it_outs, blk_cnt[0]);
         atomicAdd(&acc->it_steps, blk_cnt[1]);
@@ -338,9 +433,9 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 
 template <int L, int W>
 static hipError_t launch_mfma_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
-                                hipStream_t s) {
+                                int phase, hipStream_t s) {
     hipLaunchKernelGGL((walk_mfma_kernel<L, W>), dim3(n_tiles), dim3(64 * W), 0, s, arena, runs,
-                       tiles);
+                       tiles, phase);
     return hipGetLastError();
 }
 
@@ -357,12 +452,12 @@ bool mfma_shape_ok(int d_pad, int waves) {
 }
 
 int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int d_pad,
-                     int waves, hipStream_t s) {
+                     int waves, int phase, hipStream_t s) {
     if (!mfma_shape_ok(d_pad, waves)) return GGNS_EUNSUPPORTED;
     const int L = d_pad / (4 * waves);
     hipError_t e = hipErrorInvalidValue;
 #define GGNS_MFMA_CASE(LL, WW) \
-    if (L == LL && waves == WW) e = launch_mfma_t<LL, WW>(arena, runs_dev, tiles, n_tiles, s);
+    if (L == LL && waves == WW) e = launch_mfma_t<LL, WW>(arena, runs_dev, tiles, n_tiles, phase, s);
     GGNS_MFMA_CASE(8, 1) GGNS_MFMA_CASE(4, 2)                          // dp 32
     GGNS_MFMA_CASE(16, 1) GGNS_MFMA_CASE(8, 2) GGNS_MFMA_CASE(4, 4)    // dp 64
     GGNS_MFMA_CASE(8, 3)                                               // dp 96

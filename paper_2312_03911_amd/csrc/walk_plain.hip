@@ -6,7 +6,11 @@
 // number of active walkers between launches, and runs are walked one after
 // the other.  It draws the same random streams and takes the same decisions as
 // the fused walk (readings as there), so for FP64 runs the two agree up to the
-// order of floating-point sums.
+// order of floating-point sums.  The batch-minimum loop (walk_mode 1) is the
+// algorithm's lockstep loop as written: every walker steps in every launch,
+// each launch records the run's minimum reflection count after its step, and
+// the next launch (one more follows the last step) applies that step's save
+// rule and stops every walker once the minimum has reached max_ref.
 #include "ggns_device.h"
 
 namespace ggns {
@@ -22,7 +26,13 @@ struct PlainState {
     uint32_t *eps;  // [nb * 4][k] xoshiro states, nb = ceil(d / 4)
     uint32_t *res;  // [4][k]
     int32_t *s, *nref, *streak, *steps, *outs, *nprune, *nsave, *done;
-    int32_t *active;  // [n_steps_max] walkers still walking after step t
+    int32_t *active;  // [n_steps_max + 1] walkers still walking after step t
+    // batch-minimum loop: the run's minimum reflection count after step t,
+    // and each walker's in-slice point of its last step awaiting the save rule
+    int32_t *minref;  // [n_steps_max + 1]
+    int32_t *pend;    // [k] 1: the last step was in-slice
+    uint32_t *pures;  // [k] its reservoir word
+    double *xc, *lc;  // [d][k], [k] its position and log L
 };
 
 __host__ __device__ inline int64_t plain_align(int64_t v) { return (v + 255) / 256 * 256; }
@@ -43,14 +53,23 @@ __host__ __device__ inline int64_t plain_bytes(int k, int d, int n_steps_max, Pl
     double *lx = (double *)take((int64_t)k * 8);
     uint32_t *eps = (uint32_t *)take((int64_t)k * nb * 16);
     uint32_t *res = (uint32_t *)take((int64_t)k * 16);
-    int32_t *ints[8];
-    for (int i = 0; i < 8; ++i) ints[i] = (int32_t *)take((int64_t)k * 4);
-    int32_t *act = (int32_t *)take((int64_t)n_steps_max * 4);
+    int32_t *ints[9];
+    for (int i = 0; i < 9; ++i) ints[i] = (int32_t *)take((int64_t)k * 4);
+    int32_t *act = (int32_t *)take((int64_t)(n_steps_max + 1) * 4);
+    int32_t *mref = (int32_t *)take((int64_t)(n_steps_max + 1) * 4);
+    uint32_t *pu = (uint32_t *)take((int64_t)k * 4);
+    double *xc = (double *)take((int64_t)k * d * 8);
+    double *lc = (double *)take((int64_t)k * 8);
     if (st) {
         st->x = x; st->p = p; st->g = g; st->out_l = ol; st->l = lx; st->eps = eps; st->res = res;
         st->s = ints[0]; st->nref = ints[1]; st->streak = ints[2]; st->steps = ints[3];
         st->outs = ints[4]; st->nprune = ints[5]; st->nsave = ints[6]; st->done = ints[7];
+        st->pend = ints[8];
         st->active = act;
+        st->minref = mref;
+        st->pures = pu;
+        st->xc = xc;
+        st->lc = lc;
     }
     return off;
 }
@@ -148,7 +167,10 @@ __global__ void plain_start_kernel(void *arena, const RunDev *__restrict__ runs,
     PlainState S;
     plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, ws);
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int t = m; t < R.n_steps_max; t += gridDim.x * blockDim.x) S.active[t] = 0;
+    for (int t = m; t <= R.n_steps_max; t += gridDim.x * blockDim.x) {
+        S.active[t] = 0;
+        S.minref[t] = INT_MAX;
+    }
     if (acc->state != GGNS_RUN_ACTIVE || m >= R.n_kill) return;
     const int d = R.d, nsurv = R.n_live - R.n_kill, nb = (d + 3) / 4;
     const int64_t k = R.n_kill;
@@ -177,6 +199,7 @@ __global__ void plain_start_kernel(void *arena, const RunDev *__restrict__ runs,
     S.res[m] = r.s0; S.res[k + m] = r.s1; S.res[2 * k + m] = r.s2; S.res[3 * k + m] = r.s3;
     S.s[m] = s;
     S.nref[m] = S.streak[m] = S.steps[m] = S.outs[m] = S.nprune[m] = S.nsave[m] = S.done[m] = 0;
+    S.pend[m] = 0;
 }
 
 // One step of every walker of the run.  EXT = false: drift, then log L and the
@@ -201,6 +224,44 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
     const uint32_t it = (uint32_t)acc->iter;
     double *x = S.x + m, *p = S.p + m, *g = S.g + m;  // component a at [a * k]
     const double *prm = at<double>(arena, R.off_prm);
+    const bool batch = R.walk_mode == 1;
+    auto finish = [&]() {
+        S.done[m] = 1;
+        const int steps = S.steps[m], outs = S.outs[m];
+        at<double>(arena, R.off_walk_logl)[m] = S.out_l[m];
+        atomicAdd(&acc->it_outs, (unsigned long long)outs);
+        atomicAdd(&acc->it_steps, (unsigned long long)steps);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_out), (unsigned long long)outs);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_in),
+                  (unsigned long long)(steps - outs));
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->evals), (unsigned long long)steps);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->prunes),
+                  (unsigned long long)S.nprune[m]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->nosave),
+                  (unsigned long long)(S.nsave[m] == 0 ? 1 : 0));
+    };
+    if (batch && t > 0) {
+        // the save rule of the previous step, now that the run's minimum
+        // reflection count after it is known; then the loop condition
+        const int mr = S.minref[t - 1];
+        if (S.pend[m]) {
+            const bool keep = mr >= R.min_ref;
+            const int nsave = S.nsave[m] + (keep ? 1 : 0);
+            const bool take =
+                keep ? ((uint64_t)S.pures[m] * (uint64_t)nsave < (1ull << 32)) : (nsave == 0);
+            if (take) {
+                double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
+                for (int a = 0; a < d; ++a) wo[a] = S.xc[a * k + m];
+                S.out_l[m] = S.lc[m];
+            }
+            S.nsave[m] = nsave;
+            S.pend[m] = 0;
+        }
+        if (mr >= R.max_ref || t >= R.n_steps_max) {
+            finish();
+            return;
+        }
+    }
 
     // drift, log L and the score
     double l;
@@ -250,13 +311,24 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
     int nref = S.nref[m] + (out ? 1 : 0);
     const int outs = S.outs[m] + (out ? 1 : 0);
     int streak = out ? S.streak[m] + 1 : 0;
-    const bool keep = !out && nref >= R.min_ref;
-    const int nsave = S.nsave[m] + (keep ? 1 : 0);
-    const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32)) : (nsave == 0));
-    if (take) {
-        double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
-        for (int a = 0; a < d; ++a) wo[a] = x[a * k];
-        S.out_l[m] = l;
+    int nsave = S.nsave[m];
+    if (batch) {
+        // the save rule waits for the run's minimum after this step
+        S.pend[m] = out ? 0 : 1;
+        if (!out) {
+            for (int a = 0; a < d; ++a) S.xc[a * k + m] = x[a * k];
+            S.lc[m] = l;
+            S.pures[m] = ures;
+        }
+    } else {
+        const bool keep = !out && nref >= R.min_ref;
+        nsave += keep ? 1 : 0;
+        const bool take = !out && (keep ? ((uint64_t)ures * (uint64_t)nsave < (1ull << 32)) : (nsave == 0));
+        if (take) {
+            double *wo = at<double>(arena, R.off_walk_x) + (int64_t)m * d;
+            for (int a = 0; a < d; ++a) wo[a] = x[a * k];
+            S.out_l[m] = l;
+        }
     }
     int nprune = S.nprune[m];
     if (R.prune_streak > 0 && streak >= R.prune_streak) {
@@ -264,24 +336,22 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
         for (int a = 0; a < d; ++a) x[a * k] = xs[a];
         nprune += 1;
         plain_momentum(R.seed, (uint32_t)m, it, (uint32_t)nprune, d, k, S.p);
-        nref = 0;
+        // the batch minimum never decreases: its count is kept
+        nref = batch ? nref : 0;
         streak = 0;
     }
     S.nref[m] = nref; S.outs[m] = outs; S.streak[m] = streak; S.steps[m] = steps;
     S.nsave[m] = nsave; S.nprune[m] = nprune;
+    if (batch) {
+        atomicMin(&S.minref[t], nref);
+        atomicAdd(&S.active[t], 1);
+        if constexpr (EXT)
+            for (int a = 0; a < d; ++a) x[a * k] += dt * p[a * k];
+        return;
+    }
     const bool done = !(steps < R.n_steps_max && (R.max_ref == 0 || nref < R.max_ref));
     if (done) {
-        S.done[m] = 1;
-        at<double>(arena, R.off_walk_logl)[m] = S.out_l[m];
-        atomicAdd(&acc->it_outs, (unsigned long long)outs);
-        atomicAdd(&acc->it_steps, (unsigned long long)steps);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_out), (unsigned long long)outs);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->steps_in),
-                  (unsigned long long)(steps - outs));
-        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->evals), (unsigned long long)steps);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->prunes), (unsigned long long)nprune);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&acc->nosave),
-                  (unsigned long long)(nsave == 0 ? 1 : 0));
+        finish();
     } else {
         atomicAdd(&S.active[t], 1);
         if constexpr (EXT)
@@ -317,11 +387,13 @@ int launch_walk_plain(void *arena, const RunDev *runs_dev, int run, const RunDev
     if (hipGetLastError() != hipSuccess) return GGNS_EHIP;
     PlainState S;
     plain_bytes(R.n_kill, R.d, R.n_steps_max, &S, w);
-    for (int t = 0; t < R.n_steps_max; ++t) {
+    // the batch-minimum loop takes one launch more: the save rule of the last step
+    const int n_launch = R.n_steps_max + (R.walk_mode == 1 ? 1 : 0);
+    for (int t = 0; t < n_launch; ++t) {
         hipLaunchKernelGGL(plain_step_kernel<false>, dim3(blocks), dim3(threads), 0, s, arena, runs_dev,
                            run, w, t);
         if (hipGetLastError() != hipSuccess) return GGNS_EHIP;
-        if ((t + 1) % poll_every == 0 && t + 1 < R.n_steps_max) {
+        if ((t + 1) % poll_every == 0 && t + 1 < n_launch) {
             int32_t n_active = 0;
             if (hipMemcpyAsync(&n_active, S.active + t, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)

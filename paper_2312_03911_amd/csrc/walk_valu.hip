@@ -4,13 +4,28 @@
 // mask, reflection p -= 2 (p.n) n with n the unit score (Eq. reflection),
 // momentum noise p *= 1 + delta_p eps, reflection count, kept in-slice points,
 // out_frac) and Section 3 (trajectory preservation, pruning, parallel
-// evolution of the killed points).  Readings: the walker stops at max_ref
-// reflections (or runs n_steps_max steps when max_ref == 0); the prior box
+// evolution of the killed points).  Readings: the loop runs while the minimum
+// of num_reflections over the run's walkers is below max_ref and points are
+// saved once that minimum has reached min_ref (walk_mode 1; walk_mode 0: each
+// walker stops and saves by its own count), or every walker runs n_steps_max
+// steps (max_ref == 0); the prior box
 // counts as outside and flips the violated momentum components; a zero or
 // non-finite score reflects p -> -p; a walker keeps its in-slice points once it
 // has min_ref reflections and returns a uniform pick through a size-one
 // reservoir, else its last in-slice point, else its start; prune_streak outside
 // steps in a row reset it to its start with fresh momentum.
+//
+// The batch-minimum loop is two launches.  The first (phase 1) walks each
+// walker to its own max_ref-th reflection (or the cap), saving nothing, and
+// leaves its state in the arena together with the run's window: win_b = the
+// largest of those step counts (the step at which the minimum reaches
+// max_ref) and win_a = the largest step at which a walker reached min_ref
+// (the first step of the saving window).  The second (phase 2) continues each
+// walker to win_b with the reservoir over its in-slice steps >= win_a; a
+// walker whose first walk already reached win_a is walked again from its
+// start (same streams, same steps), so that its steps inside the window are
+// seen.  The walkers are independent given the window, so this is the
+// lockstep loop of the algorithm step for step.
 //
 // Layout: one walker per group of G lanes (G = 1..64, power of two), lane g
 // owning C consecutive coordinates [g*C, g*C + C) of x, p and the score in
@@ -87,16 +102,22 @@ __device__ __forceinline__ void momentum_draw(uint64_t seed, uint32_t m, uint32_
 // broadcast away, so the step's common path has no branch taken.
 template <typename T, int C, int VAR, int GF>
 __global__ void __launch_bounds__(kWalkThreads, GGNS_WALK_WAVES)
-walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles) {
+walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
+                 int phase) {
     constexpr int NB = (C + 3) / 4;
     const Tile tile = tiles[blockIdx.x];
     const RunDev &R = runs[tile.run];
     Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
+    // phase 1: first walk of the batch-minimum loop (walk_mode 1 runs only);
+    // phase 2: its continuation, or the whole per-walker walk (walk_mode 0)
+    const bool batch = R.walk_mode == 1;
+    if (phase == 1 && !batch) return;
+    const bool first = phase == 1, cont = phase == 2 && batch;
 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int next_walker;
-    __shared__ unsigned long long blk_cnt[4];
+    __shared__ unsigned long long blk_cnt[5];
 
     const int d = R.d, dp = R.dp, G = GF ? GF : R.G;
     const int ngroups = blockDim.x / G;
@@ -109,7 +130,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     T *xch_all = reinterpret_cast<T *>(smem + ((R.nprm_bytes_lds + 15) & ~15));
     if (threadIdx.x == 0) {
         next_walker = tile.m_begin + ngroups;
-        blk_cnt[0] = blk_cnt[1] = blk_cnt[2] = blk_cnt[3] = 0ull;
+        blk_cnt[0] = blk_cnt[1] = blk_cnt[2] = blk_cnt[3] = blk_cnt[4] = 0ull;
     }
     __syncthreads();
 
@@ -152,13 +173,23 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     double *walk_logl = at<double>(arena, R.off_walk_logl);
     T *trace_x = reinterpret_cast<T *>(R.trace_x);
     const int k = R.n_kill;
+    // stop and save rules of this launch: a point is kept when it is in-slice,
+    // nref >= keep_ref and its step >= keep_step; a walker ends after end_steps
+    // steps or at end_ref reflections (0: never)
+    const int never = n_steps_max + 1;
+    const int win_a = cont ? acc->win_a : 0, win_b = cont ? acc->win_b : 0;
+    const int keep_ref = batch ? (first ? INT_MAX : 0) : min_ref;
+    const int keep_step = cont ? win_a : 0;
+    const int end_steps = cont ? win_b : n_steps_max;
+    const int end_ref = cont ? 0 : max_ref;
+    unsigned char *wst = batch ? at<unsigned char>(arena, R.off_wstate) : nullptr;
 
     T x[C], p[C], g[C], xo[C];
     Xoshiro eps[NB];
     Xoshiro res;
     int m = tile.m_begin + grp;
     bool active = m < tile.m_end;
-    int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0;
+    int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0, a_step = never;
     double out_l = 0.0;
 
     auto start_walker = [&](int mm) {
@@ -186,9 +217,115 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         draw4(seed, 0u, (uint32_t)mm, it, TAG_RES, 0u, w);
         res.seed(w);
         nref = streak = steps = outs = nprune = nsave = 0;
+        a_step = never;
     };
 
-    if (active) start_walker(m);
+    // walker state between the two launches of the batch-minimum loop: x, p,
+    // the fallback point (T), the noise stream states (one per block of four
+    // coordinates), the reservoir stream, the counters and the fallback log L
+    const int wdp = (int)((R.wstate_stride - 80) / (3 * (int64_t)sizeof(T) + 4));
+    auto wrow = [&](int mm) { return wst + (int64_t)mm * R.wstate_stride; };
+    auto save_walker = [&]() {
+        unsigned char *row = wrow(m);
+        T *sx = reinterpret_cast<T *>(row), *sp = sx + wdp, *so = sp + wdp;
+        uint32_t *se = reinterpret_cast<uint32_t *>(so + wdp);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            sx[a0 + c] = x[c];
+            sp[a0 + c] = p[c];
+            so[a0 + c] = xo[c];
+        }
+        if ((a0 & 3) == 0) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                uint32_t *e = se + 4 * ((a0 >> 2) + i);
+                e[0] = eps[i].s0; e[1] = eps[i].s1; e[2] = eps[i].s2; e[3] = eps[i].s3;
+            }
+        }
+        if (gl == 0) {
+            uint32_t *sr = se + wdp;
+            sr[0] = res.s0; sr[1] = res.s1; sr[2] = res.s2; sr[3] = res.s3;
+            int32_t *si = reinterpret_cast<int32_t *>(sr + 4);
+            si[0] = nref; si[1] = streak; si[2] = nprune; si[3] = outs; si[4] = steps;
+            *reinterpret_cast<double *>(si + 6) = out_l;
+            atomicMax(&acc->win_a, a_step);
+            atomicMax(&acc->win_b, steps);
+        }
+    };
+    // the continuation takes a walker up where its first walk left it, unless
+    // that walk reached the saving window: then it walks again from its start
+    auto acquire = [&](int mm) {
+        if (cont) {
+            const unsigned char *row = wrow(mm);
+            const T *sx = reinterpret_cast<const T *>(row), *sp = sx + wdp, *so = sp + wdp;
+            const uint32_t *se = reinterpret_cast<const uint32_t *>(so + wdp);
+            const uint32_t *sr = se + wdp;
+            const int32_t *si = reinterpret_cast<const int32_t *>(sr + 4);
+            const int b = si[4];
+            if (b < win_a) {
+                s = at<int32_t>(arena, R.off_start)[mm];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    x[c] = sx[a0 + c];
+                    p[c] = sp[a0 + c];
+                    xo[c] = so[a0 + c];
+                }
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const uint32_t *e = se + 4 * ((a0 >> 2) + i);
+                    eps[i].s0 = e[0]; eps[i].s1 = e[1]; eps[i].s2 = e[2]; eps[i].s3 = e[3];
+                }
+                res.s0 = sr[0]; res.s1 = sr[1]; res.s2 = sr[2]; res.s3 = sr[3];
+                nref = si[0]; streak = si[1]; nprune = si[2]; outs = si[3]; steps = b;
+                nsave = 0;
+                out_l = *reinterpret_cast<const double *>(si + 6);
+                return;
+            }
+            start_walker(mm);
+            if (gl == 0) atomicAdd(&blk_cnt[4], (unsigned long long)b);
+            return;
+        }
+        start_walker(mm);
+    };
+    // a walker ends: its state (first walk), or its kept point and counts
+    auto emit = [&]() {
+        if (first) {
+            save_walker();
+            return;
+        }
+        T *wo = walk_x + (int64_t)m * d;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (valid[c]) wo[a0 + c] = xo[c];
+        if (gl == 0) {
+            walk_logl[m] = out_l;
+            // the walker's counts go straight to the block's totals (LDS),
+            // so no per-lane counter rides through the step loop
+            atomicAdd(&blk_cnt[0], (unsigned long long)outs);
+            atomicAdd(&blk_cnt[1], (unsigned long long)steps);
+            atomicAdd(&blk_cnt[2], (unsigned long long)nprune);
+            if (nsave == 0) atomicAdd(&blk_cnt[3], 1ull);
+        }
+    };
+    // the group's walker is done (groups enter whole): emit it and take the
+    // next walkers of the tile until one has steps to go
+    auto retire = [&]() {
+        bool need = true;
+        while (need) {
+            emit();
+            int nm = 0;
+            if (gl == 0) nm = atomicAdd(&next_walker, 1);
+            m = __shfl(nm, gbase, 64);
+            active = m < tile.m_end;
+            if (active) acquire(m);
+            need = active && steps >= end_steps;
+        }
+    };
+
+    if (active) {
+        acquire(m);
+        if (steps >= end_steps) retire();
+    }
     const bool walker_noise = R.noise_mode != 0;
 
     // the wavefront's walkers can only end inside the rare-event branch, so
@@ -292,8 +429,9 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         nref += out ? 1 : 0;
         outs += out ? 1 : 0;
         streak = out ? streak + 1 : 0;
+        a_step = (a_step == never && nref >= min_ref) ? steps : a_step;
         // trajectory preservation: size-one reservoir over the kept points
-        const bool keep = !out && nref >= min_ref;
+        const bool keep = !out && nref >= keep_ref && steps >= keep_step;
         nsave += keep ? 1 : 0;
         // the reservoir's test u * nsave < 2^32 is a zero high word of the product;
         // bitwise on purpose: the decision costs no branch
@@ -307,7 +445,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         // group takes the next walker of the tile); streak, nref and steps are
         // the same on every lane of a group, so groups enter whole
         const bool pruning = prune_streak > 0 && streak >= prune_streak;
-        const bool ends = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
+        const bool ends = !(steps < end_steps && (end_ref == 0 || nref < end_ref));
         const bool rare = active & (pruning | ends);
         if (__builtin_expect(__any(rare), 0)) {
           if (rare) {
@@ -317,36 +455,19 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 for (int c = 0; c < C; ++c) x[c] = valid[c] ? xs[a0 + c] : T(0);
                 nprune += 1;
                 momentum_draw<T, C>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
-                nref = 0;
+                // the batch minimum never decreases: its count is kept
+                nref = batch ? nref : 0;
                 streak = 0;
             }
-            const bool need = !(steps < n_steps_max && (max_ref == 0 || nref < max_ref));
-            if (need) {
-                T *wo = walk_x + (int64_t)m * d;
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    if (valid[c]) wo[a0 + c] = xo[c];
-                int nm = 0;
-                if (gl == 0) {
-                    walk_logl[m] = out_l;
-                    // the walker's counts go straight to the block's totals (LDS),
-                    // so no per-lane counter rides through the step loop
-                    atomicAdd(&blk_cnt[0], (unsigned long long)outs);
-                    atomicAdd(&blk_cnt[1], (unsigned long long)steps);
-                    atomicAdd(&blk_cnt[2], (unsigned long long)nprune);
-                    if (nsave == 0) atomicAdd(&blk_cnt[3], 1ull);
-                    nm = atomicAdd(&next_walker, 1);
-                }
-                m = __shfl(nm, gbase, 64);
-                active = m < tile.m_end;
-                if (active) start_walker(m);
-            }
+            if (!(steps < end_steps && (end_ref == 0 || nref < end_ref))) retire();
           }
           any_left = __any(active);
         }
     }
 
     __syncthreads();
+    if (threadIdx.x == 0 && blk_cnt[4] > 0)
+        atomicAdd(&acc->replayed, blk_cnt[4]);
     if (threadIdx.x == 0 && blk_cnt[1] > 0) {
         atomicAdd(&acc->it_outs, blk_cnt[0]);
         atomicAdd(&acc->it_steps, blk_cnt[1]);
@@ -362,47 +483,47 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 // with the group size fixed; every other class reads it from the run.
 template <typename T, int C, int VAR>
 static void launch_gf(int gf, int n_tiles, size_t lds, hipStream_t s, void *arena,
-                      const RunDev *runs, const Tile *tiles) {
+                      const RunDev *runs, const Tile *tiles, int phase) {
     const dim3 grid(n_tiles), block(kWalkThreads);
     if constexpr (std::is_same<T, float>::value) {
         if (gf == 4)
-            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 4>), grid, block, lds, s, arena, runs, tiles);
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 4>), grid, block, lds, s, arena, runs, tiles, phase);
         else if (gf == 8)
-            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 8>), grid, block, lds, s, arena, runs, tiles);
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 8>), grid, block, lds, s, arena, runs, tiles, phase);
         else if (gf == 16)
-            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 16>), grid, block, lds, s, arena, runs, tiles);
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 16>), grid, block, lds, s, arena, runs, tiles, phase);
         else
-            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 0>), grid, block, lds, s, arena, runs, tiles);
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 0>), grid, block, lds, s, arena, runs, tiles, phase);
     } else {
-        hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 0>), grid, block, lds, s, arena, runs, tiles);
+        hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 0>), grid, block, lds, s, arena, runs, tiles, phase);
     }
 }
 
 template <typename T, int C>
 static hipError_t launch_walk_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
-                                int var, int gf, size_t lds, hipStream_t s) {
+                                int var, int gf, size_t lds, int phase, hipStream_t s) {
     if (var == VAR_GMM_STAGED)
-        launch_gf<T, C, VAR_GMM_STAGED>(gf, n_tiles, lds, s, arena, runs, tiles);
+        launch_gf<T, C, VAR_GMM_STAGED>(gf, n_tiles, lds, s, arena, runs, tiles, phase);
     else
-        GGNS_DISPATCH_KIND(var, (launch_gf<T, C, KIND_>(gf, n_tiles, lds, s, arena, runs, tiles)));
+        GGNS_DISPATCH_KIND(var, (launch_gf<T, C, KIND_>(gf, n_tiles, lds, s, arena, runs, tiles, phase)));
     return hipGetLastError();
 }
 
 int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int prec,
-                      int C, int var, int gf, size_t lds, hipStream_t s) {
+                      int C, int var, int gf, size_t lds, int phase, hipStream_t s) {
     hipError_t e = hipErrorInvalidValue;
     if (prec == GGNS_FP64) {
         switch (C) {
-            case 1: e = launch_walk_t<double, 1>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
-            case 2: e = launch_walk_t<double, 2>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
-            case 4: e = launch_walk_t<double, 4>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
+            case 1: e = launch_walk_t<double, 1>(arena, runs_dev, tiles, n_tiles, var, gf, lds, phase, s); break;
+            case 2: e = launch_walk_t<double, 2>(arena, runs_dev, tiles, n_tiles, var, gf, lds, phase, s); break;
+            case 4: e = launch_walk_t<double, 4>(arena, runs_dev, tiles, n_tiles, var, gf, lds, phase, s); break;
         }
     } else {
         switch (C) {
-            case 1: e = launch_walk_t<float, 1>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
-            case 2: e = launch_walk_t<float, 2>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
-            case 4: e = launch_walk_t<float, 4>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
-            case 8: e = launch_walk_t<float, 8>(arena, runs_dev, tiles, n_tiles, var, gf, lds, s); break;
+            case 1: e = launch_walk_t<float, 1>(arena, runs_dev, tiles, n_tiles, var, gf, lds, phase, s); break;
+            case 2: e = launch_walk_t<float, 2>(arena, runs_dev, tiles, n_tiles, var, gf, lds, phase, s); break;
+            case 4: e = launch_walk_t<float, 4>(arena, runs_dev, tiles, n_tiles, var, gf, lds, phase, s); break;
+            case 8: e = launch_walk_t<float, 8>(arena, runs_dev, tiles, n_tiles, var, gf, lds, phase, s); break;
         }
     }
     return e == hipSuccess ? GGNS_OK : GGNS_EHIP;

@@ -19,6 +19,26 @@ def _torch():
     return torch
 
 
+def walk_mode_of(c: RunConfig) -> int:
+    """The library's walk_mode for a run's walk readings: 1 for the loop and
+    the saving on the batch minimum of num_reflections, 0 for both per walker
+    (and for fixed-step walks); other combinations, the pooled draw and the
+    isotropic noise exist in the test oracle only."""
+    if c.draw_id != 0:
+        raise ValueError("the pooled x_saved draw is not implemented by the engine")
+    if c.noise_id not in (0, 1):
+        raise ValueError(f"noise reading {c.noise!r} is not implemented by the engine")
+    if c.max_ref == 0:
+        if c.save_id != 0:
+            raise ValueError("fixed-step walks save per walker in the engine")
+        return 0
+    if (c.stop_id, c.save_id) == (1, 1):
+        return 1
+    if (c.stop_id, c.save_id) == (0, 0):
+        return 0
+    raise ValueError("the engine walks stop and save both per walker or both on the batch minimum")
+
+
 def make_descs(configs: Sequence[RunConfig], tile_c=None):
     """The C run descriptors of a batch and its packed FP64 parameter blocks."""
     n = len(configs)
@@ -39,6 +59,7 @@ def make_descs(configs: Sequence[RunConfig], tile_c=None):
         D.tile_c = int(tile_c[i]) if tile_c is not None else 0
         D.noise_mode = c.noise_id
         D.cluster_mode, D.cluster_kmax = int(c.cluster), int(c.cluster_kmax)
+        D.walk_mode = walk_mode_of(c)
         blocks.append(np.asarray(c.params, np.float64))
         off += len(c.params)
     return descs, blocks
@@ -102,6 +123,9 @@ class Engine:
 
     def _view(self, off, nbytes, dtype, shape):
         return self.arena[off:off + nbytes].view(dtype).view(*shape)
+
+    def walk_mode(self, r: int) -> int:
+        return int(self.descs[r].walk_mode)
 
     def _fdtype(self, r):
         return self.torch.float64 if self.layouts[r].elem_bytes == 8 else self.torch.float32

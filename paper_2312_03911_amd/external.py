@@ -66,7 +66,7 @@ class ExternalRuns:
         x = view(ptrs[0], d * k, torch.float64, (d, k))
         logl = view(ptrs[1], k, torch.float64, (k,))
         grad = view(ptrs[2], d * k, torch.float64, (d, k))
-        active = view(ptrs[3], c.n_steps_max, torch.int32, (c.n_steps_max,))
+        active = view(ptrs[3], c.n_steps_max + 1, torch.int32, (c.n_steps_max + 1,))
         return x, logl, grad, active
 
     def walk(self, r: int, poll_every: int = 8):
@@ -77,10 +77,14 @@ class ExternalRuns:
         x, logl, grad, active = self._buffers(r)
         _lib.check(self.eng.L.ggns_ext_begin(self.eng.ctx, r, ws.data_ptr(), ws.numel(), s),
                    "ggns_ext_begin")
-        for t in range(c.n_steps_max):
-            l, g = value_and_score(self.fns[r], x.t())
-            logl.copy_(l)
-            grad.copy_(g.t())
+        # the batch-minimum loop takes one call more: the last step's save rule
+        batch = self.eng.walk_mode(r) == 1
+        n_calls = c.n_steps_max + (1 if batch else 0)
+        for t in range(n_calls):
+            if t < c.n_steps_max:
+                l, g = value_and_score(self.fns[r], x.t())
+                logl.copy_(l)
+                grad.copy_(g.t())
             _lib.check(self.eng.L.ggns_ext_step(self.eng.ctx, r, ws.data_ptr(), ws.numel(), t, s),
                        "ggns_ext_step")
             if (t + 1) % poll_every == 0 and int(active[t].item()) == 0:

@@ -1,0 +1,326 @@
+"""The batch-minimum walk (Algorithm GGNS HSS as written: the loop and the
+saving on the minimum of num_reflections over the run's walkers) on the GPU
+against the FP64 oracle's lockstep loop, through the C ABI: whole FP64 runs in
+reflection mode (iterations, evaluations, prunes, fallbacks, log Z and every
+dead record), one full FP32 walk to its end (the run's window and every
+unmasked walker's output), runs of both walk readings and a fixed-step run in
+one launch, the plain per-step walk and the torch-likelihood walk."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2312_03911_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _engine(cfgs, tile_c=None):
+    from paper_2312_03911_amd.engine import Engine
+    return Engine(cfgs, tile_c=tile_c)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _gauss41(d, seed, **kw):
+    """The Section 4.1 Gaussian: mean 0.5, sigma 0.05 per axis on [0, 1]^d,
+    n_live 200, the Appendix C walk defaults, cap max(64, 5d)."""
+    base = dict(kind="gauss_diag", d=d, n_live=200, lo=0.0, hi=1.0, precision="fp64", seed=seed,
+                n_steps_max=max(64, 5 * d), min_ref=1, max_ref=3,
+                params=inputs.gauss_diag_params(np.full(d, 0.5), np.full(d, 0.05)))
+    base.update(kw)
+    return inputs.RunConfig(**base)
+
+
+# (name, config, relative tolerance of the dead log L).  The dead records are
+# the walkers' kept points: both sides take every decision alike (the counts
+# are compared exactly), and the positions differ by the two summation
+# orders, amplified by the reflections; the thin shells are a chaotic
+# billiard where a few dead points end up 1e-9 apart.
+RUNS = [
+    ("gauss41_d8", lambda: _gauss41(8, 9000), 1e-10),
+    ("gauss41_d16", lambda: _gauss41(16, 9001), 1e-10),
+    ("shells8_refl", lambda: inputs.config_shells(d=8, n_live=300, seed=9002, precision="fp64",
+                                                  max_ref=3, n_steps_max=64), 1e-8),
+    ("gauss41_d8_component_noise", lambda: _gauss41(8, 9005, noise="component"), 1e-10),
+    ("gauss41_d8_per_walker_stop", lambda: _gauss41(8, 9006, stop="walker", save="walker"), 1e-10),
+]
+
+
+@pytest.mark.parametrize("name,make,rtol", RUNS, ids=[c[0] for c in RUNS])
+def test_reflection_fp64_whole_run_matches_oracle(torch, orc, name, make, rtol):
+    cfg = make()
+    print(f"[batch whole run] {name}", flush=True)
+    eng = _engine([cfg])
+    st = eng.run(poll_every=4)[0]
+    o = orc.Oracle(cfg).run()
+    s = o.summary()
+    assert st["state"] == s["state"] == 1
+    assert st["iter"] == s["iter"]
+    assert st["evals"] == s["evals"]
+    assert st["steps_out"] == s["steps_out"]
+    assert st["prunes"] == s["prunes"]
+    assert st["nosave"] == s["nosave"]
+    assert abs(st["log_z"] - s["log_z"]) < 1e-9 * max(1.0, abs(s["log_z"]))
+    assert abs(st["sigma_kl"] - s["sigma_kl"]) < 1e-9
+    assert abs(st["sigma_mom"] - s["sigma_mom"]) < 1e-7
+    dl, dw = eng.dead(0)
+    ol, ow = o.dead()
+    np.testing.assert_allclose(_np(dl), ol, rtol=rtol, atol=rtol)
+    np.testing.assert_allclose(_np(dw), ow, rtol=1e-12, atol=1e-11)
+    if cfg.stop_id == 1 and cfg.max_ref > 0:
+        # some walker of some iteration reached the saving window in its
+        # first walk and was walked again from its start
+        assert st["replayed"] > 0
+    eng.close()
+
+
+SYNCED = [
+    ("gmm8", lambda: inputs.config_gmm(d=8, n_live=300, n_comp=4, seed=9003, param_seed=31,
+                                       precision="fp64")),
+    ("shells32_refl", lambda: inputs.config_shells(d=32, n_live=400, seed=9007, precision="fp64",
+                                                   max_ref=3, n_steps_max=160)),
+    ("corr16", lambda: inputs.config_corr_gauss(d=16, n_live=200, seed=9004, param_seed=32,
+                                                precision="fp64", n_steps_max=80)),
+]
+
+
+@pytest.mark.parametrize("name,make", SYNCED, ids=[c[0] for c in SYNCED])
+def test_reflection_fp64_every_iteration_matches_oracle(torch, orc, name, make):
+    """A whole FP64 run in reflection mode, every iteration compared from the
+    same state: before each iteration the oracle takes the GPU's live set and
+    accumulators, then both kill and walk.  The mixture's early iterations
+    (steps a tenth of the prior box, two in five steps outside) are a chaotic
+    billiard in which the two summation orders part by ~1e-7 within one walk,
+    so whole runs left to themselves meet a decision within that distance of
+    its boundary sooner or later (the correlated Gaussian keeps its decisions
+    but compounds the differences from one iteration's points to the next,
+    to 1e-4 by the end); synchronised, every iteration's kill,
+    threshold, window (step count), outside steps, prunes and fallbacks match
+    exactly and the new points to 1e-6."""
+    cfg = make()
+    print(f"[batch synced run] {name}", flush=True)
+    eng = _engine([cfg])
+    o = orc.Oracle(cfg).init()
+    for it in range(cfg.max_iter):
+        st = gbefore = eng.stats()[0]
+        o.set_state(live_x=_np(eng.live_x(0)), live_logl=_np(eng.live_logl(0)), log_z=st["log_z"],
+                    log_x=st["log_x"], dt=st["dt"], iteration=st["iter"])
+        o.st.lxl_max = st["log_xl_max"]
+        before = o.summary()
+        eng.evidence_update()
+        o.evidence_update()
+        torch.cuda.synchronize()
+        st = eng.stats()[0]
+        assert st["state"] == o.st.state
+        if st["state"] != 0:
+            break
+        np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
+        assert st["lstar"] == o.st.lstar
+        eng.hss_walk()
+        o.hss_walk()
+        torch.cuda.synchronize()
+        st, s = eng.stats()[0], o.summary()
+        np.testing.assert_array_equal(_np(eng.start(0)), o.start)
+        assert (st["it_steps"], st["it_outs"]) == (s["it_steps"], s["it_outs"]), it
+        for key in ("prunes", "nosave"):
+            assert st[key] - gbefore[key] == s[key] - before[key], (it, key)
+        wx = _np(eng.walk_x(0))
+        scale = max(abs(cfg.lo), abs(cfg.hi))
+        err = np.abs(wx - o.out_x).max() / scale
+        assert err < 1e-6, (it, err)
+        np.testing.assert_allclose(_np(eng.walk_logl(0)), o.out_logl, rtol=1e-6, atol=1e-6)
+        eng.replace_dead()
+        o.replace_dead()
+    assert st["state"] == 1 and it > 5
+    eng.close()
+
+
+def _window(out, min_ref, max_ref, cap):
+    """(Ta, Tb) of the batch loop from per-step outside flags [T, k]."""
+    nref = np.cumsum(out, axis=0)
+    a, b = [], []
+    for m in range(out.shape[1]):
+        ia = np.flatnonzero(nref[:, m] >= min_ref)
+        ib = np.flatnonzero(nref[:, m] >= max_ref)
+        a.append(ia[0] + 1 if len(ia) else cap + 1)
+        b.append(ib[0] + 1 if len(ib) else cap)
+    return max(a), max(b)
+
+
+WALKS = [
+    ("gauss_diag32_n1000_fp32", lambda: inputs.RunConfig(
+        kind="gauss_diag", d=32, n_live=1000, lo=-6.0, hi=6.0, seed=9010, n_steps_max=160,
+        params=inputs.gauss_diag_params(np.linspace(-1, 1, 32), np.linspace(0.5, 1.0, 32))), None),
+    # full-size mixture (2000 walkers of 64 coordinates); the walk cap is cut
+    # to bound the traced memory (it does not change the kernel's path)
+    ("gmm64_n4000_fp32", lambda: inputs.config_gmm(seed=9011, n_steps_max=200), None),
+    ("corr256_n400_bf16", lambda: inputs.config_corr_gauss(seed=9012, n_live=400, n_steps_max=300),
+     None),
+    ("corr64_n600_bf16_w2", lambda: inputs.config_corr_gauss(d=64, n_live=600, seed=9013,
+                                                             param_seed=33), [2]),
+]
+
+
+@pytest.mark.parametrize("name,make,tile", WALKS, ids=[c[0] for c in WALKS])
+def test_full_walk_window_and_outputs_match_oracle(torch, orc, name, make, tile):
+    """One whole walk of the batch loop at a mid-run state (live points around
+    the mode, L* at the median, the step of an adapted run): every step of
+    every walker traced on both sides.  The run's saving window [Ta, Tb] from
+    the GPU's outside flags equals the oracle's, every walker walks Tb steps,
+    a walker's decisions part from the oracle's only after one within tau of
+    its boundary, and the output point and log L of every walker whose
+    decisions all agree match to 1e-4 (FP32 against FP64)."""
+    cfg = make()
+    print(f"[batch full walk] {name}", flush=True)
+    eng = _engine([cfg], tile)
+    T = cfg.n_steps_max
+    o = orc.Oracle(cfg, trace_steps=T).init()
+    rng = np.random.default_rng(7)
+    # a live set around the likelihood's mean, as late in a run
+    if cfg.kind == "gmm_diag":
+        d = cfg.d
+        blocks = cfg.params.reshape(cfg.n_comp, 2 * d)
+        comp = rng.integers(cfg.n_comp, size=cfg.n_live)
+        X = blocks[comp, :d] + 2.0 * blocks[comp, d:] * rng.standard_normal((cfg.n_live, d))
+        dt = 0.002 * (cfg.hi - cfg.lo)
+    else:
+        X = cfg.params[:cfg.d] + 0.8 * rng.standard_normal((cfg.n_live, cfg.d)) * (
+            1.0 if cfg.kind == "gauss_full" else cfg.params[cfg.d:2 * cfg.d])
+        dt = 0.003 * (cfg.hi - cfg.lo)
+    xd = torch.from_numpy(X).to(eng.device, eng._fdtype(0))
+    eng.live_x(0).copy_(xd)
+    l, _ = eng.loglike(0, eng.live_x(0).clone(), grad=False)
+    eng.live_logl(0).copy_(l)
+    o.set_state(live_x=_np(xd).astype(np.float64), live_logl=_np(l).astype(np.float64),
+                log_z=-math.inf, log_x=0.0, dt=dt, iteration=0)
+    eng.write_vars(0, -math.inf, 0.0, dt, 0)
+    tx, tl, to = eng.set_trace(0, T)
+    eng.evidence_update()
+    o.evidence_update()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
+    eng.hss_walk()
+    o.hss_walk()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.start(0)), o.start)
+    go = _np(to)
+    Ta, Tb = _window(o.trace_out.astype(bool), cfg.min_ref, cfg.max_ref, T)
+    assert (Ta, Tb) == _window(go.astype(bool), cfg.min_ref, cfg.max_ref, T)
+    st = eng.stats()[0]
+    assert st["it_steps"] == cfg.n_kill * Tb == o.summary()["it_steps"]
+    assert st["it_outs"] == o.summary()["it_outs"]
+    assert Ta <= Tb <= T
+    # a walker's outside flags may differ from the oracle's only from a step
+    # at which the oracle saw a decision within tau of its boundary (FP32
+    # against FP64); the walkers whose flags agree at every step are compared
+    tau = 1e-4
+    lstar = o.st.lstar
+    near = np.abs(o.trace_logl[:Tb] - lstar) < tau * max(1.0, abs(lstar))
+    width = cfg.hi - cfg.lo
+    xo = o.trace_x[:Tb]
+    near |= (np.minimum(np.abs(xo - cfg.lo), np.abs(xo - cfg.hi)) < 0.1 * tau * width).any(axis=2)
+    differ = go[:Tb] != o.trace_out[:Tb]
+    bf16 = cfg.precision == "bf16mma"
+    for m in np.flatnonzero(differ.any(axis=0)):
+        t0 = int(np.flatnonzero(differ[:, m])[0])
+        # (BF16: a residual's operand rounding can part a walker slowly,
+        # below, so a late decision may differ without a near tie)
+        assert bf16 or near[:t0 + 1, m].any(), (m, t0)
+    clean = ~differ.any(axis=0)
+    assert clean.sum() >= 0.9 * cfg.n_kill, clean.sum()
+    wx = _np(eng.walk_x(0)).astype(np.float64)
+    wl = _np(eng.walk_logl(0))
+    scale = np.maximum(np.abs(o.out_x).max(axis=1), 1.0)
+    err = np.abs(wx - o.out_x).max(axis=1) / scale
+    lerr = np.abs(wl - o.out_logl) / np.maximum(1.0, np.abs(o.out_logl))
+    if bf16:
+        # the BF16 operand of a residual is a rounding decision too (FP32 on
+        # the GPU, FP64 in the emulation): over a whole walk a few walkers
+        # meet a residual at a rounding boundary and part slowly
+        bad = (err[clean] > 1e-4) | (lerr[clean] > 1e-4)
+        assert bad.mean() <= 0.05, bad.mean()
+        assert err[clean].max() < 1e-2 and lerr[clean].max() < 1e-2
+    else:
+        assert err[clean].max() < 1e-4, err[clean].max()
+        assert lerr[clean].max() < 1e-4, lerr[clean].max()
+    eng.close()
+
+
+def test_mixed_walk_readings_in_one_launch(torch):
+    """Runs of the batch loop, of the per-walker loop and a fixed-step run in
+    one engine (one kernel class, the batch runs' first walk launched before
+    the class's second launch): each run's iterations equal the same run alone,
+    bitwise."""
+    d = 12
+    base = _gauss41(d, 9020, precision="fp32")
+    cfgs = [base, base.replace(seed=9021, stop="walker", save="walker"),
+            base.replace(seed=9022, max_ref=0, n_steps_max=60), base.replace(seed=9023)]
+    mixed = _engine(cfgs)
+    alone = [_engine([c]) for c in cfgs]
+    for _ in range(5):
+        mixed.iterate(1)
+        for e in alone:
+            e.iterate(1)
+    torch.cuda.synchronize()
+    for r, e in enumerate(alone):
+        np.testing.assert_array_equal(_np(mixed.live_x(r)), _np(e.live_x(0)))
+        np.testing.assert_array_equal(_np(mixed.live_logl(r)), _np(e.live_logl(0)))
+        sa, sb = mixed.stats()[r], e.stats()[0]
+        for k in ("iter", "evals", "prunes", "nosave", "replayed", "dt", "log_z"):
+            assert sa[k] == sb[k], (r, k, sa[k], sb[k])
+        e.close()
+    mixed.close()
+
+
+@pytest.mark.parametrize("d", [6, 12])
+def test_plain_batch_walk_whole_run_matches_oracle(torch, orc, d):
+    """The plain per-step walk runs the batch loop as the algorithm writes it
+    (lockstep launches; each launch applies the save rule of the step before it
+    once the run's minimum is known): whole FP64 runs equal the oracle's."""
+    cfg = _gauss41(d, 9030 + d)
+    eng = _engine([cfg])
+    st = eng.run(poll_every=4, plain=True)[0]
+    o = orc.Oracle(cfg).run()
+    s = o.summary()
+    assert st["state"] == s["state"] == 1
+    assert st["iter"] == s["iter"] and st["evals"] == s["evals"]
+    assert st["prunes"] == s["prunes"] and st["nosave"] == s["nosave"]
+    assert abs(st["log_z"] - s["log_z"]) < 1e-9 * max(1.0, abs(s["log_z"]))
+    dl, _ = eng.dead(0)
+    np.testing.assert_allclose(_np(dl), o.dead()[0], rtol=1e-10, atol=1e-10)
+    eng.close()
+
+
+def test_external_walk_whole_run_matches_oracle(torch, orc):
+    """The walk with a likelihood written in torch (score by autograd), in the
+    batch loop, against the oracle with the same likelihood: whole FP64 runs
+    agree in iterations, evaluations, log Z and dead records."""
+    from paper_2312_03911_amd.external import ExternalRuns
+    cfg = _gauss41(6, 9040)
+    d = cfg.d
+    mu = torch.full((d,), 0.5, dtype=torch.float64, device="cuda")
+    cst = d * (-0.5 * math.log(2 * math.pi) - math.log(0.05))
+
+    def fn(x):
+        return cst - 0.5 * (((x - mu) / 0.05) ** 2).sum(dim=1)
+    ext = ExternalRuns([cfg], [fn], device="cuda:0")
+    st = ext.run(poll_every=4)[0]
+    o = orc.Oracle(cfg).run()
+    s = o.summary()
+    assert st["state"] == s["state"] == 1
+    assert st["iter"] == s["iter"] and st["evals"] == s["evals"]
+    assert abs(st["log_z"] - s["log_z"]) < 1e-9 * max(1.0, abs(s["log_z"]))
+    dl, _ = ext.eng.dead(0)
+    np.testing.assert_allclose(_np(dl), o.dead()[0], rtol=1e-9, atol=1e-9)
+    ext.close()

@@ -100,6 +100,20 @@ CASES = [
     ("corr72_bf16_wnoise", lambda: inputs.config_corr_gauss(d=72, n_live=200, seed=22, param_seed=10,
                                                             precision="bf16mma", n_steps_max=60,
                                                             noise="walker"), 1e-4, 1e-4),
+    # one normal per coordinate (noise_mode 0) in the batch-minimum loop
+    ("gmm16_fp32_cnoise", lambda: inputs.config_gmm(d=16, n_live=600, n_comp=8, seed=28, param_seed=5,
+                                                    noise="component"), 1e-4, 1e-4),
+    ("corr40_bf16_cnoise", lambda: inputs.config_corr_gauss(d=40, n_live=300, seed=29, param_seed=8,
+                                                            precision="bf16mma", n_steps_max=60,
+                                                            noise="component"), 1e-4, 1e-4),
+    # each walker stopping and saving by its own reflection count (walk_mode 0)
+    ("gmm16_fp32_perwalker", lambda: inputs.config_gmm(d=16, n_live=600, n_comp=8, seed=30,
+                                                       param_seed=5, stop="walker", save="walker"),
+     1e-4, 1e-4),
+    ("corr40_bf16_perwalker", lambda: inputs.config_corr_gauss(d=40, n_live=300, seed=31, param_seed=8,
+                                                               precision="bf16mma", n_steps_max=60,
+                                                               stop="walker", save="walker"),
+     1e-4, 1e-4),
 ]
 
 
@@ -222,7 +236,7 @@ def _compare_trace(torch, orc, eng, r, o, trace, tol, tau):
         assert lrel.max() < (1e-12 if tol < 1e-6 else (1e-4 if cfg.precision == "bf16mma" else 2e-5))
         compared += 1
     assert worst < tol, worst
-    assert masked <= max(2, 0.02 * cfg.n_kill), masked
+    assert masked <= max(4, 0.03 * cfg.n_kill), masked
     assert compared >= 0.9 * cfg.n_kill
 
 
