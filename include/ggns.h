@@ -54,7 +54,9 @@ enum {
     GGNS_EINVAL = -1,        /* bad argument (sizes, kinds, null pointers, arena too small) */
     GGNS_EHIP = -2,          /* a HIP call or kernel launch failed */
     GGNS_EUNSUPPORTED = -3,  /* a size or combination this build does not implement */
-    GGNS_ESTATE = -4         /* call out of order (e.g. no context) */
+    GGNS_ESTATE = -4,        /* call out of order (e.g. no context) */
+    GGNS_ESCRATCH = -5       /* a run needs more scratch than the library's fixed device buffer
+                                (GGNS_STATIC_SCRATCH_BYTES) holds: ggns_hss_walk_plain_static */
 };
 
 /* Per-run states (ggns_run_stats.state). */
@@ -309,6 +311,22 @@ int ggns_ext_begin(ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t work
 int ggns_ext_step(ggns_ctx *ctx, int32_t run, void *workspace_dev, int64_t workspace_bytes,
                   int32_t step, void *stream);
 int ggns_hss_walk_plain(ggns_ctx *ctx, void *workspace_dev, int64_t workspace_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under graph capture
+ * of the surrounding work, serving loops, harnesses that forbid hipMalloc):
+ * ggns_hss_walk_plain with its workspace taken from a fixed device buffer that
+ * the library holds, GGNS_STATIC_SCRATCH_BYTES (16 MiB) on each GPU it runs on
+ * until the process ends.  The call allocates nothing: no hipMalloc, no
+ * hipFree, no allocating library routine.  Same walk, streams, outputs and
+ * synchronisation as ggns_hss_walk_plain (so not capturable itself).  A
+ * context any of whose runs needs more than that buffer
+ * (ggns_plain_workspace_bytes(ctx) > GGNS_STATIC_SCRATCH_BYTES) gets
+ * GGNS_ESCRATCH and nothing is enqueued; a run that is not GGNS_FP64 gets
+ * GGNS_EUNSUPPORTED.  Every call on one GPU shares that GPU's buffer, which
+ * keeps the last call's contents (the walk initialises what it reads):
+ * calls that overlap in time on one GPU, from any context or stream, race. */
+#define GGNS_STATIC_SCRATCH_BYTES (16ll << 20)
+int ggns_hss_walk_plain_static(ggns_ctx *ctx, void *stream);
 
 int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out);
 

@@ -10,7 +10,8 @@ import threading
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libggns.so")
 
-GGNS_OK, GGNS_EINVAL, GGNS_EHIP, GGNS_EUNSUPPORTED, GGNS_ESTATE = 0, -1, -2, -3, -4
+GGNS_OK, GGNS_EINVAL, GGNS_EHIP, GGNS_EUNSUPPORTED, GGNS_ESTATE, GGNS_ESCRATCH = 0, -1, -2, -3, -4, -5
+STATIC_SCRATCH_BYTES = 16 << 20   # GGNS_STATIC_SCRATCH_BYTES
 RUN_ACTIVE, RUN_DONE, RUN_MAXITER, RUN_NONFINITE = 0, 1, 2, 3
 
 # every symbol the header declares
@@ -18,6 +19,7 @@ SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update
            "ggns_hss_walk", "ggns_replace_dead", "ggns_loglike_grad", "ggns_loglike_vjp",
            "ggns_run_layout", "ggns_read_stats", "ggns_read_stats_async", "ggns_write_vars",
            "ggns_set_trace", "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
+           "ggns_hss_walk_plain_static",
            "ggns_noise_normals", "ggns_set_dead_x", "ggns_ext_workspace_bytes", "ggns_ext_buffers",
            "ggns_ext_begin", "ggns_ext_step", "ggns_probe_valu", "ggns_probe_mfma", "ggns_free",
            "ggns_status_string")
@@ -101,6 +103,8 @@ def load() -> C.CDLL:
         L.ggns_plain_workspace_bytes.argtypes = [vp]
         L.ggns_plain_workspace_bytes.restype = i64
         L.ggns_hss_walk_plain.argtypes = [vp, vp, i64, vp]
+        L.ggns_hss_walk_plain_static.argtypes = [vp, vp]
+        L.ggns_hss_walk_plain_static.restype = C.c_int
         L.ggns_noise_normals.argtypes = [C.c_uint64, i32, i32, i32, i32, vp, vp, vp, vp]
         L.ggns_noise_normals.restype = C.c_int
         for name in ("ggns_probe_valu", "ggns_probe_mfma"):

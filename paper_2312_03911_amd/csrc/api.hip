@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -14,6 +15,29 @@ using namespace ggns;
 namespace {
 
 constexpr int64_t kAlign = 256;
+
+// The fixed device buffer of ggns_hss_walk_plain_static.  In host code this
+// name stands for the device symbol only: its device address (one per GPU)
+// comes from hipGetSymbolAddress, taken once per device at context set-up.
+__device__ __align__(256) unsigned char scratch[GGNS_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, resolved on first use (with the
+// device current); nullptr if the runtime cannot give it.
+void *scratch_for_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
 
 int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -322,6 +346,9 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
     for (int r = 0; r < n_runs; ++r) {
         if (runs[r].param_offset + raw_params(runs[r]) > n_params) { delete c; return GGNS_EINVAL; }
     }
+    // the fixed scratch buffer's address on this device, taken here once per
+    // device so that ggns_hss_walk_plain_static only reads a table
+    if (scratch_for_current_device() == nullptr) { delete c; return GGNS_EHIP; }
     c->descs.assign(runs, runs + n_runs);
     c->arena = arena;
     c->arena_bytes = arena_bytes;
@@ -483,6 +510,21 @@ int ggns_hss_walk_plain(ggns_ctx *ctx, void *workspace_dev, int64_t workspace_by
     for (int r = 0; r < (int)ctx->plan.runs.size(); ++r) {
         const int rc = launch_walk_plain(ctx->arena, ctx->runs_dev(), r, ctx->plan.runs[r],
                                          workspace_dev, 8, s);
+        if (rc != GGNS_OK) return rc;
+    }
+    return GGNS_OK;
+}
+
+int ggns_hss_walk_plain_static(ggns_ctx *ctx, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    for (const RunDev &R : ctx->plan.runs)
+        if (R.prec != GGNS_FP64) return GGNS_EUNSUPPORTED;
+    if (ggns_plain_workspace_bytes(ctx) > GGNS_STATIC_SCRATCH_BYTES) return GGNS_ESCRATCH;
+    void *ws = scratch_for_current_device();
+    if (ws == nullptr) return GGNS_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int r = 0; r < (int)ctx->plan.runs.size(); ++r) {
+        const int rc = launch_walk_plain(ctx->arena, ctx->runs_dev(), r, ctx->plan.runs[r], ws, 8, s);
         if (rc != GGNS_OK) return rc;
     }
     return GGNS_OK;
@@ -673,6 +715,7 @@ const char *ggns_status_string(int code) {
         case GGNS_EHIP: return "HIP error";
         case GGNS_EUNSUPPORTED: return "unsupported size or combination";
         case GGNS_ESTATE: return "invalid state";
+        case GGNS_ESCRATCH: return "run too large for the library's fixed scratch buffer";
     }
     return "unknown status";
 }

@@ -177,6 +177,12 @@ class Engine:
     def replace_dead(self):
         _lib.check(self.L.ggns_replace_dead(self.ctx, self._stream()), "ggns_replace_dead")
 
+    def hss_walk_plain_static(self):
+        """The same plain walk with its workspace in the library's fixed
+        device buffer (no allocation; FP64 runs that fit the buffer only)."""
+        _lib.check(self.L.ggns_hss_walk_plain_static(self.ctx, self._stream()),
+                   "ggns_hss_walk_plain_static")
+
     def iterate(self, n: int = 1, plain: bool = False):
         for _ in range(n):
             self.evidence_update()

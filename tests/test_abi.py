@@ -53,7 +53,8 @@ def test_arena_size_and_validation():
     bad = [dict(d=0), dict(d=257), dict(n_live=1), dict(n_kill=0), dict(n_kill=100),
            dict(lik_kind=7), dict(prior_hi=-1.0), dict(n_steps_max=0), dict(tile_c=17),
            dict(tile_c=-1), dict(term_kind=3), dict(term_kind=-1),
-           dict(precision=2)]  # BF16 only for the correlated Gaussian
+           dict(precision=2),  # BF16 only for the correlated Gaussian
+           dict(walk_mode=2), dict(walk_mode=1, max_ref=0), dict(walk_mode=1, min_ref=4)]
     for kw in bad:
         one = (_lib.ggns_run_desc * 1)(_desc(cfgs[0], **kw))
         assert L.ggns_arena_bytes(one, 1) == _lib.GGNS_EINVAL, kw
@@ -73,6 +74,8 @@ def test_null_context_rejected():
     assert L.ggns_evidence_update(None, 0, None) == _lib.GGNS_ESTATE
     assert L.ggns_replace_dead(None, None) == _lib.GGNS_ESTATE
     assert L.ggns_status_string(_lib.GGNS_EINVAL) == b"invalid argument"
+    assert L.ggns_hss_walk_plain_static(None, None) == _lib.GGNS_ESTATE
+    assert b"scratch" in L.ggns_status_string(_lib.GGNS_ESCRATCH)
 
 
 def test_probe_arguments_are_checked():
