@@ -145,7 +145,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         bhi[c] = VALID(c) ? hi : INFINITY;
     }
 
-    auto start_walker = [&](int mm) {
+    auto start_walker = [&](int mm) __attribute__((always_inline)) {
         uint32_t w[4];
         draw4(seed, 0u, (uint32_t)mm, it, TAG_START, 0u, w);
         int cl;
@@ -174,8 +174,8 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     };
 
     // walker state between the two launches (layout as in the vector-ALU walk)
-    auto wrow = [&](int mm) { return wst + (int64_t)mm * R.wstate_stride; };
-    auto save_walker = [&]() {
+    auto wrow = [&](int mm) __attribute__((always_inline)) { return wst + (int64_t)mm * R.wstate_stride; };
+    auto save_walker = [&]() __attribute__((always_inline)) {
         unsigned char *row = wrow(m);
         float *sx = reinterpret_cast<float *>(row), *sp = sx + DP, *so = sp + DP;
         uint32_t *se = reinterpret_cast<uint32_t *>(so + DP);
@@ -200,7 +200,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             atomicMax(&acc->win_b, steps);
         }
     };
-    auto acquire = [&](int mm) {
+    auto acquire = [&](int mm) __attribute__((always_inline)) {
         if (cont) {
             const unsigned char *row = wrow(mm);
             const float *sx = reinterpret_cast<const float *>(row), *sp = sx + DP, *so = sp + DP;
@@ -233,7 +233,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
         start_walker(mm);
     };
-    auto emit = [&]() {
+    auto emit = [&]() __attribute__((always_inline)) {
         if (first) {
             save_walker();
             return;
@@ -254,7 +254,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     // slots whose walker is done emit it and take the next walkers of the tile
     // in slot order, until each has a walker with steps to go (or none is
     // left); every lane of every wavefront sees the same masks
-    auto retire = [&](bool need) {
+    auto retire = [&](bool need) __attribute__((always_inline)) {
         while (__any(need)) {
             if (need) emit();
             const uint32_t fin = (uint32_t)(__ballot(need) & 0xFFFFull);

@@ -192,7 +192,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0, a_step = never;
     double out_l = 0.0;
 
-    auto start_walker = [&](int mm) {
+    auto start_walker = [&](int mm) __attribute__((always_inline)) {
         uint32_t w[4];
         draw4(seed, 0u, (uint32_t)mm, it, TAG_START, 0u, w);
         int cl;
@@ -224,8 +224,8 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     // the fallback point (T), the noise stream states (one per block of four
     // coordinates), the reservoir stream, the counters and the fallback log L
     const int wdp = (int)((R.wstate_stride - 80) / (3 * (int64_t)sizeof(T) + 4));
-    auto wrow = [&](int mm) { return wst + (int64_t)mm * R.wstate_stride; };
-    auto save_walker = [&]() {
+    auto wrow = [&](int mm) __attribute__((always_inline)) { return wst + (int64_t)mm * R.wstate_stride; };
+    auto save_walker = [&]() __attribute__((always_inline)) {
         unsigned char *row = wrow(m);
         T *sx = reinterpret_cast<T *>(row), *sp = sx + wdp, *so = sp + wdp;
         uint32_t *se = reinterpret_cast<uint32_t *>(so + wdp);
@@ -254,7 +254,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     };
     // the continuation takes a walker up where its first walk left it, unless
     // that walk reached the saving window: then it walks again from its start
-    auto acquire = [&](int mm) {
+    auto acquire = [&](int mm) __attribute__((always_inline)) {
         if (cont) {
             const unsigned char *row = wrow(mm);
             const T *sx = reinterpret_cast<const T *>(row), *sp = sx + wdp, *so = sp + wdp;
@@ -288,7 +288,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         start_walker(mm);
     };
     // a walker ends: its state (first walk), or its kept point and counts
-    auto emit = [&]() {
+    auto emit = [&]() __attribute__((always_inline)) {
         if (first) {
             save_walker();
             return;
@@ -309,7 +309,7 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     };
     // the group's walker is done (groups enter whole): emit it and take the
     // next walkers of the tile until one has steps to go
-    auto retire = [&]() {
+    auto retire = [&]() __attribute__((always_inline)) {
         bool need = true;
         while (need) {
             emit();
