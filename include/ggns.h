@@ -142,7 +142,10 @@ typedef struct {
                                 prior volumes (Section 3, mode collapse mitigation; Algorithm GGNS
                                 with its cluster-finding algorithm; Eqs. update0, update2, new0);
                                 0: one cluster.  sigma_mom is not computed in cluster mode. */
-    int32_t cluster_kmax;    /* largest neighbour count the cluster finding tries, 2..8 */
+    int32_t cluster_kmax;    /* largest neighbour count the cluster finding tries, 2..32 (the
+                                neighbours are found in passes of eight, a pass only for the
+                                clusters whose loop has not stopped; a cluster still going at
+                                cluster_kmax stays whole, counted in the table's n_cut) */
     int32_t walk_mode;       /* reflection-mode walks (max_ref > 0), Algorithm GGNS HSS:
                                 1 = the loop runs while the minimum of num_reflections over the
                                 run's n_kill walkers is below max_ref (every walker moves until the
@@ -175,7 +178,13 @@ typedef struct {
     int64_t cluster_table;   /* cluster mode: double log_xbar[64], double spawn_cdf[64],
                                 int32 n_live[64], int32 survivor_offsets[65],
                                 int32 member_offsets[65], int32 n_clusters, n_splits, stopping,
-                                pad; survivors are grouped by cluster; else -1 */
+                                pad, int32 need[64], cc_done, n_cut, pad[2], then the logs of the
+                                cluster moments double Zbar_p[64], Z2bar_p[64], ZXbar_p[64],
+                                ZpXpbar_p[64], X2bar_p[64], XpXqbar[64][64]; survivors are
+                                grouped by cluster; else -1 */
+    int64_t knn;             /* cluster mode: [n_live][32] int32 neighbour slots of each live
+                                slot within its cluster, nearest first; else -1 */
+    int64_t knn_dist;        /* cluster mode: [n_live][32] double, their squared distances */
 } ggns_layout;
 
 /* Per-run results and counters. */

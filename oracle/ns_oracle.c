@@ -387,8 +387,14 @@ typedef struct {
     int32_t *start_cl;     /* [n_kill] cluster of each walker */
     int32_t n_clusters, n_splits;
     int32_t split_kmax;    /* the largest neighbour count at which a split was made */
-    int32_t pad3;
+    int32_t kstop_max;     /* the largest neighbour count the loop reached (stop or end) */
+    /* cluster moments (cluster_mode 1), logs of: Zbar_p, Z2bar_p, (Z X_p)bar,
+     * (Z_p X_p)bar, (X_p^2)bar [ORC_CL_MAX each], then (X_p X_q)bar
+     * [ORC_CL_MAX x ORC_CL_MAX]; see ORC_CM_* */
+    double *cm;
 } orc_state;
+
+static void moments_init(orc_state *S);
 
 /* Step 1 of the outer loop: n_live uniform prior draws and their likelihoods
  * (Algorithm GGNS, first three lines); moments as in Eqs. (ini0)-(ini11). */
@@ -422,6 +428,8 @@ int orc_init(const orc_desc *D, const double *prm, orc_state *S)
         S->n_clusters = 1;
         S->n_splits = 0;
         S->split_kmax = 0;
+        moments_init(S);
+        S->kstop_max = 0;
         S->clx[0] = 0.0;
         S->cn[0] = n;
     }
@@ -504,7 +512,7 @@ static void final_sweep(const orc_desc *D, orc_state *S)
     S->h = h;
     S->sigma_kl = sqrt(h > 0.0 ? h / n : 0.0);
     double v = S->lz2 - 2.0 * S->lz;
-    S->sigma_mom = D->cluster_mode ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
+    S->sigma_mom = sqrt(v > 0.0 ? v : 0.0);
 }
 
 /* ------------------------------------------------------------------------
@@ -534,10 +542,178 @@ static void final_sweep(const orc_desc *D, orc_state *S)
  *       over the clusters with survivors (start stream word 1, inverse CDF in
  *       cluster order), then a start uniformly among that cluster's survivors
  *       (word 0); the new point joins that cluster;
- *   C6  the second-moment recursion is single-cluster only: sigma_mom is not
- *       computed in cluster mode (sigma_KL is).
+ *   C6  the second moments follow the cluster recursion, Eqs. (update0)-
+ *       (update9) per killed point and (new0)-(new6) per split (see
+ *       moments_kill, moments_split); sigma_mom from log Z2bar and log Zbar
+ *       as in the single-cluster case.
  * ------------------------------------------------------------------------ */
 #define ORC_CL_MAX 64
+
+/* The moments of the cluster recursion (Eqs. ini0-ini11, update0-update9,
+ * new0-new6), all kept as logarithms (every moment is >= 0):
+ *   lzp[p]   log Zbar_p          evidence of cluster p
+ *   lz2p[p]  log (Z_p^2)bar
+ *   lzx[p]   log (Z X_p)bar      run evidence times the cluster's volume
+ *   lzpx[p]  log (Z_p X_p)bar
+ *   lx2[p]   log (X_p^2)bar
+ *   lxx[p][q] log (X_p X_q)bar   (p != q; symmetric)
+ * beside log Zbar, log Z2bar (the run's) and log Xbar_p (clx). */
+#define ORC_CM_LZP 0
+#define ORC_CM_LZ2P (ORC_CL_MAX)
+#define ORC_CM_LZX (2 * ORC_CL_MAX)
+#define ORC_CM_LZPX (3 * ORC_CL_MAX)
+#define ORC_CM_LX2 (4 * ORC_CL_MAX)
+#define ORC_CM_LXX (5 * ORC_CL_MAX)
+#define ORC_CM_SIZE (5 * ORC_CL_MAX + ORC_CL_MAX * ORC_CL_MAX)
+
+/* Eqs. (ini0)-(ini11): one cluster holding the whole prior, Xbar = 1,
+ * (X^2)bar = 1 (its value for the volume before any kill), no evidence. */
+static void moments_init(orc_state *S)
+{
+    double *cm = S->cm;
+    for (int i = 0; i < ORC_CM_SIZE; ++i) cm[i] = -INFINITY;
+    cm[ORC_CM_LX2 + 0] = 0.0;
+    S->lz = -INFINITY;
+    S->lz2 = -INFINITY;
+}
+
+/* Kill a point of log-likelihood l from cluster p, which holds n_p live
+ * points before the removal: the dead record with weight Xbar_p / (n_p + 1),
+ * then Eqs. (update0)-(update9), every right-hand side taking the values
+ * before this kill.  In (update3) the likelihood is the killed point's (the
+ * subscript of the printed L_p is read as a typo), and in (update6) the
+ * cross moment added to is (Z X_q)bar, the right-hand side's (Z X_p)bar read
+ * as a typo for it. */
+static void moments_kill(orc_state *S, double l, int p)
+{
+    double *cm = S->cm;
+    const int nq = S->n_clusters;
+    const int n_p = S->cn[p];
+    const double ln = log((double)n_p), ln1 = log((double)n_p + 1.0), ln2 = log((double)n_p + 2.0);
+    const double lx = S->clx[p], lzx = cm[ORC_CM_LZX + p], lx2 = cm[ORC_CM_LX2 + p];
+    const double lzp = cm[ORC_CM_LZP + p], lz2p = cm[ORC_CM_LZ2P + p], lzpx = cm[ORC_CM_LZPX + p];
+    const double l2 = log(2.0);
+    const double logw = lx - ln1;
+    if (S->n_dead < S->dead_cap) {
+        S->dead_logl[S->n_dead] = l;
+        S->dead_logw[S->n_dead] = logw;
+    }
+    S->n_dead += 1;
+    S->lz = logaddexp(S->lz, lx + l - ln1);                                        /* update0 */
+    cm[ORC_CM_LZP + p] = logaddexp(lzp, lx + l - ln1);                           /* update1 */
+    S->clx[p] = lx + ln - ln1;                                                    /* update2 */
+    S->lz2 = logaddexp(S->lz2, logaddexp(l2 + lzx + l - ln1,
+                                         l2 + lx2 + 2.0 * l - ln1 - ln2));       /* update3 */
+    cm[ORC_CM_LZ2P + p] = logaddexp(lz2p, logaddexp(l2 + lzpx + l - ln1,
+                                                    l2 + lx2 + 2.0 * l - ln1 - ln2)); /* update4 */
+    cm[ORC_CM_LZX + p] = logaddexp(ln + lzx - ln1, ln + lx2 + l - ln1 - ln2);    /* update5 */
+    for (int q = 0; q < nq; ++q)                                                  /* update6 */
+        if (q != p) cm[ORC_CM_LZX + q] = logaddexp(cm[ORC_CM_LZX + q],
+                                                   cm[ORC_CM_LXX + p * ORC_CL_MAX + q] + l - ln1);
+    cm[ORC_CM_LZPX + p] = logaddexp(ln + lzpx - ln1, ln + lx2 + l - ln1 - ln2);  /* update7 */
+    cm[ORC_CM_LX2 + p] = lx2 + ln - ln2;                                          /* update8 */
+    for (int q = 0; q < nq; ++q) {                                                /* update9 */
+        if (q == p) continue;
+        const double v = cm[ORC_CM_LXX + p * ORC_CL_MAX + q] + ln - ln1;
+        cm[ORC_CM_LXX + p * ORC_CL_MAX + q] = v;
+        cm[ORC_CM_LXX + q * ORC_CL_MAX + p] = v;
+    }
+    S->cn[p] = n_p - 1;
+    if (S->cn[p] == 0) S->clx[p] = -INFINITY;
+}
+
+/* Split cluster p of m points into nc clusters of cnt[c] points, component c
+ * taking index q[c] (q[0] = p): Eqs. (new0)-(new6) from the values of p
+ * before the split.  (new3) with Y = X_r applies to every other existing
+ * cluster r; (new2) gives the cross moments between the new clusters. */
+static void moments_split(orc_state *S, int p, int m, int nc, const int32_t *cnt, const int *q)
+{
+    double *cm = S->cm;
+    const double lx = S->clx[p], lx2 = cm[ORC_CM_LX2 + p], lzx = cm[ORC_CM_LZX + p];
+    const double lzp = cm[ORC_CM_LZP + p], lz2p = cm[ORC_CM_LZ2P + p], lzpx = cm[ORC_CM_LZPX + p];
+    const double lm = log((double)m), lmm = log((double)m * (m + 1.0));
+    const int n_before = S->n_clusters;
+    double lxr[ORC_CL_MAX];
+    for (int r = 0; r < n_before; ++r) lxr[r] = cm[ORC_CM_LXX + p * ORC_CL_MAX + r];
+    for (int c = 0; c < nc; ++c) {
+        const int qc = q[c];
+        const double ln = log((double)cnt[c]), lnn = log((double)cnt[c] * (cnt[c] + 1.0));
+        S->clx[qc] = lx + ln - lm;                                   /* new0 */
+        cm[ORC_CM_LX2 + qc] = lx2 + lnn - lmm;                       /* new1 */
+        cm[ORC_CM_LZX + qc] = lzx + ln - lm;                         /* new3, Y = Z */
+        cm[ORC_CM_LZP + qc] = lzp + ln - lm;                         /* new4 */
+        cm[ORC_CM_LZPX + qc] = lzpx + lnn - lmm;                     /* new5 */
+        cm[ORC_CM_LZ2P + qc] = lz2p + lnn - lmm;                     /* new6 */
+        for (int r = 0; r < n_before; ++r) {                         /* new3, Y = X_r */
+            if (r == p) continue;
+            const double v = lxr[r] + ln - lm;
+            cm[ORC_CM_LXX + qc * ORC_CL_MAX + r] = v;
+            cm[ORC_CM_LXX + r * ORC_CL_MAX + qc] = v;
+        }
+        S->cn[qc] = cnt[c];
+    }
+    for (int a = 0; a < nc; ++a)                                     /* new2 */
+        for (int b = 0; b < nc; ++b) {
+            if (a == b) continue;
+            cm[ORC_CM_LXX + q[a] * ORC_CL_MAX + q[b]] =
+                lx2 + log((double)cnt[a] * (double)cnt[b]) - lmm;
+        }
+}
+
+/* The cluster recursion over a given event sequence (test hook for the
+ * Monte Carlo pin of the moments): type 0 kills a point of log L l[e] from
+ * cluster cl[e]; type 1 adds a live point to cluster cl[e]; type 2 splits
+ * cluster cl[e] into ncomp[e] clusters whose point counts follow in counts[]
+ * (consumed in order; the new ones take the next free indices).  Starts from
+ * one cluster of n0 points.  Writes log Zbar, log Z2bar, then per cluster
+ * log Zbar_p, log (Z_p^2)bar, log Xbar_p (ORC_CL_MAX each) to out. */
+int orc_moment_sequence(int n0, int n_events, const int32_t *type, const int32_t *cl,
+                        const double *l, const int32_t *ncomp, const int32_t *counts, double *out)
+{
+    orc_state S;
+    memset(&S, 0, sizeof(S));
+    double cm[ORC_CM_SIZE], clx[ORC_CL_MAX], dl[1], dw[1];
+    int32_t cn[ORC_CL_MAX];
+    S.cm = cm;
+    S.clx = clx;
+    S.cn = cn;
+    S.dead_logl = dl;
+    S.dead_logw = dw;
+    S.dead_cap = 0;
+    for (int p = 0; p < ORC_CL_MAX; ++p) { clx[p] = -INFINITY; cn[p] = 0; }
+    clx[0] = 0.0;
+    cn[0] = n0;
+    S.n_clusters = 1;
+    moments_init(&S);
+    int ci = 0;
+    for (int e = 0; e < n_events; ++e) {
+        if (type[e] == 0) {
+            if (cn[cl[e]] < 1) return -1;
+            moments_kill(&S, l[e], cl[e]);
+        } else if (type[e] == 1) {
+            cn[cl[e]] += 1;
+        } else {
+            int nc = ncomp[e], p = cl[e], q[ORC_CL_MAX], m = 0;
+            if (nc < 2 || S.n_clusters + nc - 1 > ORC_CL_MAX) return -1;
+            for (int c = 0; c < nc; ++c) {
+                q[c] = (c == 0) ? p : S.n_clusters + c - 1;
+                m += counts[ci + c];
+            }
+            if (m != cn[p]) return -1;
+            moments_split(&S, p, m, nc, counts + ci, q);
+            S.n_clusters += nc - 1;
+            ci += nc;
+        }
+    }
+    out[0] = S.lz;
+    out[1] = S.lz2;
+    for (int p = 0; p < ORC_CL_MAX; ++p) {
+        out[2 + p] = cm[ORC_CM_LZP + p];
+        out[2 + ORC_CL_MAX + p] = cm[ORC_CM_LZ2P + p];
+        out[2 + 2 * ORC_CL_MAX + p] = clx[p];
+    }
+    return 0;
+}
 
 /* Squared Euclidean distance (FP64). */
 static double dist2(const double *a, const double *b, int d)
@@ -654,20 +830,18 @@ static void find_clusters(const orc_desc *D, orc_state *S)
             nprev = nc;
         }
         free(nb);
+        if ((found ? k : kend) > S->kstop_max) S->kstop_max = found ? k : kend;
         if (!found || nc < 2 || S->n_clusters + nc - 1 > ORC_CL_MAX) continue;
         /* components in order of their smallest slot (= their root, local) */
         for (int i = 0; i < m; ++i) best[i] = -1;
         int next = 0;
         for (int i = 0; i < m; ++i)
             if (root[i] == i) best[i] = next++;
-        double lxp = S->clx[p], lm = log((double)m);
         int32_t *cnt = (int32_t *)calloc((size_t)nc, sizeof(int32_t));
+        int qs[ORC_CL_MAX];
         for (int i = 0; i < m; ++i) cnt[best[root[i]]] += 1;
-        for (int c = 0; c < nc; ++c) {
-            int q = (c == 0) ? p : S->n_clusters + c - 1;
-            S->clx[q] = lxp + log((double)cnt[c]) - lm;
-            S->cn[q] = cnt[c];
-        }
+        for (int c = 0; c < nc; ++c) qs[c] = (c == 0) ? p : S->n_clusters + c - 1;
+        moments_split(S, p, m, nc, cnt, qs);
         for (int i = 0; i < m; ++i) {
             int c = best[root[i]];
             S->label[idx[i]] = (c == 0) ? p : S->n_clusters + c - 1;
@@ -688,21 +862,11 @@ static double log_sum_clusters(const orc_state *S)
     return r;
 }
 
-/* Kill one point of cluster p (C4): dead record, evidence, volume. */
+/* Kill one point of cluster p (C4): dead record, evidence, volume and the
+ * moments of the cluster recursion. */
 static void kill_one_cluster(orc_state *S, double l, int p)
 {
-    int n_p = S->cn[p];
-    double ln = log((double)n_p), ln1 = log((double)n_p + 1.0);
-    double logw = S->clx[p] - ln1;
-    if (S->n_dead < S->dead_cap) {
-        S->dead_logl[S->n_dead] = l;
-        S->dead_logw[S->n_dead] = logw;
-    }
-    S->n_dead += 1;
-    S->lz = logaddexp(S->lz, logw + l);
-    S->clx[p] = S->clx[p] + ln - ln1;
-    S->cn[p] = n_p - 1;
-    if (S->cn[p] == 0) S->clx[p] = -INFINITY;
+    moments_kill(S, l, p);
 }
 
 /* Termination test, kill step and evidence update of one iteration

@@ -69,9 +69,11 @@ class _State(C.Structure):
                 ("trace_steps", C.c_int32), ("pad2", C.c_int32),
                 ("label", _PI), ("clx", _PD), ("cn", _PI), ("surv_off", _PI), ("start_cl", _PI),
                 ("n_clusters", C.c_int32), ("n_splits", C.c_int32),
-                ("split_kmax", C.c_int32), ("pad3", C.c_int32)]
+                ("split_kmax", C.c_int32), ("kstop_max", C.c_int32),
+                ("cm", _PD)]
 
 CL_MAX = 64
+CM_SIZE = 5 * CL_MAX + CL_MAX * CL_MAX
 
 
 def stale() -> bool:
@@ -105,6 +107,8 @@ def lib():
                                            C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]
             L.orc_round_bf16.argtypes = [C.c_double]
             L.orc_round_bf16.restype = C.c_double
+            L.orc_moment_sequence.argtypes = [C.c_int, C.c_int, _PI, _PI, _PD, _PI, _PI, _PD]
+            L.orc_moment_sequence.restype = C.c_int
             L.orc_num_threads.restype = C.c_int
             L.orc_set_threads.argtypes = [C.c_int]
             _lib = L
@@ -180,6 +184,27 @@ def loglike(cfg, x, bf16: bool = False):
     return logl, grad
 
 
+def moment_sequence(n0: int, events) -> dict:
+    """The cluster recursion (Eqs. update0-update9, new0-new6) over an event
+    list: ("kill", p, logL), ("add", p), ("split", p, [counts...])."""
+    typ, cl, lv, nco, cnts = [], [], [], [], []
+    for ev in events:
+        if ev[0] == "kill":
+            typ.append(0); cl.append(ev[1]); lv.append(float(ev[2])); nco.append(0)
+        elif ev[0] == "add":
+            typ.append(1); cl.append(ev[1]); lv.append(0.0); nco.append(0)
+        else:
+            typ.append(2); cl.append(ev[1]); lv.append(0.0); nco.append(len(ev[2])); cnts.extend(ev[2])
+    t = np.array(typ, np.int32); c = np.array(cl, np.int32); lv = np.array(lv, np.float64)
+    nc = np.array(nco, np.int32); cn = np.array(cnts or [0], np.int32)
+    out = np.zeros(2 + 3 * CL_MAX)
+    rc = lib().orc_moment_sequence(int(n0), len(t), _ip(t), _ip(c), _dp(lv), _ip(nc), _ip(cn), _dp(out))
+    if rc != 0:
+        raise ValueError("inconsistent event sequence")
+    return {"log_z": out[0], "log_z2": out[1], "log_zp": out[2:2 + CL_MAX],
+            "log_z2p": out[2 + CL_MAX:2 + 2 * CL_MAX], "log_xp": out[2 + 2 * CL_MAX:]}
+
+
 # ---------------------------------------------------------------- sampler
 
 class Oracle:
@@ -234,6 +259,8 @@ class Oracle:
         self.start_cl = np.zeros(k, np.int32)
         self.st.label, self.st.clx, self.st.cn = _ip(self.label), _dp(self.clx), _ip(self.cn)
         self.st.surv_off, self.st.start_cl = _ip(self.surv_off), _ip(self.start_cl)
+        self.cm = np.full(CM_SIZE, -np.inf)
+        self.st.cm = _dp(self.cm)
 
     # -- steps
     def init(self):

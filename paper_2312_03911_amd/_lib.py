@@ -45,7 +45,8 @@ class ggns_layout(C.Structure):
                 ("survivors", C.c_int64), ("start", C.c_int64), ("walk_x", C.c_int64),
                 ("walk_logl", C.c_int64), ("dead_logl", C.c_int64), ("dead_logw", C.c_int64),
                 ("dead_cap", C.c_int64), ("elem_bytes", C.c_int32), ("reserved", C.c_int32),
-                ("label", C.c_int64), ("cluster_table", C.c_int64)]
+                ("label", C.c_int64), ("cluster_table", C.c_int64),
+                ("knn", C.c_int64), ("knn_dist", C.c_int64)]
 
 
 class ggns_run_stats(C.Structure):

@@ -178,11 +178,13 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
             R.off_cltab = off; off = align_up(off + (int64_t)sizeof(ClusterTab));
             R.off_members = off; off = align_up(off + (int64_t)D.n_live * 4);
             R.off_knn = off; off = align_up(off + (int64_t)D.n_live * kKnnMax * 4);
+            R.off_knn_d = off; off = align_up(off + (int64_t)D.n_live * kKnnMax * 8);
             R.off_start_cl = off; off = align_up(off + (int64_t)D.n_kill * 4);
-            R.off_knn_part = off; off = align_up(off + (int64_t)D.n_live * kKnnSplit * kKnnMax * 8);
-            R.off_knn_part_s = off; off = align_up(off + (int64_t)D.n_live * kKnnSplit * kKnnMax * 4);
+            R.off_knn_part = off; off = align_up(off + (int64_t)D.n_live * kKnnSplit * kKnnPass * 8);
+            R.off_knn_part_s = off; off = align_up(off + (int64_t)D.n_live * kKnnSplit * kKnnPass * 4);
         } else {
             R.off_label = R.off_cltab = R.off_members = R.off_knn = R.off_start_cl = -1;
+            R.off_knn_d = -1;
             R.off_knn_part = R.off_knn_part_s = -1;
         }
         if (D.walk_mode == 1) {
@@ -623,6 +625,8 @@ int ggns_run_layout(const ggns_ctx *ctx, int32_t run, ggns_layout *out) {
     out->reserved = 0;
     out->label = R.off_label;
     out->cluster_table = R.off_cltab;
+    out->knn = R.off_knn;
+    out->knn_dist = R.off_knn_d;
     return GGNS_OK;
 }
 

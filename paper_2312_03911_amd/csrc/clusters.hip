@@ -6,14 +6,17 @@
 // its k nearest other points of the cluster (squared Euclidean distance,
 // ties by slot) and the connected components of the undirected graph are
 // taken; the first k whose component sizes equal those of k - 1 gives the
-// clustering (k up to min(cluster_kmax, m - 1), else the cluster stays
-// whole); components ordered by their smallest slot become clusters, the
-// first keeping the old index, at most kClMax in all; Xbar_i = (n_i/n) Xbar_p.
+// clustering (k up to min(cluster_kmax, m - 1), cluster_kmax <= 32, else the
+// cluster stays whole); components ordered by their smallest slot become
+// clusters, the first keeping the old index, at most kClMax in all;
+// Xbar_i = (n_i/n) Xbar_p.
 //
-// Three launches per iteration: cluster_pre (termination decision; the live
-// slots grouped by cluster), knn (one wavefront per point: its nearest
-// neighbours within its cluster, distances summed in FP64 in coordinate order
-// so that neighbour ranks are exact), cluster_cc (one workgroup per run:
+// Launches per iteration: cluster_pre (termination decision; the live slots
+// grouped by cluster), then up to four passes of knn (the next kKnnPass
+// nearest neighbours of every point within its cluster, beyond the last one
+// of the previous pass in (distance, slot) order) and cluster_cc (one
+// workgroup per run: over the neighbours found so far; a cluster whose loop
+// is still going when they run out asks for the next pass, the others wait;
 // union-find over the k-th neighbour edges for k = 1, 2, ...; since the graph
 // for k contains the graph for k - 1, its partition is a coarsening, and equal
 // component sizes are equal component counts, which is what is compared).
@@ -71,7 +74,11 @@ cluster_pre_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep
     }
     lmax = block_max_d(lmax, scratch);
     const int stop = nanflag ? 1 : termination_decision(R, acc, lmax, final_sweep, nullptr);
-    if (t == 0) tab->stopping = stop;
+    if (t == 0) {
+        tab->stopping = stop;
+        tab->cc_done = 0;
+    }
+    for (int p = t; p < kClMax; p += T) tab->need[p] = 0;
     if (stop) return;
     // live slots grouped by cluster: sort of (label << 12 | slot) keys
     if (n <= 1024) group_members<1>(n, label, key, slot_s);
@@ -105,13 +112,13 @@ constexpr int kKnnWaves = 4;
 
 template <typename T, int KN>
 __global__ void __launch_bounds__(64 * kKnnWaves)
-knn_part_kernel(void *arena, const RunDev *__restrict__ runs) {
+knn_part_kernel(void *arena, const RunDev *__restrict__ runs, int pass) {
     const RunDev &R = runs[blockIdx.y];
     if (!R.cluster_mode || (R.prec == GGNS_FP64) != (sizeof(T) == 8)) return;
     const Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
     const ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
-    if (tab->stopping) return;
+    if (tab->stopping || tab->cc_done) return;
     const int n = R.n_live;
     const int qb = blockIdx.x / kKnnSplit, split = blockIdx.x % kKnnSplit;
     const int q0 = qb * 64;
@@ -122,9 +129,20 @@ knn_part_kernel(void *arena, const RunDev *__restrict__ runs) {
     const int32_t *label = at<int32_t>(arena, R.off_label);
     const int32_t *members = at<int32_t>(arena, R.off_members);
     const int qn = (n - q0 < 64) ? n - q0 : 64;
-    const bool qvalid = lane < qn;
-    const int qi = members[q0 + (qvalid ? lane : 0)];
+    const int qi = members[q0 + (lane < qn ? lane : 0)];
     const int qc = label[qi];
+    // after the first pass only the points of clusters whose loop goes on;
+    // the same queries in every wavefront of the block
+    const bool qvalid = lane < qn && (pass == 0 || tab->need[qc] != 0);
+    if (!__any(qvalid)) return;
+    // candidates must come after the last neighbour found by the passes before
+    T thr_d = (T)(-INFINITY);
+    int thr_s = -1;
+    if (pass > 0 && qvalid) {
+        const int64_t at_ = (int64_t)qi * kKnnMax + kKnnPass * pass - 1;
+        thr_d = (T)at<double>(arena, R.off_knn_d)[at_];
+        thr_s = at<int32_t>(arena, R.off_knn)[at_];
+    }
     // candidate range: the clusters of the first and the last query; this
     // block's share of it, and this wavefront's share of that
     const int c_lo = label[members[q0]], c_hi = label[members[q0 + qn - 1]];
@@ -172,7 +190,7 @@ knn_part_kernel(void *arena, const RunDev *__restrict__ runs) {
         for (int t = 0; t < TILE; ++t) {
             const int j = cj[t];
             if (j < 0) continue;
-            const bool ok = qvalid && label[j] == qc && j != qi &&
+            const bool ok = qvalid && label[j] == qc && j != qi && lex_less(thr_d, thr_s, acc2[t], j) &&
                             lex_less(acc2[t], j, bd[KN - 1], bs[KN - 1]);
             if (ok) {
                 bd[KN - 1] = acc2[t];
@@ -200,8 +218,8 @@ knn_part_kernel(void *arena, const RunDev *__restrict__ runs) {
         int head[kKnnWaves];
 #pragma unroll
         for (int w = 0; w < kKnnWaves; ++w) head[w] = 0;
-        double *pd = at<double>(arena, R.off_knn_part) + ((int64_t)(q0 + lane) * kKnnSplit + split) * KN;
-        int32_t *ps = at<int32_t>(arena, R.off_knn_part_s) + ((int64_t)(q0 + lane) * kKnnSplit + split) * KN;
+        double *pd = at<double>(arena, R.off_knn_part) + ((int64_t)(q0 + lane) * kKnnSplit + split) * kKnnPass;
+        int32_t *ps = at<int32_t>(arena, R.off_knn_part_s) + ((int64_t)(q0 + lane) * kKnnSplit + split) * kKnnPass;
         for (int r = 0; r < KN; ++r) {
             int bw = 0;
             T dmin = (T)INFINITY;
@@ -220,38 +238,43 @@ knn_part_kernel(void *arena, const RunDev *__restrict__ runs) {
     }
 }
 
-__global__ void knn_merge_kernel(void *arena, const RunDev *__restrict__ runs) {
+__global__ void knn_merge_kernel(void *arena, const RunDev *__restrict__ runs, int pass) {
     const RunDev &R = runs[blockIdx.y];
     if (!R.cluster_mode) return;
     const Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
     const ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
-    if (tab->stopping) return;
+    if (tab->stopping || tab->cc_done) return;
     const int qpos = blockIdx.x * blockDim.x + threadIdx.x;
     if (qpos >= R.n_live) return;
     const int qi = at<int32_t>(arena, R.off_members)[qpos];
     const int qc = at<int32_t>(arena, R.off_label)[qi];
+    if (pass > 0 && !tab->need[qc]) return;
     const int m = tab->moff[qc + 1] - tab->moff[qc];
     if (m < 3) return;
     const int keff = (R.cluster_kmax < m - 1) ? R.cluster_kmax : m - 1;
-    const double *pd = at<double>(arena, R.off_knn_part) + (int64_t)qpos * kKnnSplit * kKnnMax;
-    const int32_t *ps = at<int32_t>(arena, R.off_knn_part_s) + (int64_t)qpos * kKnnSplit * kKnnMax;
+    const int r0 = kKnnPass * pass;
+    const int nr = (keff - r0 < kKnnPass) ? keff - r0 : kKnnPass;
+    const double *pd = at<double>(arena, R.off_knn_part) + (int64_t)qpos * kKnnSplit * kKnnPass;
+    const int32_t *ps = at<int32_t>(arena, R.off_knn_part_s) + (int64_t)qpos * kKnnSplit * kKnnPass;
     int head[kKnnSplit];
 #pragma unroll
     for (int w = 0; w < kKnnSplit; ++w) head[w] = 0;
-    int32_t *knn = at<int32_t>(arena, R.off_knn) + (int64_t)qi * kKnnMax;
-    for (int r = 0; r < keff; ++r) {
+    int32_t *knn = at<int32_t>(arena, R.off_knn) + (int64_t)qi * kKnnMax + r0;
+    double *knn_d = at<double>(arena, R.off_knn_d) + (int64_t)qi * kKnnMax + r0;
+    for (int r = 0; r < nr; ++r) {
         int bw = 0;
         double dmin = INFINITY;
         int smin = 0x7FFFFFFF;
 #pragma unroll
         for (int w = 0; w < kKnnSplit; ++w) {
-            if (head[w] >= kKnnMax) continue;
-            const double dv = pd[w * kKnnMax + head[w]];
-            const int sv = ps[w * kKnnMax + head[w]];
+            if (head[w] >= kKnnPass) continue;
+            const double dv = pd[w * kKnnPass + head[w]];
+            const int sv = ps[w * kKnnPass + head[w]];
             if (lex_less(dv, sv, dmin, smin)) { dmin = dv; smin = sv; bw = w; }
         }
         knn[r] = smin;
+        knn_d[r] = dmin;
         head[bw] += 1;
     }
 }
@@ -286,13 +309,16 @@ __device__ void sort_roots(int n, const int *label, const int *par, const int *s
 // One workgroup per run: components for k = 1, 2, ... neighbours, the stop
 // rule per cluster, and the splits.
 __global__ void __launch_bounds__(kClThreads)
-cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
+cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs, int pass) {
     const RunDev &R = runs[blockIdx.x];
     if (!R.cluster_mode) return;
     Acc *acc = at<Acc>(arena, R.off_acc);
     if (acc->state != GGNS_RUN_ACTIVE) return;
     ClusterTab *tab = at<ClusterTab>(arena, R.off_cltab);
-    if (tab->stopping) return;
+    if (tab->stopping || tab->cc_done) return;
+    // neighbours available after this pass
+    const int kav = (kKnnPass * (pass + 1) < R.cluster_kmax) ? kKnnPass * (pass + 1) : R.cluster_kmax;
+    __shared__ int any_need;
     __shared__ int par[kMaxLive];
     __shared__ int keff[kClMax], stopped[kClMax], cnt_prev[kClMax], cnt_cur[kClMax];
     __shared__ int nroot[kClMax], roots[kClMax][kClMax], newid_base[kClMax];
@@ -318,7 +344,7 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
     }
     for (int i = t; i < n; i += T) par[i] = i;
     __syncthreads();
-    for (int k = 1; k <= R.cluster_kmax && k <= kKnnMax; ++k) {
+    for (int k = 1; k <= kav; ++k) {
         // add the edges to each point's k-th nearest neighbour, merge roots
         do {
             __syncthreads();
@@ -355,6 +381,23 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs) {
         }
         __syncthreads();
         if (!changed) break;
+    }
+    // a cluster still going when the neighbours found so far run out takes
+    // the next pass (the run's splits wait for it); at the last pass it stays
+    // whole (counted in n_cut)
+    if (t == 0) any_need = 0;
+    __syncthreads();
+    for (int p = t; p < nc0; p += T) {
+        const int nd = (keff[p] && !stopped[p] && keff[p] > kav) ? 1 : 0;
+        tab->need[p] = nd;
+        if (nd) any_need = 1;
+    }
+    __syncthreads();
+    if (any_need && pass + 1 < kKnnPasses) return;
+    if (t == 0) {
+        tab->cc_done = 1;
+        if (any_need)
+            for (int p = 0; p < nc0; ++p) tab->n_cut += tab->need[p];
     }
     // roots of the stopped clusters in ascending slot order: a sort of
     // (cluster << 12 | slot) keys of the roots, then per-cluster runs
@@ -428,15 +471,19 @@ int launch_clusters(void *arena, const RunDev *runs_dev, int n_runs, int max_liv
     hipLaunchKernelGGL(cluster_pre_kernel, dim3(n_runs), dim3(kClThreads), 0, s, arena, runs_dev,
                        final_sweep);
     const dim3 grid((max_live + 63) / 64 * kKnnSplit, n_runs);
-    if (any_fp64)
-        hipLaunchKernelGGL((knn_part_kernel<double, kKnnMax>), grid, dim3(64 * kKnnWaves), 0, s,
-                           arena, runs_dev);
-    if (any_fp32)
-        hipLaunchKernelGGL((knn_part_kernel<float, kKnnMax>), grid, dim3(64 * kKnnWaves), 0, s,
-                           arena, runs_dev);
-    hipLaunchKernelGGL(knn_merge_kernel, dim3((max_live + 255) / 256, n_runs), dim3(256), 0, s,
-                       arena, runs_dev);
-    hipLaunchKernelGGL(cluster_cc_kernel, dim3(n_runs), dim3(kClThreads), 0, s, arena, runs_dev);
+    // every pass is enqueued; a pass nobody needs returns at once
+    for (int pass = 0; pass < kKnnPasses; ++pass) {
+        if (any_fp64)
+            hipLaunchKernelGGL((knn_part_kernel<double, kKnnPass>), grid, dim3(64 * kKnnWaves), 0, s,
+                               arena, runs_dev, pass);
+        if (any_fp32)
+            hipLaunchKernelGGL((knn_part_kernel<float, kKnnPass>), grid, dim3(64 * kKnnWaves), 0, s,
+                               arena, runs_dev, pass);
+        hipLaunchKernelGGL(knn_merge_kernel, dim3((max_live + 255) / 256, n_runs), dim3(256), 0, s,
+                           arena, runs_dev, pass);
+        hipLaunchKernelGGL(cluster_cc_kernel, dim3(n_runs), dim3(kClThreads), 0, s, arena, runs_dev,
+                           pass);
+    }
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }
 

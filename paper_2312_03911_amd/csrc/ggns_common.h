@@ -49,6 +49,7 @@ struct RunDev {
     // live slots grouped by cluster, k-nearest-neighbour lists, walker clusters
     int32_t cluster_mode, cluster_kmax;
     int64_t off_label, off_cltab, off_members, off_knn, off_start_cl;
+    int64_t off_knn_d;         // the neighbours' squared distances (double) beside off_knn
     int64_t off_knn_part, off_knn_part_s;   // per query and share: partial neighbour lists
     int64_t off_surv_sorted;   // survivors of the last kill in (log L, slot) order
     int64_t off_fin;           // run summary: five FP64 partials per chunk of dead records
@@ -59,7 +60,9 @@ constexpr int kFinThreads = 256;                      // run summary: threads pe
 constexpr int kFinPerThread = 16;                     // records per thread
 constexpr int kFinChunk = kFinThreads * kFinPerThread; // records per chunk (one workgroup)
 constexpr int kClMax = 64;      // clusters per run
-constexpr int kKnnMax = 8;      // neighbours kept per point (largest cluster_kmax)
+constexpr int kKnnMax = 32;     // neighbours kept per point (largest cluster_kmax)
+constexpr int kKnnPass = 8;     // neighbours found per search pass
+constexpr int kKnnPasses = kKnnMax / kKnnPass;
 constexpr int kKnnSplit = 16;   // shares of the candidate range searched in parallel
 
 // Per-run cluster table (arena).
@@ -70,6 +73,15 @@ struct ClusterTab {
     int32_t soff[kClMax + 1];   // survivors grouped by cluster: offsets into the survivor list
     int32_t moff[kClMax + 1];   // live slots grouped by cluster: offsets into members
     int32_t n_clusters, n_splits, stopping, pad;
+    // neighbour search in passes of kKnnPass: clusters whose loop needs the
+    // next pass, the run's search finished, loops cut at kKnnMax
+    int32_t need[kClMax];
+    int32_t cc_done, n_cut, pad2[2];
+    // the cluster recursion's moments, as logarithms (Eqs. update0-update9,
+    // new0-new6): Zbar_p, (Z_p^2)bar, (Z X_p)bar, (Z_p X_p)bar, (X_p^2)bar,
+    // (X_p X_q)bar
+    double lzp[kClMax], lz2p[kClMax], lzx[kClMax], lzpx[kClMax], lx2[kClMax];
+    double lxx[kClMax * kClMax];
 };
 
 // Mutable per-run state on the device.

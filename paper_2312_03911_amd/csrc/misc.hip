@@ -151,6 +151,15 @@ __global__ void prepare_kernel(void *arena, const RunDev *__restrict__ runs, con
             tab->n_clusters = 1;
             tab->n_splits = 0;
             tab->stopping = 0;
+            tab->cc_done = 0;
+            tab->n_cut = 0;
+            // Eqs. (ini0)-(ini11): one cluster, Xbar = 1, (X^2)bar = 1, no evidence
+            for (int p = 0; p < kClMax; ++p) {
+                tab->need[p] = 0;
+                tab->lzp[p] = tab->lz2p[p] = tab->lzx[p] = tab->lzpx[p] = -INFINITY;
+                tab->lx2[p] = (p == 0) ? 0.0 : -INFINITY;
+            }
+            for (int i = 0; i < kClMax * kClMax; ++i) tab->lxx[i] = -INFINITY;
         }
     }
     if (init_state && R.cluster_mode) {

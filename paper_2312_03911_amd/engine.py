@@ -340,9 +340,20 @@ class Engine:
         raw = self.arena[lay.cluster_table:lay.cluster_table + 1816].cpu().numpy()
         f64, i32 = raw[:1024].view(np.float64), raw[1024:1816].view(np.int32)
         nc = int(i32[194])
+        ext = self.arena[lay.cluster_table + 1816:lay.cluster_table + 2088].cpu().numpy().view(np.int32)
         return {"log_xbar": f64[:64].copy(), "cdf": f64[64:128].copy(), "n_live": i32[:64].copy(),
                 "surv_off": i32[64:129].copy(), "member_off": i32[129:194].copy(),
-                "n_clusters": nc, "n_splits": int(i32[195]), "stopping": int(i32[196])}
+                "n_clusters": nc, "n_splits": int(i32[195]), "stopping": int(i32[196]),
+                "n_cut": int(ext[65])}
+
+    def knn(self, r):
+        """The run's neighbour lists (cluster mode): slots [n_live, 32] and
+        squared distances."""
+        c, lay = self.cfgs[r], self.layouts[r]
+        if lay.knn < 0:
+            raise ValueError("run is not in cluster mode")
+        return (self._view(lay.knn, c.n_live * 32 * 4, self.torch.int32, (c.n_live, 32)),
+                self._view(lay.knn_dist, c.n_live * 32 * 8, self.torch.float64, (c.n_live, 32)))
 
     def set_trace(self, r: int, steps: int):
         """Record the first `steps` steps of every walker of run r."""

@@ -63,7 +63,7 @@ class RunConfig:
     name: str = ""
     noise: str = "walker"         # eps of p *= 1 + delta_p eps: one per walker ("walker"), per coordinate ("component"), isotropic (oracle only)
     cluster: int = 0              # 1: cluster recognition and volume-proportional spawning
-    cluster_kmax: int = 8         # largest neighbour count the cluster finding tries
+    cluster_kmax: int = 32        # largest neighbour count the cluster finding tries (0: every k, oracle only)
     stop: str = ""                # walk ends at the batch minimum of reflections ("batch") or each walker's own ("walker"); "" = batch with max_ref > 0
     save: str = ""                # points saved once the batch minimum ("batch") or the walker's own count ("walker") reaches min_ref; "" = batch with max_ref > 0
     draw: str = "walker"          # new point: one pick per walker ("walker") or pooled draws from all saved points ("pooled", oracle only)

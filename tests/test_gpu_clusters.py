@@ -127,3 +127,81 @@ def test_cluster_mode_runs_batched_with_plain_runs(torch):
     np.testing.assert_array_equal(_np(both.live_x(1)), _np(alone.live_x(0)))
     np.testing.assert_array_equal(_np(both.labels(1)), _np(alone.labels(0)))
     assert both.stats()[1] == alone.stats()[0]
+
+
+def _exact_knn(X, K):
+    """FP64 neighbour lists of one cluster holding every point, in (squared
+    distance, slot) order (distances as sums of squared differences), and the
+    relative gap between consecutive ranks."""
+    n = len(X)
+    order = np.empty((n, K + 1), np.int64)
+    dd = np.empty((n, K + 1))
+    for a in range(0, n, 256):
+        D = ((X[a:a + 256, None, :] - X[None, :, :]) ** 2).sum(-1)
+        D[np.arange(D.shape[0]), np.arange(a, a + D.shape[0])] = np.inf
+        part = np.argpartition(D, K + 1, axis=1)[:, :K + 2]
+        for i in range(D.shape[0]):
+            c = part[i]
+            o = c[np.lexsort((c, D[i, c]))][:K + 1]
+            order[a + i], dd[a + i] = o, D[i, o]
+    gap = np.abs(np.diff(dd, axis=1)) / np.maximum(dd[:, 1:], 1e-300)
+    return order[:, :K], dd[:, :K], gap
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_knn_lists_match_fp64_distances(torch, orc, precision):
+    """The first pass of neighbours at the d = 64, 4000-point size (one cluster
+    holding the prior draws): the GPU's lists equal exact FP64 neighbour
+    lists at every rank whose order is decided by a margin larger than the
+    run precision's distance error (relative gap to the next rank 1e-10 in
+    FP64, 1e-5 in FP32); the masked share stays small."""
+    cfg = inputs.config_gmm(precision=precision, cluster=1, seed=9310)
+    eng = _engine([cfg])
+    eng.evidence_update()
+    torch.cuda.synchronize()
+    X = _np(eng.live_x(0)).astype(np.float64)
+    slots, dist = eng.knn(0)
+    g = _np(slots)[:, :8]
+    ref, refd, gap = _exact_knn(X, 8)
+    tau = 1e-10 if precision == "fp64" else 1e-5
+    # a rank is decided when its distance is apart from both neighbours' ranks
+    near = np.zeros_like(ref, bool)
+    near[:, :8] |= gap[:, :8] < tau
+    near[:, 1:] |= gap[:, :7] < tau
+    ok = ~near
+    assert ok.mean() > 0.98, ok.mean()
+    np.testing.assert_array_equal(g[ok], ref[ok])
+    np.testing.assert_allclose(_np(dist)[:, :8][ok], refd[ok], rtol=1e-12 if precision == "fp64" else 2e-5)
+    eng.close()
+
+
+def test_cluster_step_with_deep_neighbour_loop_matches_oracle(torch, orc):
+    """The d = 64, 4000-point mixture (config 4) in cluster mode, FP64: two
+    iterations on both sides from the same seed, then the third iteration's
+    cluster finding, whose loop runs to k = 13 (the second pass of eight
+    neighbours): clusters, labels, volumes and the kill that follows match
+    the oracle exactly."""
+    cfg = inputs.config_gmm(precision="fp64", cluster=1, seed=9300)
+    eng = _engine([cfg])
+    o = orc.Oracle(cfg).init()
+    for _ in range(2):
+        eng.iterate(1)
+        o.iterate()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_np(eng.labels(0)), o.label)
+    np.testing.assert_allclose(_np(eng.live_x(0)), o.live_x, rtol=0, atol=1e-9)
+    before = o.st.kstop_max
+    eng.evidence_update()
+    o.evidence_update()
+    torch.cuda.synchronize()
+    assert o.st.kstop_max > 8 >= before
+    tab = eng.clusters(0)
+    nc = o.st.n_clusters
+    assert tab["n_clusters"] == nc and tab["n_splits"] == o.st.n_splits and tab["n_cut"] == 0
+    np.testing.assert_array_equal(_np(eng.labels(0)), o.label)
+    np.testing.assert_array_equal(tab["n_live"][:nc], o.cn[:nc])
+    np.testing.assert_allclose(tab["log_xbar"][:nc], o.clx[:nc], rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
+    st = eng.stats()[0]
+    assert abs(st["log_z"] - o.st.lz) < 1e-12 * max(1.0, abs(o.st.lz))
+    eng.close()
