@@ -140,8 +140,8 @@ typedef struct {
                                 (default reading), 0 = one normal per coordinate */
     int32_t cluster_mode;    /* 1: cluster recognition and spawning in proportion to the clusters'
                                 prior volumes (Section 3, mode collapse mitigation; Algorithm GGNS
-                                with its cluster-finding algorithm; Eqs. update0, update2, new0);
-                                0: one cluster.  sigma_mom is not computed in cluster mode. */
+                                with its cluster-finding algorithm; Eqs. update0-update9 and
+                                new0-new6 for the volumes and moments); 0: one cluster. */
     int32_t cluster_kmax;    /* largest neighbour count the cluster finding tries, 2..32 (the
                                 neighbours are found in passes of eight, a pass only for the
                                 clusters whose loop has not stopped; a cluster still going at
@@ -191,13 +191,16 @@ typedef struct {
 typedef struct {
     double log_z;            /* log Zbar (batched kills, Xbar convention) */
     double log_x;            /* log Xbar */
-    double log_z2;           /* log of the second moment of Z (Eqs. update3, update5, update8) */
+    double log_z2;           /* log of the second moment of Z (Eqs. update3, update5, update8):
+                                after ggns_finalize with one cluster; in cluster mode (the
+                                cluster recursion, Eqs. update3-update9, new0-new6) kept
+                                after every kill */
     double dt;               /* current step (prior units) */
     double lstar;            /* current threshold log L* */
     double log_xl_max;       /* running max of log(X * L_max) (X*L peak criterion) */
     double h;                /* information H = sum p_i log(L_i / Z), after ggns_finalize */
     double sigma_kl;         /* sqrt(H / n_live) (Eq. logZ_error) */
-    double sigma_mom;        /* sqrt(log Z2bar - 2 log Zbar); 0 in cluster mode */
+    double sigma_mom;        /* sqrt(log Z2bar - 2 log Zbar), after ggns_finalize */
     int64_t iter;            /* iterations done */
     int64_t evals;           /* likelihood+gradient evaluations (n_live + walker steps) */
     int64_t n_dead;          /* dead records written */

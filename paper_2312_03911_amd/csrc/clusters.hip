@@ -328,6 +328,7 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs, int pass) {
     __shared__ unsigned long long rkey[kMaxLive];
     __shared__ int rslot[kMaxLive];
     __shared__ int fpos[kClMax];
+    __shared__ double lxr[kClMax];
     const int n = R.n_live, t = threadIdx.x, T = blockDim.x;
     int32_t *label_g = at<int32_t>(arena, R.off_label);
     for (int i = t; i < n; i += T) label[i] = label_g[i];
@@ -452,16 +453,48 @@ cluster_cc_kernel(void *arena, const RunDev *__restrict__ runs, int pass) {
         atomicAdd(&ccount[q], 1);
     }
     __syncthreads();
+    // volumes and moments of the new clusters (Eqs. new0-new6), split by split
+    // in ascending order of the split cluster, each from the values before it:
+    // the clusters that exist before a split (those of earlier splits
+    // included) take the cross moments of (new3) with Y = X_r, the new
+    // clusters among themselves those of (new2)
     if (t == 0) {
+        int nb = nc0;
         for (int p = 0; p < nc0; ++p) {
             if (newid_base[p] < 0) continue;
-            const double lxp = tab->clx[p], lm = log((double)(tab->moff[p + 1] - tab->moff[p]));
+            const int m = tab->moff[p + 1] - tab->moff[p];
+            const double lxp = tab->clx[p], lm = log((double)m), lmm = log((double)m * (m + 1.0));
+            const double lx2 = tab->lx2[p], lzx = tab->lzx[p], lzp = tab->lzp[p];
+            const double lzpx = tab->lzpx[p], lz2p = tab->lz2p[p];
+            for (int r = 0; r < nb; ++r) lxr[r] = tab->lxx[p * kClMax + r];
             const int c = nroot[p];
             for (int r = 0; r < c; ++r) {
                 const int q = (r == 0) ? p : newid_base[p] + r - 1;
-                tab->clx[q] = lxp + log((double)ccount[q]) - lm;
+                const double ln = log((double)ccount[q]);
+                const double lnn = log((double)ccount[q] * (ccount[q] + 1.0));
+                tab->clx[q] = lxp + ln - lm;              // new0
                 tab->cn[q] = ccount[q];
+                tab->lx2[q] = lx2 + lnn - lmm;            // new1
+                tab->lzx[q] = lzx + ln - lm;              // new3, Y = Z
+                tab->lzp[q] = lzp + ln - lm;              // new4
+                tab->lzpx[q] = lzpx + lnn - lmm;          // new5
+                tab->lz2p[q] = lz2p + lnn - lmm;          // new6
+                for (int o = 0; o < nb; ++o) {            // new3, Y = X_o
+                    if (o == p) continue;
+                    const double v = lxr[o] + ln - lm;
+                    tab->lxx[q * kClMax + o] = v;
+                    tab->lxx[o * kClMax + q] = v;
+                }
             }
+            for (int a = 0; a < c; ++a)                   // new2
+                for (int b = 0; b < c; ++b) {
+                    if (a == b) continue;
+                    const int qa = (a == 0) ? p : newid_base[p] + a - 1;
+                    const int qb = (b == 0) ? p : newid_base[p] + b - 1;
+                    tab->lxx[qa * kClMax + qb] =
+                        lx2 + log((double)ccount[qa] * (double)ccount[qb]) - lmm;
+                }
+            nb += c - 1;
         }
     }
 }

@@ -209,6 +209,176 @@ __device__ __forceinline__ int count_below(const unsigned long long *lk, const i
     return pos;
 }
 
+// Cluster mode: the moments of the cluster recursion (Eqs. update1, update3-
+// update9) over one batch of kills, in kill order (ascending log L, then
+// slot).  Within a batch the per-kill factors telescope: the r-th kill of
+// cluster q, which held n0 points at the batch start, sees
+//   Xbar_q = Xbar_q0 (n0+1-r)/(n0+1),
+//   (X_q^2)bar = (X_q^2)bar_0 (n0+1-r)(n0+2-r)/((n0+1)(n0+2)),
+//   (X_a X_q)bar = (X_a X_q)bar_0 f_a f_q,   f = (n0+1-r)/(n0+1) per cluster.
+// With G_q = (Z X_q)bar / f_q and H_q = (Z_q X_q)bar / f_q every update
+// becomes a sum over earlier kills with coefficients fixed at the batch start:
+// a kill of log L l in cluster a adds to G_q
+//   (a == q) (X_q^2)bar_0 L / (n0_q+2),   (a != q) (X_a X_q)bar_0 L / (n0_a+1),
+// and to H_a the first of these; the kill itself adds to Z2bar
+//   2 L G_a / (n0_a+1) + 2 (X_a^2)bar_0 L^2 / ((n0_a+1)(n0_a+2))
+// (G_a before it), to (Z_a^2)bar the same with H_a, and to Zbar_a
+// Xbar_a0 L / (n0_a+1).  The sums run in linear space, scaled per cluster
+// (kill values by the cluster's largest log L, G and H by their largest
+// term), as an exclusive scan over chunks of the kill list for every target
+// cluster at once: thread t takes target q = t mod Q and chunk t / Q.  Called
+// by every thread of the block, before the volumes are updated.
+__device__ void cluster_moments(ClusterTab *tab, const int32_t *label, const unsigned long long *key,
+                                const int *slot, int nkill, const int *kcount, Acc *acc) {
+    __shared__ double ev[kMaxLive];               // exp(log L_j - lam[cluster of j])
+    __shared__ unsigned char kc[kMaxLive];        // cluster of kill j
+    __shared__ double kap[kClMax * kClMax];       // [a][q] G coefficient, scaled
+    __shared__ double bg[kEvThreads], bh[kEvThreads];   // per (chunk, target) partials
+    double *b3 = ev, *b4 = ev + kEvThreads;       // ev is free once the chunks are walked
+    __shared__ double lam[kClMax], mq[kClMax], nq[kClMax], g0[kClMax], h0[kClMax], rho[kClMax];
+    __shared__ double gfin[kClMax], hfin[kClMax], lf[kClMax], zq[kClMax];
+    __shared__ int lastj[kClMax];
+    const int t = threadIdx.x, T = blockDim.x;
+    const int nc = tab->n_clusters;
+    for (int q = t; q < kClMax; q += T) lastj[q] = -1;
+    __syncthreads();
+    for (int j = t; j < nkill; j += T) {
+        const int a = label[slot[j]];
+        kc[j] = (unsigned char)a;
+        atomicMax(&lastj[a], j);
+    }
+    __syncthreads();
+    // per cluster: its largest killed log L, log f after the batch, and the
+    // scales of G and H
+    for (int q = t; q < nc; q += T) {
+        lam[q] = (lastj[q] >= 0) ? key_value(key[lastj[q]]) : -INFINITY;
+        const int n0 = tab->cn[q], kq = kcount[q];
+        lf[q] = (kq > 0) ? log((double)(n0 + 1 - kq)) - log((double)n0 + 1.0) : 0.0;
+    }
+    __syncthreads();
+    for (int q = t; q < nc; q += T) {
+        const int n0 = tab->cn[q];
+        double m = tab->lzx[q];
+        for (int a = 0; a < nc; ++a) {
+            if (lastj[a] < 0) continue;
+            const double lc = (a == q) ? tab->lx2[q] - log((double)n0 + 2.0)
+                                       : tab->lxx[a * kClMax + q] - log((double)tab->cn[a] + 1.0);
+            const double v = lc + lam[a];
+            m = v > m ? v : m;
+        }
+        mq[q] = m;
+        g0[q] = (m == -INFINITY || tab->lzx[q] == -INFINITY) ? 0.0 : exp(tab->lzx[q] - m);
+        double nh = tab->lzpx[q];
+        const double hv = (lastj[q] >= 0) ? tab->lx2[q] - log((double)n0 + 2.0) + lam[q] : -INFINITY;
+        nh = hv > nh ? hv : nh;
+        nq[q] = nh;
+        h0[q] = (nh == -INFINITY || tab->lzpx[q] == -INFINITY) ? 0.0 : exp(tab->lzpx[q] - nh);
+        rho[q] = (nh == -INFINITY || hv == -INFINITY) ? 0.0 : exp(hv - nh);
+    }
+    __syncthreads();
+    for (int e = t; e < nc * nc; e += T) {
+        const int a = e / nc, q = e % nc;
+        double v = 0.0;
+        if (lastj[a] >= 0 && mq[q] != -INFINITY) {
+            const double lc = (a == q) ? tab->lx2[q] - log((double)tab->cn[q] + 2.0)
+                                       : tab->lxx[a * kClMax + q] - log((double)tab->cn[a] + 1.0);
+            if (lc != -INFINITY) v = exp(lc + lam[a] - mq[q]);
+        }
+        kap[a * kClMax + q] = v;
+    }
+    for (int j = t; j < nkill; j += T) ev[j] = exp(key_value(key[j]) - lam[kc[j]]);
+    __syncthreads();
+    // targets Q (a power of two >= nc) by chunks C
+    int Q = 1;
+    while (Q < nc) Q <<= 1;
+    const int C = T / Q, q = t & (Q - 1), c = t / Q;
+    const int csz = (nkill + C - 1) / C, j0 = c * csz, j1 = (j0 + csz < nkill) ? j0 + csz : nkill;
+    const bool on = q < nc;
+    double sg = 0.0, sh = 0.0;
+    if (on)
+        for (int j = j0; j < j1; ++j) {
+            const int a = kc[j];
+            sg += kap[a * kClMax + q] * ev[j];
+            if (a == q) sh += rho[q] * ev[j];
+        }
+    // exclusive scan over the chunks of each target (Hillis-Steele on the
+    // partials shifted by one chunk)
+    if (c + 1 < C) { bg[(c + 1) * Q + q] = sg; bh[(c + 1) * Q + q] = sh; }
+    if (c == 0) { bg[q] = 0.0; bh[q] = 0.0; }
+    __syncthreads();
+    for (int off = 1; off < C; off <<= 1) {
+        const double vg = (c >= off) ? bg[(c - off) * Q + q] : 0.0;
+        const double vh = (c >= off) ? bh[(c - off) * Q + q] : 0.0;
+        __syncthreads();
+        bg[c * Q + q] += vg;
+        bh[c * Q + q] += vh;
+        __syncthreads();
+    }
+    double g = on ? g0[q] + bg[c * Q + q] : 0.0, h = on ? h0[q] + bh[c * Q + q] : 0.0;
+    double cross = 0.0, own = 0.0, sq = 0.0, zp = 0.0;
+    if (on)
+        for (int j = j0; j < j1; ++j) {
+            const int a = kc[j];
+            const double e = ev[j];
+            if (a == q) {
+                cross += e * g;
+                own += e * h;
+                sq += e * e;
+                zp += e;
+                h += rho[q] * e;
+            }
+            g += kap[a * kClMax + q] * e;
+        }
+    if (on && c == C - 1) { gfin[q] = g; hfin[q] = h; }
+    __syncthreads();
+    // sums over the chunks of each target
+    bg[c * Q + q] = cross;
+    bh[c * Q + q] = own;
+    b3[c * Q + q] = sq;
+    b4[c * Q + q] = zp;
+    __syncthreads();
+    for (int s = C >> 1; s > 0; s >>= 1) {
+        if (c < s) {
+            bg[c * Q + q] += bg[(c + s) * Q + q];
+            bh[c * Q + q] += bh[(c + s) * Q + q];
+            b3[c * Q + q] += b3[(c + s) * Q + q];
+            b4[c * Q + q] += b4[(c + s) * Q + q];
+        }
+        __syncthreads();
+    }
+    const double l2 = 0.69314718055994530942;
+    if (t < nc) {
+        const int p = t, n0 = tab->cn[p], kp = kcount[p];
+        const double ln1 = log((double)n0 + 1.0), ln2 = log((double)n0 + 2.0);
+        double z2 = -INFINITY;
+        if (kp > 0) {
+            const double lcr = (bg[p] > 0.0) ? l2 + lam[p] + mq[p] - ln1 + log(bg[p]) : -INFINITY;
+            const double lsq = l2 + tab->lx2[p] - ln1 - ln2 + 2.0 * lam[p] + log(b3[p]);
+            const double lown = (bh[p] > 0.0) ? l2 + nq[p] + lam[p] - ln1 + log(bh[p]) : -INFINITY;
+            z2 = lae(lcr, lsq);
+            tab->lz2p[p] = lae(tab->lz2p[p], lae(lown, lsq));                           // update4
+            tab->lzp[p] = lae(tab->lzp[p], tab->clx[p] - ln1 + lam[p] + log(b4[p]));     // update1
+            tab->lzpx[p] = (hfin[p] > 0.0) ? lf[p] + nq[p] + log(hfin[p]) : -INFINITY;  // update7
+            tab->lx2[p] += log((double)(n0 + 1 - kp) * (double)(n0 + 2 - kp)) - ln1 - ln2;  // update8
+        }
+        // update5, update6 (every cluster, killed from or not)
+        tab->lzx[p] = (gfin[p] > 0.0) ? lf[p] + mq[p] + log(gfin[p]) : -INFINITY;
+        zq[p] = z2;
+    }
+    __syncthreads();
+    // update9 on every pair, then the run's Z2bar (update3)
+    for (int e = t; e < nc * nc; e += T) {
+        const int a = e / nc, b = e % nc;
+        if (a != b) tab->lxx[a * kClMax + b] += lf[a] + lf[b];
+    }
+    if (t == 0) {
+        double s = acc->log_z2;
+        for (int p = 0; p < nc; ++p) s = lae(s, zq[p]);
+        acc->log_z2 = s;
+    }
+    __syncthreads();
+}
+
 template <int E>
 __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_sweep,
                               unsigned long long *key, int *slot, unsigned char *dead_flag,
@@ -384,6 +554,7 @@ __device__ void evidence_body(void *arena, const RunDev &R, Acc *acc, int final_
     }
     if (clm) {
         __syncthreads();   // kcount complete
+        cluster_moments(tab, label, key, slot, nkill, kcount, acc);
         if (t == 0) {
             // volumes after the batch: Xbar_p (n_p - k_p + 1) / (n_p + 1); a
             // cluster left without points is removed; Xbar = sum over clusters
@@ -733,9 +904,10 @@ fin_total_kernel(void *arena, const RunDev *__restrict__ runs) {
     const double lz2 = block_lse(m2, s2, scratch);
     const double lzr = block_lse(mr, sr, scratch);
     if (threadIdx.x == 0) {
-        acc->log_z2 = R.cluster_mode ? -INFINITY : lz2;
-        const double v = lz2 - 2.0 * lzr;
-        acc->sigma_mom = R.cluster_mode ? 0.0 : sqrt(v > 0.0 ? v : 0.0);
+        // cluster mode keeps Z2bar from the cluster recursion, run per batch
+        if (!R.cluster_mode) acc->log_z2 = lz2;
+        const double v = R.cluster_mode ? acc->log_z2 - 2.0 * acc->log_z : lz2 - 2.0 * lzr;
+        acc->sigma_mom = sqrt(v > 0.0 ? v : 0.0);
         acc->summary_pending = 0;
     }
 }

@@ -341,10 +341,15 @@ class Engine:
         f64, i32 = raw[:1024].view(np.float64), raw[1024:1816].view(np.int32)
         nc = int(i32[194])
         ext = self.arena[lay.cluster_table + 1816:lay.cluster_table + 2088].cpu().numpy().view(np.int32)
+        mom = self.arena[lay.cluster_table + 2088:lay.cluster_table + 37416].cpu().numpy().view(np.float64)
         return {"log_xbar": f64[:64].copy(), "cdf": f64[64:128].copy(), "n_live": i32[:64].copy(),
                 "surv_off": i32[64:129].copy(), "member_off": i32[129:194].copy(),
                 "n_clusters": nc, "n_splits": int(i32[195]), "stopping": int(i32[196]),
-                "n_cut": int(ext[65])}
+                "n_cut": int(ext[65]),
+                # moments of the cluster recursion, as logarithms
+                "log_zp": mom[0:64].copy(), "log_z2p": mom[64:128].copy(),
+                "log_zx": mom[128:192].copy(), "log_zpx": mom[192:256].copy(),
+                "log_x2": mom[256:320].copy(), "log_xx": mom[320:].reshape(64, 64).copy()}
 
     def knn(self, r):
         """The run's neighbour lists (cluster mode): slots [n_live, 32] and

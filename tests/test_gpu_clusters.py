@@ -39,6 +39,21 @@ def _blobs(centres, per, d, scale, seed):
     return np.concatenate([c + scale * rng.standard_normal((per, d)) for c in centres])
 
 
+def _moments_match(tab, o, nc, atol):
+    """The cluster recursion's moments (logs of Zbar_p, (Z_p^2)bar, (Z X_p)bar,
+    (Z_p X_p)bar, (X_p^2)bar and the cross (X_p X_q)bar) of the first nc
+    clusters equal the oracle's: the same -inf pattern, finite values within
+    atol."""
+    cm = o.cm
+    for name, off in (("log_zp", 0), ("log_z2p", 64), ("log_zx", 128), ("log_zpx", 192), ("log_x2", 256)):
+        np.testing.assert_allclose(tab[name][:nc], cm[off:off + nc], rtol=0, atol=atol, err_msg=name)
+    xx = cm[320:].reshape(64, 64)[:nc, :nc].copy()
+    g = tab["log_xx"][:nc, :nc].copy()
+    np.fill_diagonal(xx, 0.0)
+    np.fill_diagonal(g, 0.0)
+    np.testing.assert_allclose(g, xx, rtol=0, atol=atol, err_msg="log_xx")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_cluster_step_matches_oracle(torch, orc, precision):
     d, per = 5, 100
@@ -70,6 +85,10 @@ def test_cluster_step_matches_oracle(torch, orc, precision):
     st = eng.stats()[0]
     assert abs(st["log_z"] - o.st.lz) < 1e-12 and abs(st["log_x"] - o.st.lx) < 1e-12
     assert st["n_clusters"] == 4
+    # the split into four (Eqs. new0-new6) and the kill that follows
+    # (Eqs. update1-update9): every moment, and the run's Z2bar
+    _moments_match(tab, o, nc, 1e-12)
+    assert abs(st["log_z2"] - o.st.lz2) < 1e-12
     # spawning: the same clusters and starts for every walker
     eng.hss_walk()
     o.hss_walk()
@@ -109,6 +128,10 @@ def test_cluster_mode_fp64_full_run_matches_oracle(torch, orc, seed):
     assert st["iter"] == o.st.iter and st["n_clusters"] == o.st.n_clusters >= 2
     assert abs(st["log_z"] - o.st.lz) < 1e-9
     assert abs(st["sigma_kl"] - o.st.sigma_kl) < 1e-9
+    # the cluster recursion's second moment and the error it gives
+    assert abs(st["log_z2"] - o.st.lz2) < 1e-9
+    assert o.st.sigma_mom > 0 and abs(st["sigma_mom"] - o.st.sigma_mom) < 1e-9
+    _moments_match(eng.clusters(0), o, o.st.n_clusters, 1e-9)
 
 
 def test_cluster_mode_runs_batched_with_plain_runs(torch):
@@ -204,4 +227,7 @@ def test_cluster_step_with_deep_neighbour_loop_matches_oracle(torch, orc):
     np.testing.assert_array_equal(_np(eng.killed(0)), o.killed)
     st = eng.stats()[0]
     assert abs(st["log_z"] - o.st.lz) < 1e-12 * max(1.0, abs(o.st.lz))
+    # moments after three kills of 2000 points and the splits between them
+    assert abs(st["log_z2"] - o.st.lz2) < 1e-10 * max(1.0, abs(o.st.lz2))
+    _moments_match(tab, o, nc, 1e-9)
     eng.close()
