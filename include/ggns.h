@@ -136,8 +136,10 @@ typedef struct {
                                 224: 8 only); default
                                 d_pad / 32.  Other values: GGNS_EUNSUPPORTED. */
     int32_t noise_mode;      /* the eps of p <- p (1 + delta_p eps) (Algorithm GGNS HSS):
-                                1 = one normal per walker and step, the first of its stream
-                                (default reading), 0 = one normal per coordinate */
+                                1 = one normal per walker and step (default reading): two
+                                words of the walker's first block stream per step, the first
+                                normal of their Box-Muller pair; 0 = one normal per
+                                coordinate, four words of each block stream per step */
     int32_t cluster_mode;    /* 1: cluster recognition and spawning in proportion to the clusters'
                                 prior volumes (Section 3, mode collapse mitigation; Algorithm GGNS
                                 with its cluster-finding algorithm; Eqs. update0-update9 and
@@ -385,7 +387,9 @@ int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,
  * generator.  Walker m's coordinate block b at iteration `iteration` seeds
  * xoshiro128++ from Philox4x32-10(key seed; counter b, m, iteration,
  * EPS << 24) and draws four words per step, turned into four normals by
- * Box-Muller on 24-bit uniforms in FP32, as in the walk.  With
+ * Box-Muller on 24-bit uniforms in FP32, as the walk does with per-component
+ * noise (noise_mode 0; with one normal per walker the walk takes two words of
+ * block 0 per step and the first normal of their pair).  With
  * i = ((t * n_walkers + m) * n_blocks + b) * 4 + j for step t < steps, j < 4:
  *   normals_dev[i] (float) and words_dev[i] (uint32), each nullable;
  *   checksum_dev[m * n_blocks + b] = sum of the thread's normals (nullable).

@@ -41,8 +41,9 @@
  *   R6  leaving the prior box counts as outside and takes precedence; the
  *       momentum component of every violated axis is negated.
  *   R7  the noise eps of p *= (1 + delta_p eps): one normal per walker and
- *       step (the first normal of that walker's step stream) scaling all
- *       components alike (noise_mode 1, the default); per component
+ *       step scaling all components alike (noise_mode 1, the default; two
+ *       words of the walker's first block stream per step, the first normal
+ *       of their Box-Muller pair); per component
  *       (noise_mode 0); or, as an option that is not the paper's formula, an
  *       isotropic vector p += delta_p (|p| / sqrt d) eps (noise_mode 2).
  *       Applied to every walker at every step, after any reflection.
@@ -1039,11 +1040,18 @@ static uint32_t walker_step(const orc_desc *D, const double *prm, orc_state *S, 
             }
         }
     }
-    int nb = (d + 3) / 4;
-    for (int b = 0; b < nb; ++b) {
-        uint32_t w[4];
-        for (int j = 0; j < 4; ++j) w[j] = orc_xoshiro_next(W->xs + 4 * b);
-        orc_box_muller4(w, W->eps + 4 * b);
+    if (D->noise_mode == 1) {
+        /* one normal per walker and step: two words of the walker's first
+         * block stream, the first normal of their Box-Muller pair */
+        uint32_t w0 = orc_xoshiro_next(W->xs), w1 = orc_xoshiro_next(W->xs);
+        W->eps[0] = sqrt(-2.0 * log(u24_open(w0))) * cos(2.0 * M_PI * u24_half(w1));
+    } else {
+        int nb = (d + 3) / 4;
+        for (int b = 0; b < nb; ++b) {
+            uint32_t w[4];
+            for (int j = 0; j < 4; ++j) w[j] = orc_xoshiro_next(W->xs + 4 * b);
+            orc_box_muller4(w, W->eps + 4 * b);
+        }
     }
     if (D->noise_mode == 2) {
         /* isotropic: p += delta_p (|p| / sqrt d) eps, eps ~ N(0, I_d) */

@@ -10,8 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libggns.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "walk_valu.hip", "walk_mfma.hip", "walk_plain.hip", "clusters.hip", "evidence.hip", "misc.hip",
-           "probe.hip"]
+SOURCES = ["walk_valu_f1.hip", "walk_valu_f2.hip", "walk_valu_f4.hip", "walk_valu_f8.hip", "walk_valu_d.hip",
+           "walk_mfma.hip", "api.hip", "walk_valu.hip", "walk_plain.hip", "clusters.hip", "evidence.hip",
+           "misc.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,7 +31,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 5)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1, 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs

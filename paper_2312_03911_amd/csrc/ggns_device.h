@@ -87,6 +87,20 @@ __device__ __forceinline__ void normals2(uint32_t a, uint32_t b, double &z0, dou
     z1 = r * s;
 }
 
+// The first normal of the Box-Muller pair of (a, b), r cos(2 pi u2): the one
+// noise normal per walker and step (the third argument only picks the type).
+__device__ __forceinline__ float normal_first(uint32_t a, uint32_t b, float) {
+    const float u1 = ((float)(a >> 8) + 0.5f) * 0x1p-24f;
+    const float u2 = (float)(b >> 8) * 0x1p-24f;
+    return __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1)) *
+           __builtin_amdgcn_cosf(u2);
+}
+__device__ __forceinline__ double normal_first(uint32_t a, uint32_t b, double) {
+    const double u1 = ((double)(a >> 8) + 0.5) * 0x1p-24;
+    const double u2 = (double)(b >> 8) * 0x1p-24;
+    return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
 // Uniform in (0,1) from the top 24 bits (prior draws), in double.
 __device__ __forceinline__ double u24_open(uint32_t a) {
     return ((double)(a >> 8) + 0.5) * 0x1p-24;

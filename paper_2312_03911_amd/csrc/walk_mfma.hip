@@ -77,10 +77,10 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 
     __shared__ __align__(16) __bf16 rbuf[16 * RS];       // residuals of the 16 slots
     __shared__ __align__(16) floatx4 part[W * 16];       // per-wavefront partial sums
-    __shared__ float eps0s[16];                          // noise_mode 1: each slot's normal
     __shared__ unsigned long long blk_cnt[5];
 
     const int d = R.d;
+    const bool scalar_noise = R.noise_mode != 0;   // one noise normal per walker and step
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane & 15, quarter = lane >> 4;
     const int a0 = wave * (DP / W) + quarter * L;
@@ -162,9 +162,10 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
         out_l = live_logl[s];
         momentum_lane<L>(seed, (uint32_t)mm, it, 0u, a0, d, p);
+        // one normal per walker: every lane carries block 0's stream
 #pragma unroll
         for (int i = 0; i < L / 4; ++i) {
-            draw4(seed, (uint32_t)((a0 >> 2) + i), (uint32_t)mm, it, TAG_EPS, 0u, w);
+            draw4(seed, scalar_noise ? 0u : (uint32_t)((a0 >> 2) + i), (uint32_t)mm, it, TAG_EPS, 0u, w);
             eps[i].seed(w);
         }
         draw4(seed, 0u, (uint32_t)mm, it, TAG_RES, 0u, w);
@@ -324,15 +325,18 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             const bool vw = (__ballot(vany) & (0x0001000100010001ull << slot)) != 0ull;
             if (quarter == 0) part[wave * 16 + slot] = floatx4{qv, pg, gg, vw ? 1.0f : 0.0f};
         }
-        // this step's normals of the lane's first block; with one normal per walker
-        // the lane holding coordinate 0 publishes its first one
-        float zb0[4];
-        {
+        // this step's noise: with one normal per walker, two words of block 0's
+        // stream and the first normal of their pair (every lane alike), else
+        // the four normals of each block
+        float zb0[4], e0 = 0.0f;
+        if (scalar_noise) {
+            const uint32_t w0 = eps[0].next(), w1 = eps[0].next();
+            e0 = normal_first(w0, w1, 0.0f);
+        } else {
             const uint32_t w0 = eps[0].next(), w1 = eps[0].next(), w2 = eps[0].next(),
                            w3 = eps[0].next();
             normals2(w0, w1, zb0[0], zb0[1]);
             normals2(w2, w3, zb0[2], zb0[3]);
-            if (R.noise_mode && a0 == 0) eps0s[slot] = zb0[0];
         }
         __syncthreads();
         floatx4 tot = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -358,13 +362,13 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         const bool use_g = out && !viol && isfinite(gg) && gg > 0.0f;
         const bool flip_all = out && !viol && !use_g;
         const float f = use_g ? m_div(2.0f * pg, gg) : 0.0f;
-        const bool scalar_noise = R.noise_mode != 0;
-        const float e0 = scalar_noise ? eps0s[slot] : 0.0f;
 #pragma unroll
         for (int i = 0; i < L / 4; ++i) {
             // this step's noise for the block of four coordinates 4i..4i+3
             float z[4];
-            if (i == 0) {
+            if (scalar_noise) {
+                z[0] = z[1] = z[2] = z[3] = e0;
+            } else if (i == 0) {
                 z[0] = zb0[0]; z[1] = zb0[1]; z[2] = zb0[2]; z[3] = zb0[3];
             } else {
                 const uint32_t w0 = eps[i].next(), w1 = eps[i].next(), w2 = eps[i].next(),
@@ -372,7 +376,6 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                 normals2(w0, w1, z[0], z[1]);
                 normals2(w2, w3, z[2], z[3]);
             }
-            if (scalar_noise) z[0] = z[1] = z[2] = z[3] = e0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = 4 * i + j;

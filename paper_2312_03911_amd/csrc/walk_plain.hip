@@ -284,19 +284,29 @@ __global__ void plain_step_kernel(void *arena, const RunDev *__restrict__ runs, 
     const bool use_g = out && !viol && isfinite(gg) && gg > 0.0;
     const bool flip_all = out && !viol && !use_g;
     const double f = use_g ? 2.0 * pg / gg : 0.0;
-    double e0 = 0.0;   // noise_mode 1: the walker's first normal of the step
-    for (int b = 0; b < nb; ++b) {
-        uint32_t *st = S.eps + (int64_t)(4 * b) * k + m;
+    // noise_mode 1: one normal per walker, two words of block 0's stream and
+    // the first normal of their pair; noise_mode 0: four words per block
+    double e0 = 0.0;
+    if (R.noise_mode) {
+        uint32_t *st = S.eps + m;
         Xoshiro e{st[0], st[k], st[2 * k], st[3 * k]};
-        uint32_t w[4];
-        for (int j = 0; j < 4; ++j) w[j] = e.next();
+        const uint32_t w0 = e.next(), w1 = e.next();
         st[0] = e.s0; st[k] = e.s1; st[2 * k] = e.s2; st[3 * k] = e.s3;
+        e0 = normal_first(w0, w1, e0);
+    }
+    for (int b = 0; b < nb; ++b) {
         double z[4];
-        normals2(w[0], w[1], z[0], z[1]);
-        normals2(w[2], w[3], z[2], z[3]);
-        if (b == 0) e0 = z[0];
-        if (R.noise_mode)
+        if (R.noise_mode) {
             for (int j = 0; j < 4; ++j) z[j] = e0;
+        } else {
+            uint32_t *st = S.eps + (int64_t)(4 * b) * k + m;
+            Xoshiro e{st[0], st[k], st[2 * k], st[3 * k]};
+            uint32_t w[4];
+            for (int j = 0; j < 4; ++j) w[j] = e.next();
+            st[0] = e.s0; st[k] = e.s1; st[2 * k] = e.s2; st[3 * k] = e.s3;
+            normals2(w[0], w[1], z[0], z[1]);
+            normals2(w[2], w[3], z[2], z[3]);
+        }
         for (int j = 0; j < 4 && 4 * b + j < d; ++j) {
             const int64_t a = (4 * b + j) * k;
             const bool flip = flip_all || (out && (x[a] < R.lo || x[a] > R.hi));
