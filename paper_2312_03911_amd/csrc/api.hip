@@ -211,6 +211,7 @@ struct Class {
     int waves = 0;       // matrix-core classes: wavefronts per group of 16 walkers
     int gf = 0;          // vector FP32 walk: lanes per walker (4, 8 or 16) shared by the class, else 0
     bool any_batch = false;   // some run of the class walks the batch-minimum loop
+    int nz = 0;               // matrix-core classes: 1 = one noise normal per walker (noise_mode 1)
 };
 
 }  // namespace
@@ -309,13 +310,16 @@ void build_classes(ggns_ctx *c) {
     if (!mfma_runs.empty()) {
         // matrix-core walk: one class per (padded dimension, wavefronts per
         // group), 16 walkers per tile (one group of slots)
-        std::map<std::pair<int, int>, std::vector<int>> by_dp;
+        std::map<std::tuple<int, int, int>, std::vector<int>> by_dp;
         for (int r : mfma_runs)
-            by_dp[{(c->plan.runs[r].d + 31) / 32 * 32, c->plan.runs[r].mw}].push_back(r);
+            by_dp[std::make_tuple((c->plan.runs[r].d + 31) / 32 * 32, c->plan.runs[r].mw,
+                                  c->plan.runs[r].noise_mode != 0 ? 1 : 0)]
+                .push_back(r);
         for (auto &kv : by_dp) {
-            Class w{GGNS_FP32_BF16MMA, kv.first.first, GGNS_LIK_GAUSS_FULL, true,
+            Class w{GGNS_FP32_BF16MMA, std::get<0>(kv.first), GGNS_LIK_GAUSS_FULL, true,
                     (int64_t)c->tiles_host.size(), 0, 0};
-            w.waves = kv.first.second;
+            w.waves = std::get<1>(kv.first);
+            w.nz = std::get<2>(kv.first);
             for (int r : kv.second) {
                 add_tiles(r, c->plan.runs[r].n_kill, 16);
                 w.any_batch = w.any_batch || c->plan.runs[r].walk_mode == 1;
@@ -465,7 +469,7 @@ int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
     auto launch_phase = [&](const Class &w, int phase, hipStream_t st) {
         if (w.mfma)
             return launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                    w.n_tiles, w.C, w.waves, phase, st);
+                                    w.n_tiles, w.C, w.waves, w.nz, phase, st);
         return launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
                                  w.n_tiles, w.prec, w.C, w.kind, w.gf, w.lds, phase, st);
     };

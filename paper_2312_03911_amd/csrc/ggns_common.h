@@ -121,7 +121,7 @@ int launch_walk_class(void *arena, const RunDev *runs_dev, const Tile *tiles, in
                       int prec, int C, int kind, int gf, size_t lds_bytes, int phase, hipStream_t s);
 bool mfma_shape_ok(int d_pad, int waves);
 int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles,
-                     int d_pad, int waves, int phase, hipStream_t s);
+                     int d_pad, int waves, int nz, int phase, hipStream_t s);
 // bytes of one walker's saved state between the two walk launches
 int64_t walker_state_bytes(int d_pad, int elem_bytes);
 int launch_loglike(void *arena, const RunDev *run_dev, const RunDev &run_host, const void *x,

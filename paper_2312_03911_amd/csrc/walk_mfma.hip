@@ -60,11 +60,14 @@ __device__ __forceinline__ void momentum_lane(uint64_t seed, uint32_t m, uint32_
 }  // namespace
 
 // L dimensions per lane, W wavefronts per group of 16 walkers; dp = 4 L W.
-template <int L, int W>
+// NZ = 1: one noise normal per walker and step (one stream per lane, one noise
+// factor per walker); NZ = 0: one per dimension (a stream per block of four).
+template <int L, int W, int NZ>
 __global__ void __launch_bounds__(64 * W, 1)
 walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__restrict__ tiles,
                  int phase) {
     constexpr int DP = 4 * L * W, MBW = L / 4, KB = DP / 32, RS = DP + 8;
+    constexpr int NE = NZ ? 1 : L / 4;   // noise streams per lane
     const Tile tile = tiles[blockIdx.x];
     const RunDev &R = runs[tile.run];
     Acc *acc = at<Acc>(arena, R.off_acc);
@@ -80,7 +83,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     __shared__ unsigned long long blk_cnt[5];
 
     const int d = R.d;
-    const bool scalar_noise = R.noise_mode != 0;   // one noise normal per walker and step
+    constexpr bool scalar_noise = NZ != 0;   // one noise normal per walker and step
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane & 15, quarter = lane >> 4;
     const int a0 = wave * (DP / W) + quarter * L;
@@ -130,20 +133,17 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     unsigned char *wst = batch ? at<unsigned char>(arena, R.off_wstate) : nullptr;
 
     float x[L], p[L], y[L], xo[L];   // xo: the walker's reservoir point, written when it ends
-    Xoshiro eps[L / 4];
+    Xoshiro eps[NE];
     Xoshiro res;
     int m = tile.m_begin + slot;
     int next = tile.m_begin + 16;      // same in every lane: slots refill in slot order
     bool active = m < tile.m_end;
     int s = 0, nref = 0, streak = 0, steps = 0, outs = 0, nprune = 0, nsave = 0, a_step = never;
     double out_l = 0.0;
-    // the prior box per dimension; padding dimensions get an unbounded one
-    float blo[L], bhi[L];
-#pragma unroll
-    for (int c = 0; c < L; ++c) {
-        blo[c] = VALID(c) ? lo : -INFINITY;
-        bhi[c] = VALID(c) ? hi : INFINITY;
-    }
+    // padding dimensions sit at x = lo (inside the box, and without effect on
+    // log L or the score: their rows and columns of P and their mu are zero),
+    // so the box test needs no per-dimension bounds
+    const float xpad = lo;
 
     auto start_walker = [&](int mm) __attribute__((always_inline)) {
         uint32_t w[4];
@@ -157,14 +157,14 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         const float *xs = live_x + (int64_t)s * d;
 #pragma unroll
         for (int c = 0; c < L; ++c) {
-            x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
+            x[c] = VALID(c) ? xs[a0 + c] : xpad;
             xo[c] = x[c];
         }
         out_l = live_logl[s];
         momentum_lane<L>(seed, (uint32_t)mm, it, 0u, a0, d, p);
         // one normal per walker: every lane carries block 0's stream
 #pragma unroll
-        for (int i = 0; i < L / 4; ++i) {
+        for (int i = 0; i < NE; ++i) {
             draw4(seed, scalar_noise ? 0u : (uint32_t)((a0 >> 2) + i), (uint32_t)mm, it, TAG_EPS, 0u, w);
             eps[i].seed(w);
         }
@@ -187,7 +187,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             so[a0 + c] = xo[c];
         }
 #pragma unroll
-        for (int i = 0; i < L / 4; ++i) {
+        for (int i = 0; i < NE; ++i) {
             uint32_t *e = se + 4 * ((a0 >> 2) + i);
             e[0] = eps[i].s0; e[1] = eps[i].s1; e[2] = eps[i].s2; e[3] = eps[i].s3;
         }
@@ -218,7 +218,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
                     xo[c] = so[a0 + c];
                 }
 #pragma unroll
-                for (int i = 0; i < L / 4; ++i) {
+                for (int i = 0; i < NE; ++i) {
                     const uint32_t *e = se + 4 * ((a0 >> 2) + i);
                     eps[i].s0 = e[0]; eps[i].s1 = e[1]; eps[i].s2 = e[2]; eps[i].s3 = e[3];
                 }
@@ -286,7 +286,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             for (int c = 0; c < L; ++c) {
                 x[c] = x[c] + dt * p[c];
                 rb[c] = (__bf16)(x[c] - mu[c]);
-                vany = vany | (x[c] < blo[c]) | (x[c] > bhi[c]);
+                vany = vany | (x[c] < lo) | (x[c] > hi);
             }
             __bf16 *dst = rbuf + slot * RS + a0;
 #pragma unroll
@@ -295,20 +295,24 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
         __syncthreads();
         // Y^T = P R^T for this wavefront's rows; B operands: K rows 8q..8q+7 of each K-block
+        // (K-blocks outer: one B operand is live at a time; each M-block still
+        // accumulates its K-blocks in order)
         {
-            bf16x8 bop[KB];
+            floatx4 c4[MBW];
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-                bop[kb] = *reinterpret_cast<const bf16x8 *>(rbuf + slot * RS + 32 * kb + 8 * quarter);
+            for (int mb = 0; mb < MBW; ++mb) c4[mb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int mb = 0; mb < MBW; ++mb) {
-                floatx4 c4 = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int kb = 0; kb < KB; ++kb) {
+                const bf16x8 bop =
+                    *reinterpret_cast<const bf16x8 *>(rbuf + slot * RS + 32 * kb + 8 * quarter);
 #pragma unroll
-                for (int kb = 0; kb < KB; ++kb)
-                    c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amat[mb][kb], bop[kb], c4, 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) y[4 * mb + j] = c4[j];
+                for (int mb = 0; mb < MBW; ++mb)
+                    c4[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(amat[mb][kb], bop, c4[mb], 0, 0, 0);
             }
+#pragma unroll
+            for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) y[4 * mb + j] = c4[mb][j];
         }
         // r.y, p.g and g.g (g = -y) and the box test: lane sums, quarters, then wavefronts
         {
@@ -327,11 +331,12 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         }
         // this step's noise: with one normal per walker, two words of block 0's
         // stream and the first normal of their pair (every lane alike), else
-        // the four normals of each block
-        float zb0[4], e0 = 0.0f;
-        if (scalar_noise) {
+        // the four normals of each block (those of block 0 here, the others
+        // where they are used)
+        float zb0[4], nf0 = 1.0f;
+        if constexpr (NZ) {
             const uint32_t w0 = eps[0].next(), w1 = eps[0].next();
-            e0 = normal_first(w0, w1, 0.0f);
+            nf0 = 1.0f + dpn * normal_first(w0, w1, 0.0f);
         } else {
             const uint32_t w0 = eps[0].next(), w1 = eps[0].next(), w2 = eps[0].next(),
                            w3 = eps[0].next();
@@ -362,28 +367,36 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
         const bool use_g = out && !viol && isfinite(gg) && gg > 0.0f;
         const bool flip_all = out && !viol && !use_g;
         const float f = use_g ? m_div(2.0f * pg, gg) : 0.0f;
+        // box faces: a walker outside the box flips the momentum of each
+        // violated dimension (rare; f is 0 and flip_all false for it)
+        if (__builtin_expect(__any(vany), 0)) {
+#pragma unroll
+            for (int c = 0; c < L; ++c) p[c] = ((x[c] < lo) | (x[c] > hi)) ? -p[c] : p[c];
+        }
 #pragma unroll
         for (int i = 0; i < L / 4; ++i) {
-            // this step's noise for the block of four coordinates 4i..4i+3
-            float z[4];
-            if (scalar_noise) {
-                z[0] = z[1] = z[2] = z[3] = e0;
-            } else if (i == 0) {
-                z[0] = zb0[0]; z[1] = zb0[1]; z[2] = zb0[2]; z[3] = zb0[3];
+            // this step's noise factors for the block of four dimensions 4i..4i+3
+            float nf[4];
+            if constexpr (NZ) {
+                nf[0] = nf[1] = nf[2] = nf[3] = nf0;
             } else {
-                const uint32_t w0 = eps[i].next(), w1 = eps[i].next(), w2 = eps[i].next(),
-                               w3 = eps[i].next();
-                normals2(w0, w1, z[0], z[1]);
-                normals2(w2, w3, z[2], z[3]);
+                float z[4];
+                if (i == 0) {
+                    z[0] = zb0[0]; z[1] = zb0[1]; z[2] = zb0[2]; z[3] = zb0[3];
+                } else {
+                    const uint32_t w0 = eps[i].next(), w1 = eps[i].next(), w2 = eps[i].next(),
+                                   w3 = eps[i].next();
+                    normals2(w0, w1, z[0], z[1]);
+                    normals2(w2, w3, z[2], z[3]);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) nf[j] = 1.0f + dpn * z[j];
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int c = 4 * i + j;
-                // a dimension outside the box makes the step outside (viol)
-                const bool vm = (x[c] < blo[c]) | (x[c] > bhi[c]);
-                const bool flip = flip_all | vm;
-                const float pr = (flip ? -p[c] : p[c]) + f * y[c];   // p - f g with g = -y
-                p[c] = pr * (1.0f + dpn * z[j]);
+                const float pr = (flip_all ? -p[c] : p[c]) + f * y[c];   // p - f g with g = -y
+                p[c] = pr * nf[j];
             }
         }
         nref += out ? 1 : 0;
@@ -407,7 +420,7 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
             if (active & pruning) {
                 const float *xs = live_x + (int64_t)s * d;
 #pragma unroll
-                for (int c = 0; c < L; ++c) x[c] = VALID(c) ? xs[a0 + c] : 0.0f;
+                for (int c = 0; c < L; ++c) x[c] = VALID(c) ? xs[a0 + c] : xpad;
                 nprune += 1;
                 momentum_lane<L>(seed, (uint32_t)m, it, (uint32_t)nprune, a0, d, p);
                 // the batch minimum never decreases: its count is kept
@@ -436,9 +449,13 @@ walk_mfma_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
 
 template <int L, int W>
 static hipError_t launch_mfma_t(void *arena, const RunDev *runs, const Tile *tiles, int n_tiles,
-                                int phase, hipStream_t s) {
-    hipLaunchKernelGGL((walk_mfma_kernel<L, W>), dim3(n_tiles), dim3(64 * W), 0, s, arena, runs,
-                       tiles, phase);
+                                int nz, int phase, hipStream_t s) {
+    if (nz)
+        hipLaunchKernelGGL((walk_mfma_kernel<L, W, 1>), dim3(n_tiles), dim3(64 * W), 0, s, arena,
+                           runs, tiles, phase);
+    else
+        hipLaunchKernelGGL((walk_mfma_kernel<L, W, 0>), dim3(n_tiles), dim3(64 * W), 0, s, arena,
+                           runs, tiles, phase);
     return hipGetLastError();
 }
 
@@ -455,12 +472,12 @@ bool mfma_shape_ok(int d_pad, int waves) {
 }
 
 int launch_walk_mfma(void *arena, const RunDev *runs_dev, const Tile *tiles, int n_tiles, int d_pad,
-                     int waves, int phase, hipStream_t s) {
+                     int waves, int nz, int phase, hipStream_t s) {
     if (!mfma_shape_ok(d_pad, waves)) return GGNS_EUNSUPPORTED;
     const int L = d_pad / (4 * waves);
     hipError_t e = hipErrorInvalidValue;
 #define GGNS_MFMA_CASE(LL, WW) \
-    if (L == LL && waves == WW) e = launch_mfma_t<LL, WW>(arena, runs_dev, tiles, n_tiles, phase, s);
+    if (L == LL && waves == WW) e = launch_mfma_t<LL, WW>(arena, runs_dev, tiles, n_tiles, nz, phase, s);
     GGNS_MFMA_CASE(8, 1) GGNS_MFMA_CASE(4, 2)                          // dp 32
     GGNS_MFMA_CASE(16, 1) GGNS_MFMA_CASE(8, 2) GGNS_MFMA_CASE(4, 4)    // dp 64
     GGNS_MFMA_CASE(8, 3)                                               // dp 96
