@@ -32,8 +32,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16mma": 2500.0}
 # duration is), each scaled by what the counter reads for a device copy of
 # known size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), with the hash of the kernel
 # sources they were taken on; reported only while the sources still hash the same
-TRAFFIC = {"shells32x10": {"bytes": (645.69 * 2.0 + 702.86) * 1024,
-                            "sources_sha1": "2a3497947888d4c7ec846b4c1314a9dc25e7cf48"}}
+TRAFFIC = {}
 
 
 def traffic_for(workload: str):
@@ -42,8 +41,7 @@ def traffic_for(workload: str):
     if t is None:
         return None
     csrc = os.path.join(ROOT, "paper_2312_03911_amd", "csrc")
-    blob = b"".join(open(os.path.join(csrc, f), "rb").read()
-                    for f in ("walk_valu.hip", "ggns_device.h"))
+    blob = b"".join(open(os.path.join(csrc, f), "rb").read() for f in t["sources"])
     return t["bytes"] if hashlib.sha1(blob).hexdigest() == t["sources_sha1"] else None
 
 
@@ -339,7 +337,9 @@ def run_environment(torch) -> dict:
     return env
 
 
-EXTRA = ("shells32x10", "corr256x10", "gmm64x10")   # configs 2, 3 and 4 in the paper's 10-run protocol
+# configs 2, 3 and 4 in the paper's 10-run protocol, and config 4 again with
+# cluster recognition (mode recovery with and without it)
+EXTRA = ("shells32x10", "corr256x10", "gmm64x10", "gmm64_clusters_x10")
 
 
 def full_run_fn(eng, poll: int, launch: str, walk_ms: list):

@@ -3,6 +3,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from paper_2312_03911_amd import exact, inputs
 
@@ -216,3 +217,21 @@ def test_cluster_moment_recursion_matches_monte_carlo(orc):
     o.evidence_update(final_sweep=True)
     assert abs(r1["log_z"] - o.st.lz) < 1e-12
     assert abs(r1["log_z2"] - o.st.lz2) < 1e-12
+
+
+@pytest.mark.parametrize("d,n,seed", [(16, 400, 9400), (32, 600, 9402)])
+def test_neighbour_cap_changes_nothing(orc, d, n, seed):
+    """Cluster finding with k capped at 32 (the GPU's neighbour lists) and with
+    k running to n_points - 1, as the cluster-finding algorithm writes it:
+    the same clusters, labels and evidence at every one of 40 iterations of a
+    mixture run, whose neighbour loop stops well below the cap."""
+    cfg = inputs.config_gmm(d=d, n_live=n, precision="fp64", cluster=1, seed=seed)
+    assert cfg.cluster_kmax == 32
+    a = orc.Oracle(cfg).init()
+    b = orc.Oracle(cfg.replace(cluster_kmax=0)).init()
+    for _ in range(40):
+        a.iterate()
+        b.iterate()
+        np.testing.assert_array_equal(a.label, b.label)
+        assert a.st.n_clusters == b.st.n_clusters and a.st.lz == b.st.lz
+    assert a.st.n_splits >= 2 and a.st.kstop_max == b.st.kstop_max < 32
