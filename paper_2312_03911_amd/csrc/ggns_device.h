@@ -109,9 +109,10 @@ __device__ __forceinline__ double u24_open(uint32_t a) {
 // ---------------------------------------------------------------------------
 // Lane-group reductions (group of G lanes, G a power of two <= 64, aligned).
 // Offsets 1, 2, 4, 8 use DPP lane swizzles (quad permutes, half-row and row
-// mirrors) so they stay in the vector ALU; 16 and 32 cross rows through the
-// LDS permute path.  The butterfly leaves the same, bitwise identical sum in
-// every lane of the group (each step adds a pair in either order).
+// mirrors), offsets 16 and 32 the row swaps of gfx950 (v_permlane16_swap,
+// v_permlane32_swap), so every level stays in the vector ALU.  The butterfly
+// leaves the same, bitwise identical sum in every lane of the group (each
+// step adds a pair in either order).
 // ---------------------------------------------------------------------------
 
 // Every pattern used here reads a lane inside the same row, so each lane gets
@@ -126,6 +127,30 @@ __device__ __forceinline__ double dpp_mov(double v) {
     lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, true);
     hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
+}
+
+// v + (v of lane l ^ 16) and v + (v of lane l ^ 32): swapping a register with
+// itself leaves the row pair's first row in the first result and its second
+// row in the second, in both rows of the pair (or both halves of the wave)
+__device__ __forceinline__ float xor16_sum(float v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor32_sum(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xor16_sum(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
 }
 
 constexpr int kDppQuad0 = 0x00;       // quad_perm [0,0,0,0]
@@ -154,10 +179,10 @@ __device__ __forceinline__ void group_sum_n(T (&v)[N], int G) {
             for (int i = 0; i < N; ++i) v[i] = v[i] + dpp_mov<kDppMirror>(v[i]);
             if (G > 16) {
 #pragma unroll
-                for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 16, 64);
+                for (int i = 0; i < N; ++i) v[i] = xor16_sum(v[i]);
                 if (G > 32) {
 #pragma unroll
-                    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 32, 64);
+                    for (int i = 0; i < N; ++i) v[i] = xor32_sum(v[i]);
                 }
             }
         }

@@ -36,12 +36,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// sum over the four lane quarters (lanes l, l^16, l^32, l^48)
-__device__ __forceinline__ float sum4(float v) {
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
-}
+// sum over the four lane quarters (lanes l, l^16, l^32, l^48), by row swaps
+__device__ __forceinline__ float sum4(float v) { return xor32_sum(xor16_sum(v)); }
 
 template <int L>
 __device__ __forceinline__ void momentum_lane(uint64_t seed, uint32_t m, uint32_t it, uint32_t sub,
