@@ -32,7 +32,11 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16mma": 2500.0}
 # duration is), each scaled by what the counter reads for a device copy of
 # known size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), with the hash of the kernel
 # sources they were taken on; reported only while the sources still hash the same
-TRAFFIC = {}
+TRAFFIC = {"shells32x10": {"bytes": (692.94 * 2.0 + 708.44 * 1.0) * 1024,
+                            "sources": ("walk_valu.h", "walk_valu.hip", "walk_valu_f1.hip",
+                                        "walk_valu_f2.hip", "walk_valu_f4.hip", "walk_valu_f8.hip",
+                                        "ggns_device.h", "ggns_common.h"),
+                            "sources_sha1": "f8b02d3ddca20edc34df1eefecb1c78c389eb8f0"}}
 
 
 def traffic_for(workload: str):
@@ -702,7 +706,7 @@ def main():
             ent = {"evals_per_s": x["value"], "ms_per_step": x["ms_per_step"],
                    "evals_per_step": x["evals_per_step"], "runs": len(x["cfgs"]),
                    "roofline": {k: x["roofline"][k] for k in
-                                ("bound", "achieved", "peak", "unit", "frac", "kernel",
+                                ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
                                  "walk_ms_per_pass", "launch_us", "frac_model",
                                  "frac_model_probed", "out_frac")},
                    "accuracy": x["accuracy"]}
