@@ -110,6 +110,119 @@ cluster_pre_kernel(void *arena, const RunDev *__restrict__ runs, int final_sweep
 // kKnnSplit partial lists into its neighbour list.
 constexpr int kKnnWaves = 4;
 
+// What one wavefront's share of the candidate scan needs.
+template <typename T>
+struct KnnScan {
+    const T *X;
+    const int32_t *members, *label;
+    int u0, u1, d, qi, qc;
+    bool qvalid;
+    T thr_d;
+    int thr_s;
+};
+
+// Candidate j (the same for every lane) into this lane's sorted list of the KN
+// best, if it belongs to the query's cluster, is not the query and comes after
+// the previous passes' last neighbour.
+template <typename T, int KN>
+__device__ __forceinline__ void knn_insert(const KnnScan<T> &sc, T dist, int j, T (&bd)[KN], int (&bs)[KN]) {
+    const bool ok = sc.qvalid && sc.label[j] == sc.qc && j != sc.qi && lex_less(sc.thr_d, sc.thr_s, dist, j) &&
+                    lex_less(dist, j, bd[KN - 1], bs[KN - 1]);
+    if (ok) {
+        bd[KN - 1] = dist;
+        bs[KN - 1] = j;
+#pragma unroll
+        for (int q = KN - 1; q > 0; --q) {
+            const bool sw = lex_less(bd[q], bs[q], bd[q - 1], bs[q - 1]);
+            const T td = bd[q];
+            const int ts = bs[q];
+            bd[q] = sw ? bd[q - 1] : bd[q];
+            bs[q] = sw ? bs[q - 1] : bs[q];
+            bd[q - 1] = sw ? td : bd[q - 1];
+            bs[q - 1] = sw ? ts : bs[q - 1];
+        }
+    }
+}
+
+// The scan over candidates [u0, u1) of the cluster-grouped member list, TILE at
+// a time; squared distances accumulated with fused multiply-adds in coordinate
+// order from zero.  D > 0: d == D, the query's D coordinates in registers and
+// each candidate row read as 16-byte vectors through scalar loads (rows start
+// on 16-byte boundaries: the arena is aligned and D is a multiple of four).
+// D == 0: any d, the query re-read in chunks for each tile.
+template <typename T, int KN, int D>
+__device__ __forceinline__ void knn_scan(const KnnScan<T> &sc, const T *xq, T (&bd)[KN], int (&bs)[KN]) {
+    constexpr int TILE = 8;
+    if constexpr (D > 0) {
+        constexpr int V = 16 / sizeof(T);   // elements per 16-byte vector
+        typedef T vec __attribute__((ext_vector_type(V)));
+        T qv[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) qv[a] = xq[a];
+        for (int ub = sc.u0; ub < sc.u1; ub += TILE) {
+            int cj[TILE];
+            T acc2[TILE];
+#pragma unroll
+            for (int t = 0; t < TILE; ++t) {
+                cj[t] = __builtin_amdgcn_readfirstlane((ub + t < sc.u1) ? sc.members[ub + t] : -1);
+                acc2[t] = (T)0;
+            }
+#pragma unroll
+            for (int t = 0; t < TILE; ++t) {
+                if (cj[t] < 0) continue;
+                const vec *xc = reinterpret_cast<const vec *>(sc.X + (int64_t)cj[t] * D);
+#pragma unroll
+                for (int v = 0; v < D / V; ++v) {
+                    const vec c = xc[v];
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const T df = qv[V * v + e] - c[e];
+                        acc2[t] = fma(df, df, acc2[t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < TILE; ++t)
+                if (cj[t] >= 0) knn_insert<T, KN>(sc, acc2[t], cj[t], bd, bs);
+        }
+    } else {
+        constexpr int CHUNK = (sizeof(T) == 8) ? 16 : 32;
+        const int d = sc.d;
+        for (int ub = sc.u0; ub < sc.u1; ub += TILE) {
+            int cj[TILE];
+            T acc2[TILE];
+#pragma unroll
+            for (int t = 0; t < TILE; ++t) {
+                // the same candidate for every lane: make that explicit so that its
+                // coordinates come through scalar loads
+                cj[t] = __builtin_amdgcn_readfirstlane((ub + t < sc.u1) ? sc.members[ub + t] : -1);
+                acc2[t] = (T)0;
+            }
+            for (int c0 = 0; c0 < d; c0 += CHUNK) {
+                const int cn = (d - c0 < CHUNK) ? d - c0 : CHUNK;
+                T qv[CHUNK];
+#pragma unroll
+                for (int a = 0; a < CHUNK; ++a) qv[a] = (a < cn) ? xq[c0 + a] : (T)0;
+#pragma unroll
+                for (int t = 0; t < TILE; ++t) {
+                    if (cj[t] < 0) continue;
+                    const T *xc = sc.X + (int64_t)cj[t] * d + c0;
+#pragma unroll
+                    for (int a = 0; a < CHUNK; ++a) {
+                        if (a < cn) {
+                            const T e = qv[a] - xc[a];
+                            acc2[t] = fma(e, e, acc2[t]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < TILE; ++t)
+                if (cj[t] >= 0) knn_insert<T, KN>(sc, acc2[t], cj[t], bd, bs);
+        }
+    }
+}
+
 template <typename T, int KN>
 __global__ void __launch_bounds__(64 * kKnnWaves)
 knn_part_kernel(void *arena, const RunDev *__restrict__ runs, int pass) {
@@ -157,56 +270,19 @@ knn_part_kernel(void *arena, const RunDev *__restrict__ runs, int pass) {
     int bs[KN];
 #pragma unroll
     for (int q = 0; q < KN; ++q) { bd[q] = (T)INFINITY; bs[q] = 0x7FFFFFFF; }
-    constexpr int TILE = 8, CHUNK = (sizeof(T) == 8) ? 16 : 32;
-    for (int ub = u0; ub < u1; ub += TILE) {
-        int cj[TILE];
-        T acc2[TILE];
-#pragma unroll
-        for (int t = 0; t < TILE; ++t) {
-            // the same candidate for every lane: make that explicit so that its
-            // coordinates come through scalar loads
-            cj[t] = __builtin_amdgcn_readfirstlane((ub + t < u1) ? members[ub + t] : -1);
-            acc2[t] = (T)0;
-        }
-        for (int c0 = 0; c0 < d; c0 += CHUNK) {
-            const int cn = (d - c0 < CHUNK) ? d - c0 : CHUNK;
-            T qv[CHUNK];
-#pragma unroll
-            for (int a = 0; a < CHUNK; ++a) qv[a] = (a < cn) ? xq[c0 + a] : (T)0;
-#pragma unroll
-            for (int t = 0; t < TILE; ++t) {
-                if (cj[t] < 0) continue;
-                const T *xc = X + (int64_t)cj[t] * d + c0;
-#pragma unroll
-                for (int a = 0; a < CHUNK; ++a) {
-                    if (a < cn) {
-                        const T e = qv[a] - xc[a];
-                        acc2[t] = fma(e, e, acc2[t]);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < TILE; ++t) {
-            const int j = cj[t];
-            if (j < 0) continue;
-            const bool ok = qvalid && label[j] == qc && j != qi && lex_less(thr_d, thr_s, acc2[t], j) &&
-                            lex_less(acc2[t], j, bd[KN - 1], bs[KN - 1]);
-            if (ok) {
-                bd[KN - 1] = acc2[t];
-                bs[KN - 1] = j;
-#pragma unroll
-                for (int q = KN - 1; q > 0; --q) {
-                    const bool sw = lex_less(bd[q], bs[q], bd[q - 1], bs[q - 1]);
-                    const T td = bd[q];
-                    const int ts = bs[q];
-                    bd[q] = sw ? bd[q - 1] : bd[q];
-                    bs[q] = sw ? bs[q - 1] : bs[q];
-                    bd[q - 1] = sw ? td : bd[q - 1];
-                    bs[q - 1] = sw ? ts : bs[q - 1];
-                }
-            }
-        }
+    // dimensions 8, 16, 32 and 64 (FP64: up to 32): the query in registers for
+    // the whole scan and each candidate row in 16-byte scalar loads; any other d
+    // in chunks of the query
+    const KnnScan<T> sc{X, members, label, u0, u1, d, qi, qc, qvalid, thr_d, thr_s};
+    switch (d) {
+        case 8: knn_scan<T, KN, 8>(sc, xq, bd, bs); break;
+        case 16: knn_scan<T, KN, 16>(sc, xq, bd, bs); break;
+        case 32: knn_scan<T, KN, 32>(sc, xq, bd, bs); break;
+        case 64:
+            if constexpr (sizeof(T) == 4) knn_scan<T, KN, 64>(sc, xq, bd, bs);
+            else knn_scan<T, KN, 0>(sc, xq, bd, bs);
+            break;
+        default: knn_scan<T, KN, 0>(sc, xq, bd, bs); break;
     }
 #pragma unroll
     for (int q = 0; q < KN; ++q) {
