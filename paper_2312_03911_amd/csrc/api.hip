@@ -209,7 +209,7 @@ struct Class {
     int n_tiles;
     size_t lds;
     int waves = 0;       // matrix-core classes: wavefronts per group of 16 walkers
-    int gf = 0;          // vector FP32 walk: lanes per walker (4, 8 or 16) shared by the class, else 0
+    int gf = 0;          // vector FP32 walk: lanes per walker (4, 8, 16 or 32) shared by the class, else 0
     bool any_batch = false;   // some run of the class walks the batch-minimum loop
     int nz = 0;               // matrix-core classes: 1 = one noise normal per walker (noise_mode 1)
 };
@@ -250,8 +250,8 @@ namespace {
 // Walk tiles: one walker per lane group, kWalkThreads / G groups per block.
 // Init tiles: the same shape over the n_live prior draws.
 void build_classes(ggns_ctx *c) {
-    // (prec, C, kind, fixed group size) -> runs; FP32 runs with groups of 4, 8 or
-    // 16 lanes get a kernel with that size fixed at compile time
+    // (prec, C, kind, fixed group size) -> runs; FP32 runs with groups of 4, 8, 16
+    // or 32 lanes get a kernel with that size fixed at compile time
     std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     std::vector<int> mfma_runs;
     for (int r = 0; r < (int)c->plan.runs.size(); ++r) {
@@ -260,7 +260,7 @@ void build_classes(ggns_ctx *c) {
             mfma_runs.push_back(r);
         else
             groups[std::make_tuple(R.prec, R.C, R.var,
-                                   (R.prec == GGNS_FP32 && (R.G == 4 || R.G == 8 || R.G == 16)) ? R.G : 0)]
+                                   (R.prec == GGNS_FP32 && (R.G == 4 || R.G == 8 || R.G == 16 || R.G == 32)) ? R.G : 0)]
                 .push_back(r);
         c->max_kd = std::max<int>(c->max_kd, R.n_kill * R.d);
     }

@@ -99,7 +99,7 @@ __device__ __forceinline__ void momentum_draw(uint64_t seed, uint32_t m, uint32_
 
 }  // namespace
 
-// GF: the group size when fixed at compile time (4, 8 or 16), else 0 (read from the run).
+// GF: the group size when fixed at compile time (4, 8, 16 or 32), else 0 (read from the run).
 // A fixed size folds the group-size branches of the reductions and the
 // broadcast away, so the step's common path has no branch taken.
 template <typename T, int C, int VAR, int GF>
@@ -476,8 +476,8 @@ walk_valu_kernel(void *arena, const RunDev *__restrict__ runs, const Tile *__res
     }
 }
 
-// FP32 classes whose runs all have groups of 4, 8 or 16 lanes take the kernel
-// with the group size fixed; every other class reads it from the run.
+// FP32 classes whose runs all have groups of 4, 8, 16 or 32 lanes take the
+// kernel with the group size fixed; every other class reads it from the run.
 template <typename T, int C, int VAR>
 static void launch_gf(int gf, int n_tiles, size_t lds, hipStream_t s, void *arena,
                       const RunDev *runs, const Tile *tiles, int phase) {
@@ -489,6 +489,8 @@ static void launch_gf(int gf, int n_tiles, size_t lds, hipStream_t s, void *aren
             hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 8>), grid, block, lds, s, arena, runs, tiles, phase);
         else if (gf == 16)
             hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 16>), grid, block, lds, s, arena, runs, tiles, phase);
+        else if (gf == 32)
+            hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 32>), grid, block, lds, s, arena, runs, tiles, phase);
         else
             hipLaunchKernelGGL((walk_valu_kernel<T, C, VAR, 0>), grid, block, lds, s, arena, runs, tiles, phase);
     } else {
