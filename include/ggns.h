@@ -269,6 +269,17 @@ int ggns_hss_walk(ggns_ctx *ctx, void *stream);
  * iteration counter. */
 int ggns_replace_dead(ggns_ctx *ctx, void *stream);
 
+/* n_iter iterations of the nested sampling loop (Algorithm GGNS: the evidence
+ * update, the kill of the n_kill lowest points, the walk and the replacement),
+ * each the same work per run as ggns_evidence_update(final_sweep = 0),
+ * ggns_hss_walk and ggns_replace_dead called in that order, with bitwise the
+ * same results.  Each kernel class walks its own chain of iterations over its
+ * own runs, on the side streams ggns_hss_walk uses: a class does not wait for
+ * the slowest class at every iteration, only at the end of the call.  The call
+ * is ordered on `stream` like a single launch and can be graph-captured.
+ * n_iter < 0 is GGNS_EINVAL; 0 does nothing. */
+int ggns_iterate(ggns_ctx *ctx, int32_t n_iter, void *stream);
+
 /* log L (and grad log L if grad_dev is not NULL) of run `run` at n points
  * x_dev [n][d] (run precision); logl_dev [n] double, grad_dev [n][d] run
  * precision.  The likelihood the walk uses, callable on its own. */

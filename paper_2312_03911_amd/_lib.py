@@ -16,7 +16,7 @@ RUN_ACTIVE, RUN_DONE, RUN_MAXITER, RUN_NONFINITE = 0, 1, 2, 3
 
 # every symbol the header declares
 SYMBOLS = ("ggns_arena_bytes", "ggns_init", "ggns_attach", "ggns_evidence_update", "ggns_finalize",
-           "ggns_hss_walk", "ggns_replace_dead", "ggns_loglike_grad", "ggns_loglike_vjp",
+           "ggns_hss_walk", "ggns_replace_dead", "ggns_iterate", "ggns_loglike_grad", "ggns_loglike_vjp",
            "ggns_run_layout", "ggns_read_stats", "ggns_read_stats_async", "ggns_write_vars",
            "ggns_set_trace", "ggns_tile_shape", "ggns_plain_workspace_bytes", "ggns_hss_walk_plain",
            "ggns_hss_walk_plain_static",
@@ -93,6 +93,7 @@ def load() -> C.CDLL:
         L.ggns_hss_walk.argtypes = [vp, vp]
         L.ggns_finalize.argtypes = [vp, vp]
         L.ggns_replace_dead.argtypes = [vp, vp]
+        L.ggns_iterate.argtypes = [vp, i32, vp]
         L.ggns_loglike_grad.argtypes = [vp, i32, vp, i64, vp, vp, vp]
         L.ggns_loglike_vjp.argtypes = [vp, i32, vp, i64, vp, vp, vp]
         L.ggns_run_layout.argtypes = [vp, i32, C.POINTER(ggns_layout)]
@@ -127,6 +128,7 @@ def load() -> C.CDLL:
         L.ggns_status_string.argtypes = [C.c_int]
         L.ggns_status_string.restype = C.c_char_p
         for name in ("ggns_evidence_update", "ggns_finalize", "ggns_hss_walk", "ggns_replace_dead",
+                     "ggns_iterate",
                      "ggns_loglike_grad", "ggns_loglike_vjp", "ggns_run_layout",
                      "ggns_read_stats", "ggns_read_stats_async", "ggns_write_vars",
                      "ggns_set_trace", "ggns_tile_shape", "ggns_hss_walk_plain"):

@@ -94,7 +94,7 @@ int default_c(int d) {
 
 struct Plan {
     std::vector<RunDev> runs;
-    int64_t off_runs = 0, off_tiles = 0, n_tile_slots = 0, off_mirror = 0, total = 0;
+    int64_t off_runs = 0, off_class_runs = 0, off_tiles = 0, n_tile_slots = 0, off_mirror = 0, total = 0;
 };
 
 // Lay out the arena: run table, tiles, then each run's arrays.
@@ -103,6 +103,10 @@ int make_plan(const ggns_run_desc *descs, int n_runs, Plan &P) {
     P.runs.resize(n_runs);
     int64_t off = 0;
     P.off_runs = off;
+    off = align_up(off + (int64_t)sizeof(RunDev) * n_runs);
+    // the same descriptors grouped by walk class (each class's runs contiguous),
+    // for the per-class iteration chains of ggns_iterate
+    P.off_class_runs = off;
     off = align_up(off + (int64_t)sizeof(RunDev) * n_runs);
     // tiles: walk and init tiles of every run (upper bound: one per walker / point)
     int64_t ntiles = 0;
@@ -212,6 +216,11 @@ struct Class {
     int gf = 0;          // vector FP32 walk: lanes per walker (4, 8, 16 or 32) shared by the class, else 0
     bool any_batch = false;   // some run of the class walks the batch-minimum loop
     int nz = 0;               // matrix-core classes: 1 = one noise normal per walker (noise_mode 1)
+    // the class's runs: their descriptors start at class_off in the class-ordered
+    // run table; the largest n_kill * d and n_live, and their cluster and precision mix
+    std::vector<int> runs;
+    int class_off = 0, max_kd = 1, max_live = 0;
+    bool any_cluster = false, any_fp64 = false, any_fp32 = false;
 };
 
 }  // namespace
@@ -241,7 +250,13 @@ struct ggns_ctx {
         if (fork) (void)hipEventDestroy(fork);
     }
 
+    // the run descriptors grouped by walk class (host copy of the device table)
+    // and each run's position in it
+    std::vector<RunDev> class_table;
+    std::vector<int> class_pos;
+
     RunDev *runs_dev() const { return at<RunDev>(arena, plan.off_runs); }
+    RunDev *class_runs_dev() const { return at<RunDev>(arena, plan.off_class_runs); }
     Tile *tiles_dev() const { return at<Tile>(arena, plan.off_tiles); }
 };
 
@@ -287,6 +302,7 @@ void build_classes(ggns_ctx *c) {
         }
         w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
         w.lds = lds;
+        w.runs = kv.second;
         for (int r : kv.second) w.any_batch = w.any_batch || c->plan.runs[r].walk_mode == 1;
         // a mixture class with more wavefronts than the device has SIMDs is
         // bound by occupancy: its kernel reads the staged block every step
@@ -325,6 +341,7 @@ void build_classes(ggns_ctx *c) {
                 w.any_batch = w.any_batch || c->plan.runs[r].walk_mode == 1;
             }
             w.n_tiles = (int)(c->tiles_host.size() - w.tile_off);
+            w.runs = kv.second;
             c->walk_classes.push_back(w);
         }
         // prior draws of MMA runs on the FP32 vector path (one class per C)
@@ -368,6 +385,25 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
             c->n_simd = 4 * cus;   // four SIMDs per compute unit
     }
     build_classes(c);
+    // every run belongs to exactly one walk class: lay the descriptors out class
+    // by class and note what each class's chain of launches needs
+    std::vector<RunDev> &class_table = c->class_table;
+    c->class_pos.assign(n_runs, -1);
+    for (Class &w : c->walk_classes) {
+        w.class_off = (int)class_table.size();
+        for (int r : w.runs) {
+            const RunDev &R = c->plan.runs[r];
+            c->class_pos[r] = (int)class_table.size();
+            class_table.push_back(R);
+            w.max_kd = std::max<int>(w.max_kd, R.n_kill * R.d);
+            if (R.cluster_mode) {
+                w.any_cluster = true;
+                w.max_live = std::max(w.max_live, R.n_live);
+                if (R.prec == GGNS_FP64) w.any_fp64 = true; else w.any_fp32 = true;
+            }
+        }
+    }
+    if ((int)class_table.size() != n_runs) { delete c; return GGNS_EINVAL; }
     for (const RunDev &R : c->plan.runs) {
         if (R.cluster_mode) {
             c->any_cluster = true;
@@ -392,6 +428,8 @@ int create(ggns_ctx **out, const ggns_run_desc *runs, int32_t n_runs, const doub
     // likelihood use the FP32 vector path
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(c->runs_dev(), c->plan.runs.data(), sizeof(RunDev) * n_runs,
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->class_runs_dev(), class_table.data(), sizeof(RunDev) * n_runs,
                        hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(c->tiles_dev(), c->tiles_host.data(), sizeof(Tile) * c->tiles_host.size(),
                        hipMemcpyHostToDevice, s) != hipSuccess) {
@@ -421,6 +459,46 @@ int64_t walker_state_bytes(int d_pad, int elem_bytes) {
     return (int64_t)(3 * elem_bytes + 4) * d_pad + 80;
 }
 }  // namespace ggns
+
+namespace {
+// One class's walk: a class with batch-minimum runs walks twice, the first walk
+// fixing each run's window and the second finishing every run of the class.
+int walk_class(const ggns_ctx *ctx, const Class &w, hipStream_t st) {
+    auto phase = [&](int ph) {
+        if (w.mfma)
+            return launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
+                                    w.n_tiles, w.C, w.waves, w.nz, ph, st);
+        return launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
+                                 w.n_tiles, w.prec, w.C, w.kind, w.gf, w.lds, ph, st);
+    };
+    if (w.any_batch) {
+        const int rc = phase(1);
+        if (rc != GGNS_OK) return rc;
+    }
+    return phase(2);
+}
+
+// Runs `body(class, stream)` for every walk class: the first on the caller's
+// stream, the others on side streams forked from it and joined back into it.
+// Classes own disjoint runs, so their work is independent.
+template <typename F>
+int fork_classes(ggns_ctx *ctx, hipStream_t s, F body) {
+    const size_t n = ctx->walk_classes.size();
+    if (n == 0) return GGNS_OK;
+    if (n == 1) return body(ctx->walk_classes[0], s);
+    if (hipEventRecord(ctx->fork, s) != hipSuccess) return GGNS_EHIP;
+    for (size_t i = 1; i < n; ++i) {
+        if (hipStreamWaitEvent(ctx->side[i - 1], ctx->fork, 0) != hipSuccess) return GGNS_EHIP;
+        const int rc = body(ctx->walk_classes[i], ctx->side[i - 1]);
+        if (rc != GGNS_OK) return rc;
+        if (hipEventRecord(ctx->join[i - 1], ctx->side[i - 1]) != hipSuccess) return GGNS_EHIP;
+    }
+    const int rc = body(ctx->walk_classes[0], s);
+    for (size_t i = 1; i < n; ++i)
+        if (hipStreamWaitEvent(s, ctx->join[i - 1], 0) != hipSuccess) return GGNS_EHIP;
+    return rc;
+}
+}  // namespace
 
 extern "C" {
 
@@ -464,38 +542,32 @@ int ggns_finalize(ggns_ctx *ctx, void *stream) {
 
 int ggns_hss_walk(ggns_ctx *ctx, void *stream) {
     if (ctx == nullptr) return GGNS_ESTATE;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const size_t n = ctx->walk_classes.size();
-    auto launch_phase = [&](const Class &w, int phase, hipStream_t st) {
-        if (w.mfma)
-            return launch_walk_mfma(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                    w.n_tiles, w.C, w.waves, w.nz, phase, st);
-        return launch_walk_class(ctx->arena, ctx->runs_dev(), ctx->tiles_dev() + w.tile_off,
-                                 w.n_tiles, w.prec, w.C, w.kind, w.gf, w.lds, phase, st);
-    };
-    // a class with batch-minimum runs walks twice: the first walk fixes each
-    // run's window, the second finishes every run of the class
-    auto launch = [&](const Class &w, hipStream_t st) {
-        if (w.any_batch) {
-            const int rc = launch_phase(w, 1, st);
+    return fork_classes(ctx, reinterpret_cast<hipStream_t>(stream),
+                        [&](const Class &w, hipStream_t st) { return walk_class(ctx, w, st); });
+}
+
+int ggns_iterate(ggns_ctx *ctx, int32_t n_iter, void *stream) {
+    if (ctx == nullptr) return GGNS_ESTATE;
+    if (n_iter < 0) return GGNS_EINVAL;
+    if (n_iter == 0) return GGNS_OK;
+    // each class runs its own chain of iterations over its own runs; the work of
+    // one run is that of the one-call-per-step sequence, launch for launch
+    return fork_classes(ctx, reinterpret_cast<hipStream_t>(stream), [&](const Class &w, hipStream_t st) -> int {
+        RunDev *cr = ctx->class_runs_dev() + w.class_off;
+        const int nr = (int)w.runs.size();
+        for (int it = 0; it < n_iter; ++it) {
+            if (w.any_cluster) {
+                const int rc = launch_clusters(ctx->arena, cr, nr, w.max_live, 0, w.any_fp64,
+                                               w.any_fp32, st);
+                if (rc != GGNS_OK) return rc;
+            }
+            launch_evidence(ctx->arena, cr, nr, 0, w.any_cluster ? 1 : 0, st);
+            const int rc = walk_class(ctx, w, st);
             if (rc != GGNS_OK) return rc;
+            launch_replace(ctx->arena, cr, nr, w.max_kd, st);
         }
-        return launch_phase(w, 2, st);
-    };
-    if (n == 0) return GGNS_OK;
-    if (n == 1) return launch(ctx->walk_classes[0], s);
-    // classes are independent (disjoint runs): fork, run them concurrently, join
-    if (hipEventRecord(ctx->fork, s) != hipSuccess) return GGNS_EHIP;
-    for (size_t i = 1; i < n; ++i) {
-        if (hipStreamWaitEvent(ctx->side[i - 1], ctx->fork, 0) != hipSuccess) return GGNS_EHIP;
-        const int rc = launch(ctx->walk_classes[i], ctx->side[i - 1]);
-        if (rc != GGNS_OK) return rc;
-        if (hipEventRecord(ctx->join[i - 1], ctx->side[i - 1]) != hipSuccess) return GGNS_EHIP;
-    }
-    const int rc = launch(ctx->walk_classes[0], s);
-    for (size_t i = 1; i < n; ++i)
-        if (hipStreamWaitEvent(s, ctx->join[i - 1], 0) != hipSuccess) return GGNS_EHIP;
-    return rc;
+        return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
+    });
 }
 
 int64_t ggns_plain_workspace_bytes(const ggns_ctx *ctx) {
@@ -662,6 +734,19 @@ int ggns_write_vars(ggns_ctx *ctx, int32_t run, const ggns_run_vars *v, void *st
     return hipGetLastError() == hipSuccess ? GGNS_OK : GGNS_EHIP;
 }
 
+namespace {
+// Both device copies of one run's descriptor after a host-side change.
+int upload_run(ggns_ctx *ctx, int run) {
+    const RunDev &R = ctx->plan.runs[run];
+    ctx->class_table[ctx->class_pos[run]] = R;
+    if (hipMemcpy(ctx->runs_dev() + run, &R, sizeof(RunDev), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->class_runs_dev() + ctx->class_pos[run], &R, sizeof(RunDev),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return GGNS_EHIP;
+    return GGNS_OK;
+}
+}  // namespace
+
 int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl,
                    int32_t *trace_out, int32_t trace_steps) {
     if (ctx == nullptr) return GGNS_ESTATE;
@@ -672,9 +757,7 @@ int ggns_set_trace(ggns_ctx *ctx, int32_t run, void *trace_x, double *trace_logl
     R.trace_logl = trace_x ? trace_logl : nullptr;
     R.trace_out = trace_x ? trace_out : nullptr;
     R.trace_steps = trace_x ? trace_steps : 0;
-    if (hipMemcpy(ctx->runs_dev() + run, &R, sizeof(RunDev), hipMemcpyHostToDevice) != hipSuccess)
-        return GGNS_EHIP;
-    return GGNS_OK;
+    return upload_run(ctx, run);
 }
 
 int ggns_set_dead_x(ggns_ctx *ctx, int32_t run, void *dead_x_dev, int64_t capacity_rows) {
@@ -683,9 +766,7 @@ int ggns_set_dead_x(ggns_ctx *ctx, int32_t run, void *dead_x_dev, int64_t capaci
     RunDev &R = ctx->plan.runs[run];
     R.dead_x = (capacity_rows > 0) ? dead_x_dev : nullptr;
     R.dead_x_cap = (dead_x_dev != nullptr) ? capacity_rows : 0;
-    if (hipMemcpy(ctx->runs_dev() + run, &R, sizeof(RunDev), hipMemcpyHostToDevice) != hipSuccess)
-        return GGNS_EHIP;
-    return GGNS_OK;
+    return upload_run(ctx, run);
 }
 
 int ggns_tile_shape(const ggns_ctx *ctx, int32_t run, int32_t *coords_per_lane,

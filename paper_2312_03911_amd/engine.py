@@ -69,8 +69,9 @@ class Engine:
     """Many independent nested-sampling runs advanced together.
 
     One iteration = ggns_evidence_update -> ggns_hss_walk -> ggns_replace_dead
-    for every active run; `run()` repeats it (optionally as a captured HIP
-    graph of `graph_iters` iterations) until every run has stopped.
+    for every active run; a block of iterations goes through ggns_iterate,
+    which gives each kernel class its own chain of them.  `run()` repeats
+    blocks (optionally as a captured HIP graph) until every run has stopped.
     """
 
     def __init__(self, configs: Sequence[RunConfig], device: str = "cuda",
@@ -183,7 +184,13 @@ class Engine:
         _lib.check(self.L.ggns_hss_walk_plain_static(self.ctx, self._stream()),
                    "ggns_hss_walk_plain_static")
 
-    def iterate(self, n: int = 1, plain: bool = False):
+    def iterate(self, n: int = 1, plain: bool = False, per_call: bool = False):
+        """n iterations.  The fused path goes through ggns_iterate (each kernel
+        class on its own chain of iterations); `per_call` issues the same work
+        as one evidence / walk / replace call per iteration instead."""
+        if not plain and not per_call:
+            _lib.check(self.L.ggns_iterate(self.ctx, int(n), self._stream()), "ggns_iterate")
+            return
         for _ in range(n):
             self.evidence_update()
             if plain:

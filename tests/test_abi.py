@@ -73,6 +73,7 @@ def test_null_context_rejected():
     assert L.ggns_hss_walk(None, None) == _lib.GGNS_ESTATE
     assert L.ggns_evidence_update(None, 0, None) == _lib.GGNS_ESTATE
     assert L.ggns_replace_dead(None, None) == _lib.GGNS_ESTATE
+    assert L.ggns_iterate(None, 1, None) == _lib.GGNS_ESTATE
     assert L.ggns_status_string(_lib.GGNS_EINVAL) == b"invalid argument"
     assert L.ggns_hss_walk_plain_static(None, None) == _lib.GGNS_ESTATE
     assert b"scratch" in L.ggns_status_string(_lib.GGNS_ESCRATCH)

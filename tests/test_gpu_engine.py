@@ -53,6 +53,47 @@ def test_run_inside_batch_equals_run_alone(torch):
     both.close()
 
 
+def _class_mix():
+    """Runs spread over several kernel classes: vector FP32 and FP64, the
+    matrix-core walk, batch-minimum walks and a cluster-mode run."""
+    return _small_mix() + [
+        inputs.config_corr_gauss(d=64, n_live=300, seed=35, n_steps_max=200),
+        inputs.config_gmm(d=8, n_live=400, n_comp=4, seed=36, param_seed=4, cluster=1),
+        inputs.config_torus(d=8, n_live=200, seed=37)]
+
+
+def test_iterate_chains_equal_per_call_iterations(torch):
+    """ggns_iterate (one chain of iterations per kernel class) gives bitwise the
+    runs of one evidence / walk / replace call per iteration, eagerly and as a
+    replayed graph, across blocks in which some runs stop."""
+    cfgs = _class_mix()
+    calls, chains, graph = _engine(cfgs), _engine(cfgs), _engine(cfgs)
+    for block in range(6):
+        calls.iterate(4, per_call=True)
+        chains.iterate(4)
+        graph.step_block(4, use_graph=True)
+        torch.cuda.synchronize()
+        s_c, s_i, s_g = calls.stats(), chains.stats(), graph.stats()
+        for r in range(len(cfgs)):
+            for e in (chains, graph):
+                np.testing.assert_array_equal(_np(calls.live_x(r)), _np(e.live_x(r)))
+                np.testing.assert_array_equal(_np(calls.live_logl(r)), _np(e.live_logl(r)))
+            assert s_c[r] == s_i[r] == s_g[r], (block, r)
+        for r, c in enumerate(cfgs):
+            if c.cluster:
+                np.testing.assert_array_equal(_np(calls.labels(r)), _np(chains.labels(r)))
+    for e in (calls, chains, graph):
+        e.close()
+
+
+def test_iterate_rejects_negative_counts(torch):
+    from paper_2312_03911_amd import _lib
+    e = _engine(_small_mix())
+    assert e.L.ggns_iterate(e.ctx, -1, e._stream()) == _lib.GGNS_EINVAL
+    assert e.L.ggns_iterate(e.ctx, 0, e._stream()) == _lib.GGNS_OK
+    e.close()
+
+
 def test_same_seed_is_bitwise_reproducible(torch):
     cfgs = _small_mix()
     a, b = _engine(cfgs), _engine(cfgs)
