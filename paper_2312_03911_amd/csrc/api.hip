@@ -304,14 +304,15 @@ void build_classes(ggns_ctx *c) {
         w.lds = lds;
         w.runs = kv.second;
         for (int r : kv.second) w.any_batch = w.any_batch || c->plan.runs[r].walk_mode == 1;
-        // a mixture class with more wavefronts than the device has SIMDs is
-        // bound by occupancy: its kernel reads the staged block every step
-        // instead of holding it in registers
+        // the mixture kernel that holds its means and precisions in registers
+        // runs two wavefronts per SIMD; a class with more wavefronts than that
+        // fills the device with is bound by occupancy, and its kernel reads
+        // the staged block every step instead (three wavefronts per SIMD)
         if (w.kind == VAR_GMM) {
             int64_t waves = 0;
             for (int r : kv.second)
                 waves += ((int64_t)c->plan.runs[r].n_kill * c->plan.runs[r].G + 63) / 64;
-            if (waves > c->n_simd) w.kind = VAR_GMM_STAGED;
+            if (waves > 2 * (int64_t)c->n_simd) w.kind = VAR_GMM_STAGED;
         }
         c->walk_classes.push_back(w);
     }

@@ -293,13 +293,14 @@ def test_batch64_sampled_runs_match_oracle(torch, orc):
 
 
 def test_staged_mixture_walk_matches_oracle(torch, orc):
-    """A mixture walk class with more wavefronts than the device has SIMDs
-    (three d = 64 runs of 4000 live points: 3 x 2000 walkers x 16 lanes = 1500
-    wavefronts against 1024 SIMDs) runs the kernel that reads the parameter
-    block from LDS at every step; two of its runs follow the oracle step by step."""
-    cfgs = inputs.replicate(inputs.config_gmm(seed=53), 3, base_seed=53)
+    """A mixture walk class with more wavefronts than the register kernel fills
+    the device with (five d = 64 runs of 4000 live points: 5 x 2000 walkers x 16
+    lanes = 2500 wavefronts against two per SIMD on 1024 SIMDs) runs the kernel
+    that reads the parameter block from LDS at every step; two of its runs
+    follow the oracle step by step."""
+    cfgs = inputs.replicate(inputs.config_gmm(seed=53), 5, base_seed=53)
     eng = _engine(cfgs)
-    checks = {r: _prepare_trace(torch, eng, orc, r, 10) for r in (0, 2)}
+    checks = {r: _prepare_trace(torch, eng, orc, r, 10) for r in (0, 4)}
     eng.evidence_update()
     for o, _ in checks.values():
         o.evidence_update()
