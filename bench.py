@@ -628,7 +628,22 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device a few times (the reference kernel "
                          "that scales HBM byte counters) and exit")
+    ap.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",
+                    help="only gather MIB MiB of random 128-byte rows into a dense array a few times "
+                         "(the access pattern of the walk's start gathers, to read HBM byte counters "
+                         "against) and exit")
     args = ap.parse_args()
+    if args.gather_calibration:
+        import torch
+        rows = (args.gather_calibration << 20) // 128
+        src = torch.ones(rows, 32, dtype=torch.float32, device="cuda:0")
+        idx = torch.randperm(rows, device="cuda:0")
+        for _ in range(3):
+            dst = torch.index_select(src, 0, idx)
+        torch.cuda.synchronize()
+        print(json.dumps({"gather_rows": rows, "row_bytes": 128, "index_bytes": 8 * rows,
+                          "launches": 3, "checksum": float(dst.sum().item())}), flush=True)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
