@@ -552,7 +552,7 @@ int ggns_iterate(ggns_ctx *ctx, int32_t n_iter, void *stream) {
     if (n_iter < 0) return GGNS_EINVAL;
     if (n_iter == 0) return GGNS_OK;
     // each class runs its own chain of iterations over its own runs; the work of
-    // one run is that of the one-call-per-step sequence, launch for launch
+    // one run is that of the one-call-per-iteration sequence, launch for launch
     return fork_classes(ctx, reinterpret_cast<hipStream_t>(stream), [&](const Class &w, hipStream_t st) -> int {
         RunDev *cr = ctx->class_runs_dev() + w.class_off;
         const int nr = (int)w.runs.size();
